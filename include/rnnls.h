@@ -1,0 +1,198 @@
+/*
+ * rnnls.h -- C ABI of librnnls.so: RandomizedNNLS on AMD Instinct MI355X (gfx950).
+ *
+ * Method: C. Boutsidis and P. Drineas, "Random Projections for the Nonnegative
+ * Least-Squares Problem".  Given A (n x d, n >> d) and b (n), Algorithm 1
+ * (RandomizedNNLS) flips the sign of every row of [A | b] with a random +-1
+ * diagonal D (step 4), applies the n x n Hadamard-Walsh matrix H_n of Section 2
+ * (Sylvester recursion, normalised by 1/sqrt(n), rows zero-padded to the next
+ * power of two n'), keeps each row with probability r/n' rescaled by
+ * sqrt(n'/r) (steps 2-3), and solves the small nonnegative least-squares
+ * problem of Definition 1 on the kept rows exactly (step 5).  The exact solver
+ * here is Lawson-Hanson's active-set method (the paper's lsqnonneg), run in
+ * the Gram form Q = A^T A, q = A^T b that Section 3.4 describes.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are column-major (LAPACK convention): column k of A starts at
+ *    A + k*lda and holds n contiguous floats; lda >= n.
+ *  - Every data pointer is DEVICE memory owned by the caller; the library never
+ *    allocates, frees or keeps any of it.  Scratch memory comes from the
+ *    caller's workspace `ws` of `ws_bytes` bytes (size it with
+ *    rnnls_workspace_bytes; 256-byte alignment).  Results are undefined if
+ *    inputs, outputs and the workspace overlap.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *    stream) and is asynchronous: the call returns once the kernels are
+ *    launched.  Calls sharing a workspace must be ordered on one stream.
+ *  - Row indices are 0-based (the paper's row i is row i-1 here).  H_n' is in
+ *    natural (Sylvester) order: H[i][j] = (-1)^popcount(i & j).
+ *  - Return value: RNNLS_OK, or -(1-based position of the first invalid
+ *    argument) (LAPACK "info" style), or one of the RNNLS_E_* codes.  Argument
+ *    checks happen on the host before anything is launched.  Outcomes that are
+ *    only known on the device (solver status) are written to device memory.
+ *
+ * Random streams (the paper fixes only the probabilities; this definition is
+ * the library's):
+ *  mix64(z)      SplitMix64 output function (Steele, Lea & Flood 2014; shifts
+ *                30, 27, 31; multipliers 0xBF58476D1CE4E5B9, 0x94D049BB133111EB)
+ *  key(seed, s)  mix64(seed ^ (s * 0x9E3779B97F4A7C15))        (mod 2^64)
+ *  h(seed, s, i) mix64(key(seed, s) + i)
+ *  D_jj = -1 iff bit 63 of h(seed, 1, j) is set                (0 <= j < n')
+ *  EXACT rows:     {pi(k) : 0 <= k < r} ascending; pi is the bijection of
+ *                  [0, 2^m), m = log2 n', given by 4 rounds t = 0..3 of
+ *                  x ^= ka_t; x = x * (kb_t | 1) mod 2^m; x ^= x >> ceil(m/2)
+ *                  with ka_t = h(seed,3,2t) mod 2^m, kb_t = h(seed,3,2t+1) mod 2^m.
+ *  BERNOULLI rows: {i : h(seed, 2, i) < r * 2^(64-m)} ascending (each row kept
+ *                  with probability exactly r/n', Algorithm 1 step 2 as written).
+ *  Both modes scale kept rows by sqrt(n'/r) * (1/sqrt(n')) = 1/sqrt(r).
+ */
+#ifndef RNNLS_H
+#define RNNLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define RNNLS_OK 0
+#define RNNLS_E_HIP (-100)          /* a HIP runtime call failed             */
+#define RNNLS_E_WORKSPACE (-101)    /* ws NULL, misaligned or too small       */
+#define RNNLS_E_UNSUPPORTED (-102)  /* valid but unsupported (see limits)     */
+
+/* ---- per-problem solver status (device int32) --------------------------- */
+#define RNNLS_SOLVE_OK 0            /* converged, KKT certificate holds       */
+#define RNNLS_SOLVE_MAX_ITER 1      /* outer-iteration cap hit; x feasible    */
+#define RNNLS_SOLVE_KKT_FAIL 2      /* finished but the KKT check failed      */
+#define RNNLS_SOLVE_NO_ROWS 3       /* Bernoulli sample kept no row           */
+#define RNNLS_SOLVE_OVERFLOW 4      /* Bernoulli sample exceeded r_cap rows   */
+
+/* ---- options ----------------------------------------------------------- */
+#define RNNLS_SAMPLE_EXACT 0        /* exactly r distinct rows (default)      */
+#define RNNLS_SAMPLE_BERNOULLI 1    /* r~ ~ Bin(n', r/n') rows                */
+
+#define RNNLS_PREC_FP32 0           /* FP32 transform                         */
+#define RNNLS_PREC_SPLIT_BF16 1     /* reserved: split-BF16 matrix-core path  */
+
+/* Limits of this version: 1 <= d <= RNNLS_MAX_D; 1 <= r < n'; r (or r_cap)
+ * <= RNNLS_MAX_R; n' <= 2^30. */
+#define RNNLS_MAX_D 128
+#define RNNLS_MAX_R 32768
+
+typedef struct rnnls_opts {
+  int32_t sample_mode; /* RNNLS_SAMPLE_*                                      */
+  int32_t precision;   /* RNNLS_PREC_*                                        */
+  int32_t max_iter;    /* Lawson-Hanson outer-iteration cap; <= 0: 3*d        */
+  int32_t r_cap;       /* Bernoulli: rows the sketch buffers hold; <= 0: the
+                          default r + 8*ceil(sqrt(r)) + 64 (EXACT: ignored)   */
+  double tol;          /* dual tolerance tau; <= 0: 10*eps*||M||_1*max(m,d),
+                          ||M||_1 the largest column 1-norm (lsqnonneg's rule) */
+} rnnls_opts;          /* NULL opts = all defaults                            */
+
+/* Which entry point rnnls_workspace_bytes sizes. */
+#define RNNLS_OP_SKETCH 0
+#define RNNLS_OP_SOLVE 1
+#define RNNLS_OP_RAND_NNLS 2
+
+/* Library version (major*10000 + minor*100 + patch). */
+int rnnls_version(void);
+
+/* Number of gfx950 compute units the library schedules for on the current
+ * device (cached per device), or a negative RNNLS_E_* code. */
+int rnnls_device_cus(void);
+
+/* Device workspace, in bytes, that entry point `op` needs for these sizes
+ * (for RNNLS_OP_SOLVE, n is the row count m of the problem).  Returns 0 for
+ * invalid sizes. */
+size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
+                             const rnnls_opts* opts);
+
+/* rnnls_srht_sketch -- steps 1-4 of Algorithm 1.
+ *
+ *   [SA | Sb] = (1/sqrt r) * (H_n' D [A | b])[rows, :]
+ *
+ *  n, d        A is n x d (n >= 2, 1 <= d <= RNNLS_MAX_D)
+ *  r           target row count, 1 <= r < n' (n' = 2^ceil(log2 n))
+ *  seed        seed of the random streams (see above)
+ *  A, lda      input, column-major, lda >= n
+ *  b           input right-hand side of length n, or NULL (then Sb is unused)
+ *  SA, ldsa    output, column-major R x d with ldsa >= R_cap where R_cap = r
+ *              (EXACT) or opts->r_cap (BERNOULLI); rows beyond the kept
+ *              count are left untouched
+ *  Sb          output of length R_cap (ignored when b is NULL)
+ *  rows        output int32[R_cap]: kept rows of H_n', ascending; may be NULL
+ *  r_out       output int32[1]: number of kept rows; may be NULL
+ *  sign_bits   output uint32[n'/32] (n' >= 32): bit (j % 32) of word j / 32 is
+ *              set iff D_jj = -1; may be NULL
+ *  status      output int32[1]: RNNLS_SOLVE_OK, or RNNLS_SOLVE_NO_ROWS /
+ *              RNNLS_SOLVE_OVERFLOW in Bernoulli mode; may be NULL
+ */
+int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed,
+                      const float* A, int64_t lda, const float* b,
+                      float* SA, int64_t ldsa, float* Sb,
+                      int32_t* rows, int32_t* r_out, uint32_t* sign_bits,
+                      int32_t* status, const rnnls_opts* opts,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* rnnls_nnls_solve -- Definition 1 solved exactly (Lawson-Hanson, LH74 ch. 23)
+ * for a problem already on the device:  x = argmin_{x >= 0} ||M x - f||_2.
+ *
+ *  m, d        M is m x d (m >= 1, 1 <= d <= RNNLS_MAX_D)
+ *  M, ldm      input, column-major, ldm >= m
+ *  f           input right-hand side of length m
+ *  m_dev       optional device int32[1] holding the row count actually used
+ *              (<= m), e.g. r_out of a Bernoulli sketch; NULL = m
+ *  x           output double[d] (x >= 0)
+ *  w           output double[d]: dual vector M^T (f - M x); may be NULL
+ *  rnorm       output double[1]: ||M x - f||_2; may be NULL
+ *  iters       output int32[1]: outer iterations; may be NULL
+ *  status      output int32[1]: RNNLS_SOLVE_*; may be NULL
+ * The solve runs in FP64: the Gram matrix M^T M and M^T f are accumulated in
+ * FP64 from the FP32 inputs (products are exact), the passive-set systems are
+ * solved by an updated Cholesky factor.
+ */
+int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm,
+                     const float* f, const int32_t* m_dev,
+                     double* x, double* w, double* rnorm, int32_t* iters,
+                     int32_t* status, const rnnls_opts* opts,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* rnnls_rand_nnls -- Algorithm 1 end to end: sketch (as rnnls_srht_sketch)
+ * then the exact solve of the sketched problem (as rnnls_nnls_solve).
+ *
+ *  n, d, r, seed, A, lda, b   as rnnls_srht_sketch (b required)
+ *  x           output double[d]: x~ of Algorithm 1 (x~ >= 0)
+ *  rnorm       output double[1]: ||SA x~ - Sb||_2 (sketched residual); may be NULL
+ *  iters, status  as rnnls_nnls_solve; may be NULL
+ *  SA, ldsa, Sb, rows, r_out  optional copies of the sketch (as
+ *              rnnls_srht_sketch); pass NULL to keep them in the workspace
+ */
+int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
+                    const float* A, int64_t lda, const float* b,
+                    double* x, double* rnorm, int32_t* iters, int32_t* status,
+                    float* SA, int64_t ldsa, float* Sb, int32_t* rows,
+                    int32_t* r_out, const rnnls_opts* opts,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---- kernel timing ------------------------------------------------------
+ * Off by default.  When on, the library brackets every launch of the timed
+ * kernels with two HIP events recorded on the launch stream (no extra
+ * synchronisation).  rnnls_timing_read waits for the recorded events, returns
+ * the summed elapsed milliseconds and the launch count since the previous read
+ * of that timer, and forgets them.  Host-side bookkeeping is mutex-protected;
+ * a timer's begin/end pairs must not interleave across host threads. */
+#define RNNLS_TIMER_SKETCH 0   /* the sketch transform kernel (steps 1-4)      */
+#define RNNLS_TIMER_MOMENTS 1  /* Gram-form moments of the small problem       */
+#define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel                         */
+#define RNNLS_TIMER_COUNT 3
+
+int rnnls_timing_enable(int on);
+int rnnls_timing_read(int32_t which, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNNLS_H */

@@ -1,0 +1,129 @@
+// Internal definitions shared by the librnnls.so translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rnnls.h"
+
+namespace rnnls {
+
+// ---------------------------------------------------------------- random streams
+// Counter-based hash of the random diagonal D and the row sample S of
+// Algorithm 1 (definition in rnnls.h).  SplitMix64's output function.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kStreamSign = 1, kStreamSample = 2, kStreamPerm = 3;
+
+__host__ __device__ inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed ^ (stream * kGamma));
+}
+
+// Round keys of the row bijection pi on m bits (4 rounds, ka/kb per round).
+struct PermKeys {
+  uint32_t ka[4];
+  uint32_t kb[4];
+  uint32_t mask;
+  uint32_t shift;
+};
+
+inline PermKeys make_perm_keys(uint64_t seed, int m) {
+  PermKeys k;
+  const uint64_t key = stream_key(seed, kStreamPerm);
+  k.mask = (m >= 32) ? 0xFFFFFFFFu : ((1u << m) - 1u);
+  k.shift = (uint32_t)((m + 1) / 2);
+  for (int t = 0; t < 4; ++t) {
+    k.ka[t] = (uint32_t)(mix64(key + 2ull * t) & k.mask);
+    k.kb[t] = (uint32_t)(mix64(key + 2ull * t + 1ull) & k.mask) | 1u;
+  }
+  return k;
+}
+
+__device__ inline uint32_t perm_apply(const PermKeys& k, uint32_t x) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    x = (x ^ k.ka[t]) & k.mask;
+    x = (x * k.kb[t]) & k.mask;  // odd multiplier: invertible mod 2^m
+    x ^= x >> k.shift;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------- helpers
+inline int ilog2_exact(uint64_t v) {
+  int m = 0;
+  while ((1ull << m) < v) ++m;
+  return m;
+}
+inline uint64_t next_pow2(uint64_t n) { return 1ull << ilog2_exact(n); }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+#define RNNLS_HIP_CHECK(expr)                  \
+  do {                                         \
+    hipError_t err__ = (expr);                 \
+    if (err__ != hipSuccess) return RNNLS_E_HIP; \
+  } while (0)
+
+// ---------------------------------------------------------------- launchers
+// Each returns RNNLS_OK or RNNLS_E_HIP.  Pointers are device memory.
+
+// Signs: bit (j % 32) of words[j / 32] is set iff D_jj = -1, j < n_pad.
+int launch_sign_words(uint64_t seed, int64_t n_pad, uint32_t* words, hipStream_t s);
+// Exactly r rows, ascending, into rows[0..r); writes count (= r) to *count.
+int launch_rows_exact(uint64_t seed, int m, int32_t r, int32_t* rows, int32_t* count,
+                      int32_t* status, hipStream_t s);
+// Bernoulli rows; scratch must hold bernoulli_scratch_words(n_pad) uint32.
+size_t bernoulli_scratch_words(int64_t n_pad);
+int launch_rows_bernoulli(uint64_t seed, int m, int32_t r, int32_t r_cap, int32_t* rows,
+                          int32_t* count, int32_t* status, uint32_t* scratch,
+                          hipStream_t s);
+
+// The sketch transform (steps 1-4).  Partial sums go to `partials`; sizes
+// come from srht_plan.
+struct SrhtPlan {
+  int64_t n, n_pad;
+  int ncols;        // d + (b != nullptr)
+  int log_t;        // tile size T = 2^log_t (0: direct kernel for small n')
+  int64_t tiles;    // n_pad / T per column
+  int grid;         // persistent workgroups
+  int pieces;       // partial slots per column
+  int spt;          // samples per thread
+  int r_cap;
+};
+SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus);
+size_t srht_partials_bytes(const SrhtPlan& p);
+int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
+                const uint32_t* sign_words, const int32_t* rows, const int32_t* count,
+                float r_scale_num, float* partials, float* SA, int64_t ldsa, float* Sb,
+                int d, double inv_sqrt_r, hipStream_t s);
+
+// Gram-form moments of [M | f]: G = M^T M, q = M^T f, c = f^T f, column
+// 1-norms, all FP64, plus the dual tolerance tau.
+struct MomentsPlan {
+  int64_t m;
+  int d;
+  int chunks;
+};
+MomentsPlan moments_plan(int64_t m, int d, int cus);
+size_t moments_scratch_bytes(const MomentsPlan& p);
+int launch_moments(const MomentsPlan& p, const float* M, int64_t ldm, const float* f,
+                   const int32_t* m_dev, double* scratch, double* G, double* q,
+                   double* c_tau, double tol, hipStream_t s);
+
+// Lawson-Hanson on (G, q, c) for one problem.
+int launch_lawson_hanson(int d, const double* G, const double* q, const double* c_tau,
+                         int max_iter, double* x, double* w, double* rnorm,
+                         int32_t* iters, int32_t* status, const int32_t* pre_status,
+                         hipStream_t s);
+
+int device_cus();
+
+// Event timing (timing.hip): no-ops unless rnnls_timing_enable(1).
+void timer_begin(int which, hipStream_t s, void** token);
+void timer_end(int which, hipStream_t s, void* token);
+
+}  // namespace rnnls

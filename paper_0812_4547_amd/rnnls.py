@@ -1,0 +1,242 @@
+"""Python binding of librnnls.so (ctypes).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  torch provides the
+device memory and the stream.
+
+Matrices cross the boundary column-major: a torch tensor of shape (n, d) with
+stride (1, lda), lda >= n (``colmajor`` builds one from a numpy array).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librnnls.so")
+
+OK = 0
+E_HIP, E_WORKSPACE, E_UNSUPPORTED = -100, -101, -102
+SOLVE_OK, SOLVE_MAX_ITER, SOLVE_KKT_FAIL, SOLVE_NO_ROWS, SOLVE_OVERFLOW = 0, 1, 2, 3, 4
+SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
+PREC_FP32, PREC_SPLIT_BF16 = 0, 1
+OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
+MAX_D, MAX_R = 128, 32768
+
+EXPORTS = (
+    "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
+    "rnnls_nnls_solve", "rnnls_rand_nnls", "rnnls_timing_enable", "rnnls_timing_read",
+)
+TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE = 0, 1, 2
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sample_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("r_cap", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
+
+class RnnlsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+_p = ctypes.c_void_p
+_i32, _i64, _u64, _sz, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+_SIGS = {
+    "rnnls_version": ([], ctypes.c_int),
+    "rnnls_device_cus": ([], ctypes.c_int),
+    "rnnls_workspace_bytes": ([_i32, _i64, _i32, _i32, _p], _sz),
+    "rnnls_srht_sketch": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _i64, _p, _p, _p, _p, _p,
+                           _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_nnls_solve": ([_i64, _i32, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p],
+                         ctypes.c_int),
+    "rnnls_rand_nnls": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
+                         _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
+    "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load librnnls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RnnlsError(f"{path} is missing: build it with python -m paper_0812_4547_amd.build")
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise RnnlsError(f"{what} returned {rc}")
+
+
+def make_opts(sample_mode: str = "exact", precision: str = "fp32", max_iter: int = 0,
+              r_cap: int = 0, tol: float = 0.0) -> Opts:
+    return Opts(SAMPLE_EXACT if sample_mode == "exact" else SAMPLE_BERNOULLI,
+                PREC_FP32 if precision == "fp32" else PREC_SPLIT_BF16,
+                int(max_iter), int(r_cap), float(tol))
+
+
+def row_capacity(r: int, opts: Opts) -> int:
+    if opts.sample_mode == SAMPLE_EXACT:
+        return r
+    if opts.r_cap > 0:
+        return opts.r_cap
+    return r + 8 * int(np.ceil(np.sqrt(r))) + 64
+
+
+def colmajor(M: np.ndarray, device="cuda") -> torch.Tensor:
+    """Column-major device copy of a 2-D array: shape (n, d), stride (1, n)."""
+    M = np.asarray(M, dtype=np.float32)
+    return torch.from_numpy(np.ascontiguousarray(M.T)).to(device).t()
+
+
+def _check_colmajor(A: torch.Tensor, name: str) -> int:
+    if A.dim() != 2 or A.dtype != torch.float32 or not A.is_cuda:
+        raise ValueError(f"{name} must be a 2-D float32 CUDA tensor")
+    if A.shape[1] > 1 and A.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (stride (1, lda))")
+    return A.stride(1) if A.shape[1] > 1 else max(A.shape[0], 1)
+
+
+def workspace_bytes(op: int, n: int, d: int, r: int, opts: Opts | None = None) -> int:
+    return int(load().rnnls_workspace_bytes(op, n, d, r, ctypes.byref(opts or Opts())))
+
+
+def workspace(op: int, n: int, d: int, r: int, opts: Opts | None = None, device="cuda"):
+    nbytes = workspace_bytes(op, n, d, r, opts)
+    if nbytes == 0:
+        raise RnnlsError("invalid sizes for the workspace query")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Sketch:
+    SA: torch.Tensor      # (R_cap, d) column-major
+    Sb: torch.Tensor | None
+    rows: torch.Tensor    # int32 (R_cap,)
+    count: torch.Tensor   # int32 (1,)
+    status: torch.Tensor  # int32 (1,)
+    sign_bits: torch.Tensor | None
+
+
+def srht_sketch(A: torch.Tensor, b: torch.Tensor | None, r: int, seed: int,
+                opts: Opts | None = None, export_signs: bool = False, ws=None,
+                stream=None) -> Sketch:
+    """[SA | Sb] = (1/sqrt r) (H D [A | b])[rows] on the device (rnnls_srht_sketch)."""
+    opts = opts or Opts()
+    n, d = A.shape
+    lda = _check_colmajor(A, "A")
+    dev = A.device
+    rc_ = row_capacity(r, opts)
+    SA = torch.empty((d, rc_), dtype=torch.float32, device=dev).t()
+    Sb = torch.empty(rc_, dtype=torch.float32, device=dev) if b is not None else None
+    rows = torch.empty(rc_, dtype=torch.int32, device=dev)
+    count = torch.empty(1, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    n_pad = 1 << max(0, (n - 1).bit_length())
+    signs = torch.empty((n_pad + 31) // 32, dtype=torch.int32, device=dev) if export_signs else None
+    if ws is None:
+        ws = workspace(OP_SKETCH, n, d, r, opts, dev)
+    rc = load().rnnls_srht_sketch(n, d, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(b), _ptr(SA), rc_,
+                                  _ptr(Sb), _ptr(rows), _ptr(count), _ptr(signs), _ptr(status),
+                                  ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "rnnls_srht_sketch")
+    return Sketch(SA, Sb, rows, count, status, signs)
+
+
+@dataclass
+class Solution:
+    x: torch.Tensor           # float64 (d,)
+    w: torch.Tensor | None    # float64 (d,)
+    rnorm: torch.Tensor       # float64 (1,)
+    iters: torch.Tensor       # int32 (1,)
+    status: torch.Tensor      # int32 (1,)
+    sketch: Sketch | None = None
+
+
+def nnls_solve(M: torch.Tensor, f: torch.Tensor, m_dev: torch.Tensor | None = None,
+               opts: Opts | None = None, ws=None, stream=None) -> Solution:
+    """x = argmin_{x >= 0} ||M x - f|| on the device (rnnls_nnls_solve)."""
+    opts = opts or Opts()
+    m, d = M.shape
+    ldm = _check_colmajor(M, "M")
+    dev = M.device
+    x = torch.empty(d, dtype=torch.float64, device=dev)
+    w = torch.empty(d, dtype=torch.float64, device=dev)
+    rnorm = torch.empty(1, dtype=torch.float64, device=dev)
+    iters = torch.empty(1, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(OP_SOLVE, m, d, 0, opts, dev)
+    rc = load().rnnls_nnls_solve(m, d, _ptr(M), ldm, _ptr(f), _ptr(m_dev), _ptr(x), _ptr(w),
+                                 _ptr(rnorm), _ptr(iters), _ptr(status), ctypes.byref(opts),
+                                 _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "rnnls_nnls_solve")
+    return Solution(x, w, rnorm, iters, status)
+
+
+def rand_nnls(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, opts: Opts | None = None,
+              keep_sketch: bool = False, ws=None, out=None, stream=None) -> Solution:
+    """Algorithm 1 end to end on the device (rnnls_rand_nnls)."""
+    opts = opts or Opts()
+    n, d = A.shape
+    lda = _check_colmajor(A, "A")
+    dev = A.device
+    if out is None:
+        out = Solution(torch.empty(d, dtype=torch.float64, device=dev), None,
+                       torch.empty(1, dtype=torch.float64, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev))
+    sk = None
+    if keep_sketch:
+        rc_ = row_capacity(r, opts)
+        sk = Sketch(torch.empty((d, rc_), dtype=torch.float32, device=dev).t(),
+                    torch.empty(rc_, dtype=torch.float32, device=dev),
+                    torch.empty(rc_, dtype=torch.int32, device=dev),
+                    torch.empty(1, dtype=torch.int32, device=dev), out.status, None)
+    if ws is None:
+        ws = workspace(OP_RAND_NNLS, n, d, r, opts, dev)
+    rc = load().rnnls_rand_nnls(
+        n, d, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(b), _ptr(out.x), _ptr(out.rnorm),
+        _ptr(out.iters), _ptr(out.status),
+        _ptr(sk.SA) if sk else None, row_capacity(r, opts) if sk else 0,
+        _ptr(sk.Sb) if sk else None, _ptr(sk.rows) if sk else None,
+        _ptr(sk.count) if sk else None, ctypes.byref(opts), _ptr(ws), ws.numel(),
+        _stream(stream))
+    _check(rc, "rnnls_rand_nnls")
+    out.sketch = sk
+    return out
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(load().rnnls_timing_enable(1 if on else 0), "rnnls_timing_enable")
+
+
+def timing_read(which: int) -> tuple[float, int]:
+    """(summed ms, launches) of one kernel timer since its last read."""
+    ms = ctypes.c_double(0.0)
+    k = ctypes.c_int64(0)
+    _check(load().rnnls_timing_read(which, ctypes.byref(ms), ctypes.byref(k)), "rnnls_timing_read")
+    return ms.value, k.value

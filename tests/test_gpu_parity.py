@@ -1,0 +1,305 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Bars: sampled rows, counts and signs bit-exact; sketch columns within 1e-5
+relative (norm-wise per column, FP32 transform); x~ within 1e-6 relative
+residual gap of the oracle's Lawson-Hanson on the same sketch; KKT certificate.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hadamard, nnls, rand_nnls, rng
+from paper_0812_4547_amd import rnnls, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SKETCH_TOL = 1e-5
+GAP_TOL = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    rnnls.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _dev(p):
+    return rnnls.colmajor(p.A), torch.from_numpy(np.asarray(p.b, np.float32)).cuda()
+
+
+def _colwise_rel(got, want):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    if got.ndim == 1:
+        got, want = got[:, None], want[:, None]
+    num = np.linalg.norm(got - want, axis=0)
+    den = np.maximum(np.linalg.norm(want, axis=0), 1e-30)
+    return float(np.max(num / den))
+
+
+def _unpack_signs(words, n_pad):
+    w = words.cpu().numpy().view(np.uint32)
+    bits = (w[:, None] >> np.arange(32, dtype=np.uint32)) & 1
+    return np.where(bits.reshape(-1)[:n_pad] == 1, -1, 1).astype(np.int8)
+
+
+# ------------------------------------------------------------------ streams
+def test_rows_and_signs_bit_exact_against_golden():
+    with open(os.path.join(GOLDEN, "streams.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        n_pad, r, seed = c["n_pad"], c["r"], c["seed"]
+        print(f"streams case seed={seed} n'={n_pad} r={r}", flush=True)
+        A = torch.zeros((1, n_pad), dtype=torch.float32, device="cuda").t()
+        sk = rnnls.srht_sketch(A, None, r, seed, export_signs=True)
+        torch.cuda.synchronize()
+        assert int(sk.count.item()) == r
+        assert sk.rows.cpu().numpy().tolist() == c["rows_exact"]
+        D = _unpack_signs(sk.sign_bits, n_pad)
+        assert np.array_equal(D, rng.signs(seed, n_pad))
+        ob = rnnls.make_opts("bernoulli")
+        skb = rnnls.srht_sketch(A, None, r, seed, opts=ob)
+        cnt = int(skb.count.item())
+        want = rng.rows_bernoulli(seed, n_pad, r)
+        assert cnt == c["rows_bernoulli_count"] == want.size
+        assert np.array_equal(skb.rows.cpu().numpy()[:cnt], want)
+
+
+# ------------------------------------------------------------------ sketch
+def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True):
+    g = np.random.default_rng(data_seed)
+    A = g.random((n, d)).astype(np.float32)
+    b = g.standard_normal(n).astype(np.float32)
+    lda = n + lda_pad
+    buf = torch.from_numpy(np.zeros((d, lda), np.float32)).cuda()
+    buf[:, :n] = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    Ad = buf.t()[:n] if lda_pad == 0 else torch.as_strided(buf, (n, d), (1, lda))
+    bd = torch.from_numpy(b).cuda() if with_b else None
+    opts = rnnls.make_opts(mode)
+    sk = rnnls.srht_sketch(Ad, bd, r, seed, opts=opts)
+    torch.cuda.synchronize()
+    SA_o, Sb_o, R_o, _ = hadamard.srht_sketch(A, b if with_b else None, r, seed, mode)
+    cnt = int(sk.count.item())
+    assert cnt == R_o.size
+    assert np.array_equal(sk.rows.cpu().numpy()[:cnt], R_o)
+    SA = sk.SA.cpu().numpy()[:cnt]
+    assert _colwise_rel(SA, SA_o) <= SKETCH_TOL
+    if with_b:
+        assert _colwise_rel(sk.Sb.cpu().numpy()[:cnt], Sb_o) <= SKETCH_TOL
+
+
+@pytest.mark.parametrize("n,d,r,seed", [
+    (4096, 16, 512, 1),                 # one 4096-row tile
+    (3 * 32768 + 1234, 20, 1000, 5),    # several 2^15 tiles and a ragged tail
+    (1 << 16, 7, 4000, 11),             # two tiles, many samples per thread
+    (40000, 3, 2048, 2),                # ragged, 2^16 padded
+    (8192, 1, 8191, 3),                 # r = n' - 1
+    (1000, 5, 100, 4),                  # small n': direct kernel
+    (2, 1, 1, 9),                       # smallest problem
+    (20000, 128, 4096, 6),              # widest A
+])
+def test_sketch_matches_oracle(n, d, r, seed):
+    print(f"sketch n={n} d={d} r={r}", flush=True)
+    _sketch_case(n, d, r, seed, data_seed=seed + 100)
+
+
+def test_sketch_unaligned_leading_dimension():
+    _sketch_case(50001, 6, 700, 8, data_seed=3, lda_pad=3)
+
+
+def test_sketch_without_b():
+    _sketch_case(30000, 9, 500, 12, data_seed=4, with_b=False)
+
+
+@pytest.mark.parametrize("n,d,r,seed", [(50000, 8, 700, 7), (4096, 4, 300, 1), (1500, 3, 64, 2)])
+def test_sketch_bernoulli_matches_oracle(n, d, r, seed):
+    _sketch_case(n, d, r, seed, data_seed=seed, mode="bernoulli")
+
+
+def test_sketch_bernoulli_overflow_status():
+    n, d, r = 1 << 14, 2, 2000
+    A = torch.ones((d, n), dtype=torch.float32, device="cuda").t()
+    sk = rnnls.srht_sketch(A, None, r, 5, opts=rnnls.make_opts("bernoulli", r_cap=100))
+    torch.cuda.synchronize()
+    assert int(sk.status.item()) == rnnls.SOLVE_OVERFLOW
+    assert int(sk.count.item()) == 100
+    want = rng.rows_bernoulli(5, n, r)[:100]
+    assert np.array_equal(sk.rows.cpu().numpy(), want)
+
+
+def test_sketch_is_deterministic():
+    p = workloads.tfidf_like(1 << 17, 12, seed=3)
+    A, b = _dev(p)
+    s1 = rnnls.srht_sketch(A, b, 2000, 77)
+    s2 = rnnls.srht_sketch(A, b, 2000, 77)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.SA, s2.SA) and torch.equal(s1.Sb, s2.Sb)
+
+
+def test_sketch_full_size_sampled_rows():
+    # the single-instance workload at its full size (2^20 x 64, r = 4096): every
+    # row count, row index and sign is checked in full; sketch entries on a
+    # sample of rows, each computed by the oracle straight from the definition
+    n, d, r, seed = 1 << 20, 64, 4096, 2
+    p = workloads.tfidf_like(n, d, seed=2)
+    A, b = _dev(p)
+    sk = rnnls.srht_sketch(A, b, r, seed, export_signs=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(sk.rows.cpu().numpy(), rng.rows_exact(seed, n, r))
+    D = rng.signs(seed, n)
+    assert np.array_equal(_unpack_signs(sk.sign_bits, n), D)
+    SA = sk.SA.cpu().numpy()
+    Sb = sk.Sb.cpu().numpy()
+    M = np.column_stack([p.A, p.b]).astype(np.float64)
+    scale = np.linalg.norm(M, axis=0) / np.sqrt(r)   # rms size of a sketch entry
+    R = sk.rows.cpu().numpy()
+    for ell in (0, 1, 517, 2048, 4095):
+        want = hadamard.sketch_row_direct(M, D.astype(np.float64), int(R[ell]), r)
+        got = np.append(SA[ell], Sb[ell]).astype(np.float64)
+        assert np.max(np.abs(got - want) / scale) <= SKETCH_TOL
+
+
+# ------------------------------------------------------------------ solve
+def _solve_case(m, d, seed, planted_zeros=None):
+    g = np.random.default_rng(seed)
+    M = g.standard_normal((m, d)).astype(np.float32)
+    xs = np.abs(g.standard_normal(d))
+    if planted_zeros:
+        xs[g.choice(d, planted_zeros, replace=False)] = 0
+    f = (M.astype(np.float64) @ xs + 0.3 * g.standard_normal(m)).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(M), torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    ref = nnls.lawson_hanson(M, f)
+    x = sol.x.cpu().numpy()
+    gap = nnls.relative_residual_gap(M, f, x, ref.x)
+    assert abs(gap) <= GAP_TOL, gap
+    assert int(sol.status.item()) == rnnls.SOLVE_OK
+    assert np.all(x >= 0)
+    v = nnls.kkt_violation(M, f, x)
+    tau = nnls.default_tol(M)
+    assert v["dual_off"] <= 1e3 * tau
+    # x itself when the passive system is well conditioned
+    P = ref.x > 0
+    if P.any() and np.linalg.cond(M[:, P].astype(np.float64)) < 1e4:
+        np.testing.assert_allclose(x, ref.x, rtol=1e-7, atol=1e-9 * max(1.0, np.abs(ref.x).max()))
+    rn = float(sol.rnorm.item())
+    assert abs(rn - ref.rnorm) <= 1e-6 * max(ref.rnorm, 1e-3 * np.linalg.norm(f))
+    return sol
+
+
+@pytest.mark.parametrize("m,d,seed,zeros", [
+    (50, 1, 1, None), (200, 5, 2, 2), (300, 16, 3, 8), (600, 40, 4, 15),
+    (1000, 64, 5, 20), (2000, 96, 6, 30), (3000, 128, 7, 40), (130, 128, 8, 60),
+])
+def test_nnls_solve_matches_oracle(m, d, seed, zeros):
+    print(f"solve m={m} d={d}", flush=True)
+    _solve_case(m, d, seed, zeros)
+
+
+def test_nnls_solve_edge_cases():
+    # b = 0 gives x = 0
+    M = np.random.default_rng(0).random((40, 6)).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(M), torch.zeros(40, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.all(sol.x.cpu().numpy() == 0) and int(sol.iters.item()) == 0
+    # every correlation negative gives x = 0
+    f = -(M.astype(np.float64) @ np.ones(6)).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(M), torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert np.all(sol.x.cpu().numpy() == 0)
+    # a duplicated column is refused, the optimum is still reached
+    g = np.random.default_rng(9)
+    A = g.random((60, 4))
+    A = np.column_stack([A, A[:, 1]]).astype(np.float32)
+    f = (A[:, :4].astype(np.float64) @ np.array([1.0, 2.0, 0.0, 0.5]) + 0.01 * g.standard_normal(60)).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(A), torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    _, rb = nnls.brute_force(A, f)
+    got = np.linalg.norm(A.astype(np.float64) @ sol.x.cpu().numpy() - f)
+    assert got <= rb * (1 + GAP_TOL)
+    # iteration cap reports status 1
+    M2 = g.standard_normal((100, 20)).astype(np.float32)
+    f2 = (M2.astype(np.float64) @ np.abs(g.standard_normal(20))).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(M2), torch.from_numpy(f2).cuda(),
+                           opts=rnnls.make_opts(max_iter=1))
+    torch.cuda.synchronize()
+    assert int(sol.status.item()) == rnnls.SOLVE_MAX_ITER and int(sol.iters.item()) == 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_nnls_solve_matches_brute_force(seed):
+    g = np.random.default_rng(40 + seed)
+    M = g.standard_normal((30, 8)).astype(np.float32)
+    f = (M.astype(np.float64) @ g.standard_normal(8) + 0.1 * g.standard_normal(30)).astype(np.float32)
+    sol = rnnls.nnls_solve(rnnls.colmajor(M), torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    _, rb = nnls.brute_force(M, f)
+    got = np.linalg.norm(M.astype(np.float64) @ sol.x.cpu().numpy() - f.astype(np.float64))
+    assert abs(got / rb - 1) <= GAP_TOL
+
+
+# ------------------------------------------------------------------ end to end
+def _check_rand_nnls(p, r, seed, mode="exact"):
+    A, b = _dev(p)
+    sol = rnnls.rand_nnls(A, b, r, seed, opts=rnnls.make_opts(mode), keep_sketch=True)
+    torch.cuda.synchronize()
+    ref = rand_nnls.rand_nnls(p.A, p.b, r, seed, mode)
+    cnt = int(sol.sketch.count.item())
+    assert cnt == ref.rows.size
+    assert np.array_equal(sol.sketch.rows.cpu().numpy()[:cnt], ref.rows)
+    assert _colwise_rel(sol.sketch.SA.cpu().numpy()[:cnt], ref.SA) <= SKETCH_TOL
+    x = sol.x.cpu().numpy()
+    assert np.all(x >= 0)
+    # residual gap on the oracle's FP64 sketch and on the full problem
+    g_sk = nnls.relative_residual_gap(ref.SA, ref.Sb, x, ref.x)
+    g_full = nnls.relative_residual_gap(p.A, p.b, x, ref.x)
+    assert abs(g_sk) <= GAP_TOL, g_sk
+    assert abs(g_full) <= GAP_TOL, g_full
+    assert int(sol.status.item()) == rnnls.SOLVE_OK
+    return sol, ref
+
+
+def test_rand_nnls_single_instance_4096x16():
+    p = workloads.uniform_planted(seed=1)
+    _check_rand_nnls(p, 512, 1)
+
+
+@pytest.mark.parametrize("n,d,r,seed", [(3 * 32768 + 77, 24, 1500, 3), (1 << 15, 40, 3000, 4)])
+def test_rand_nnls_tfidf_like(n, d, r, seed):
+    _check_rand_nnls(workloads.tfidf_like(n, d, seed=seed), r, seed)
+
+
+def test_rand_nnls_bernoulli():
+    _check_rand_nnls(workloads.uniform_planted(n=20000, d=10, zeros=4, seed=5), 900, 6, "bernoulli")
+
+
+def test_rand_nnls_full_size_single_instance():
+    # 2^20 x 64, r = 4096: the oracle solves the GPU's own sketch (in FP64) and
+    # the GPU's x~ must reach the same residual on it and on the full problem
+    n, d, r, seed = 1 << 20, 64, 4096, 2
+    p = workloads.tfidf_like(n, d, seed=2)
+    A, b = _dev(p)
+    sol = rnnls.rand_nnls(A, b, r, seed, keep_sketch=True)
+    torch.cuda.synchronize()
+    SA = sol.sketch.SA.cpu().numpy().astype(np.float64)
+    Sb = sol.sketch.Sb.cpu().numpy().astype(np.float64)
+    ref = nnls.lawson_hanson(SA, Sb)
+    x = sol.x.cpu().numpy()
+    assert abs(nnls.relative_residual_gap(SA, Sb, x, ref.x)) <= GAP_TOL
+    assert abs(nnls.relative_residual_gap(p.A, p.b, x, ref.x)) <= GAP_TOL
+    assert int(sol.status.item()) == rnnls.SOLVE_OK
+    assert np.array_equal(sol.sketch.rows.cpu().numpy(), rng.rows_exact(seed, n, r))
+
+
+def test_workspace_too_small_is_rejected():
+    p = workloads.uniform_planted(seed=1)
+    A, b = _dev(p)
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rnnls.RnnlsError):
+        rnnls.rand_nnls(A, b, 512, 1, ws=ws)
