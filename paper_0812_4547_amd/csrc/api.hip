@@ -62,7 +62,7 @@ int row_capacity(int r, const Opts& o) {
 // Workspace layout; every region 256-byte aligned.
 struct Layout {
   size_t rows = 0, count = 0, status = 0, signs = 0, bern = 0, partials = 0, sa = 0, sb = 0,
-         mom = 0, G = 0, q = 0, ctau = 0, total = 0;
+         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, total = 0;
 };
 
 size_t put(size_t& off, size_t bytes) {
@@ -85,8 +85,7 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
   L.count = put(off, sizeof(int32_t));
   L.status = put(off, sizeof(int32_t));
   L.signs = put(off, sizeof(uint32_t) * (size_t)((z.n_pad + 31) / 32));
-  if (o.sample_mode == RNNLS_SAMPLE_BERNOULLI)
-    L.bern = put(off, sizeof(uint32_t) * bernoulli_scratch_words(z.n_pad));
+  L.bern = put(off, sizeof(uint32_t) * streams_scratch_words(z.n_pad));
   L.partials = put(off, srht_partials_bytes(z.sp));
   L.sa = put(off, sizeof(float) * (size_t)z.d * z.r_cap);
   L.sb = put(off, sizeof(float) * (size_t)(with_b ? z.r_cap : 0));
@@ -94,7 +93,8 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
     L.mom = put(off, moments_scratch_bytes(z.mp));
     L.G = put(off, sizeof(double) * (size_t)z.d * z.d);
     L.q = put(off, sizeof(double) * (size_t)z.d);
-    L.ctau = put(off, sizeof(double) * 2);
+    L.cc = put(off, sizeof(double));
+    L.colabs = put(off, sizeof(double) * (size_t)z.d);
   }
   L.total = off;
   return L;
@@ -106,7 +106,8 @@ Layout layout_solve(const Sizes& z) {
   L.mom = put(off, moments_scratch_bytes(z.mp));
   L.G = put(off, sizeof(double) * (size_t)z.d * z.d);
   L.q = put(off, sizeof(double) * (size_t)z.d);
-  L.ctau = put(off, sizeof(double) * 2);
+  L.cc = put(off, sizeof(double));
+  L.colabs = put(off, sizeof(double) * (size_t)z.d);
   L.total = off;
   return L;
 }
@@ -131,15 +132,11 @@ int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n
 
 int sketch_core(const Sizes& z, const Opts& o, uint64_t seed, const float* A, int64_t lda,
                 const float* b, float* SA, int64_t ldsa, float* Sb, int32_t* rows,
-                int32_t* count, uint32_t* signs, int32_t* status, uint32_t* bern_scratch,
+                int32_t* count, uint32_t* signs, int32_t* status, uint32_t* stream_scratch,
                 float* partials, hipStream_t s) {
   const int m = ilog2_exact((uint64_t)z.n_pad);
-  int rc = launch_sign_words(seed, z.n_pad, signs, s);
-  if (rc) return rc;
-  if (o.sample_mode == RNNLS_SAMPLE_EXACT)
-    rc = launch_rows_exact(seed, m, z.r, rows, count, status, s);
-  else
-    rc = launch_rows_bernoulli(seed, m, z.r, z.r_cap, rows, count, status, bern_scratch, s);
+  int rc = launch_streams(seed, m, z.r, z.r_cap, o.sample_mode, signs, rows, count, status,
+                          stream_scratch, s);
   if (rc) return rc;
   const double inv_sqrt_r = 1.0 / sqrt((double)z.r);
   return launch_srht(z.sp, A, lda, b, signs, rows, count, 0.0f, partials, SA, ldsa, Sb, z.d,
@@ -239,11 +236,13 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   double* G = at<double>(ws, L.G);
   double* q = at<double>(ws, L.q);
-  double* ct = at<double>(ws, L.ctau);
-  int rc = launch_moments(z.mp, M, ldm, f, m_dev, at<double>(ws, L.mom), G, q, ct, o.tol, s);
+  double* cc = at<double>(ws, L.cc);
+  double* colabs = at<double>(ws, L.colabs);
+  int rc = launch_moments(z.mp, M, ldm, f, m_dev, at<double>(ws, L.mom), G, q, cc, colabs, s);
   if (rc) return rc;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
-  return launch_lawson_hanson(d, G, q, ct, max_iter, x, w, rnorm, iters, status, nullptr, s);
+  return launch_lawson_hanson(d, G, q, cc, colabs, m, m_dev, o.tol, max_iter, x, w, rnorm, iters,
+                              status, nullptr, 1, s);
 }
 
 int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A, int64_t lda,
@@ -278,11 +277,13 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   if (rc) return rc;
   double* G = at<double>(ws, L.G);
   double* q = at<double>(ws, L.q);
-  double* ct = at<double>(ws, L.ctau);
-  rc = launch_moments(z.mp, sa, ld, sb, cnt, at<double>(ws, L.mom), G, q, ct, o.tol, s);
+  double* cc = at<double>(ws, L.cc);
+  double* colabs = at<double>(ws, L.colabs);
+  rc = launch_moments(z.mp, sa, ld, sb, cnt, at<double>(ws, L.mom), G, q, cc, colabs, s);
   if (rc) return rc;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
-  return launch_lawson_hanson(d, G, q, ct, max_iter, x, nullptr, rnorm, iters, status, st, s);
+  return launch_lawson_hanson(d, G, q, cc, colabs, z.r_cap, cnt, o.tol, max_iter, x, nullptr, rnorm,
+                              iters, status, st, 1, s);
 }
 
 }  // extern "C"

@@ -71,16 +71,14 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- launchers
 // Each returns RNNLS_OK or RNNLS_E_HIP.  Pointers are device memory.
 
-// Signs: bit (j % 32) of words[j / 32] is set iff D_jj = -1, j < n_pad.
-int launch_sign_words(uint64_t seed, int64_t n_pad, uint32_t* words, hipStream_t s);
-// Exactly r rows, ascending, into rows[0..r); writes count (= r) to *count.
-int launch_rows_exact(uint64_t seed, int m, int32_t r, int32_t* rows, int32_t* count,
-                      int32_t* status, hipStream_t s);
-// Bernoulli rows; scratch must hold bernoulli_scratch_words(n_pad) uint32.
-size_t bernoulli_scratch_words(int64_t n_pad);
-int launch_rows_bernoulli(uint64_t seed, int m, int32_t r, int32_t r_cap, int32_t* rows,
-                          int32_t* count, int32_t* status, uint32_t* scratch,
-                          hipStream_t s);
+// Signs and kept rows for n' = 2^m.  sign_words: bit (j % 32) of word j / 32
+// set iff D_jj = -1.  rows: kept rows ascending (at most r_cap written);
+// *count = kept rows (clamped to r_cap); *status = RNNLS_SOLVE_OK, _NO_ROWS or
+// _OVERFLOW.  scratch holds streams_scratch_words(n') uint32.
+size_t streams_scratch_words(int64_t n_pad);
+int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode,
+                   uint32_t* sign_words, int32_t* rows, int32_t* count, int32_t* status,
+                   uint32_t* scratch, hipStream_t s);
 
 // The sketch transform (steps 1-4).  Partial sums go to `partials`; sizes
 // come from srht_plan.
@@ -101,8 +99,8 @@ int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
                 float r_scale_num, float* partials, float* SA, int64_t ldsa, float* Sb,
                 int d, double inv_sqrt_r, hipStream_t s);
 
-// Gram-form moments of [M | f]: G = M^T M, q = M^T f, c = f^T f, column
-// 1-norms, all FP64, plus the dual tolerance tau.
+// Gram-form moments of [M | f]: G = M^T M (d x d), q = M^T f, c = f^T f and
+// the column 1-norms of M, all FP64.
 struct MomentsPlan {
   int64_t m;
   int d;
@@ -111,14 +109,17 @@ struct MomentsPlan {
 MomentsPlan moments_plan(int64_t m, int d, int cus);
 size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, const float* M, int64_t ldm, const float* f,
-                   const int32_t* m_dev, double* scratch, double* G, double* q,
-                   double* c_tau, double tol, hipStream_t s);
+                   const int32_t* m_dev, double* scratch, double* G, double* q, double* cc,
+                   double* colabs, hipStream_t s);
 
-// Lawson-Hanson on (G, q, c) for one problem.
-int launch_lawson_hanson(int d, const double* G, const double* q, const double* c_tau,
-                         int max_iter, double* x, double* w, double* rnorm,
-                         int32_t* iters, int32_t* status, const int32_t* pre_status,
-                         hipStream_t s);
+// Lawson-Hanson on (G, q, c) for nprob problems stored back to back (G at
+// d*d, q, colabs, x, w at d, c, rnorm, iters, status at 1 per problem).  The
+// tolerance is tol when > 0, else 10 eps max(colabs) max(m_eff, d).
+size_t lh_lds_bytes(int d);
+int launch_lawson_hanson(int d, const double* G, const double* q, const double* cc,
+                         const double* colabs, int64_t m, const int32_t* m_dev, double tol,
+                         int max_iter, double* x, double* w, double* rnorm, int32_t* iters,
+                         int32_t* status, const int32_t* pre_status, int nprob, hipStream_t s);
 
 int device_cus();
 
