@@ -184,6 +184,11 @@ def _solve_case(m, d, seed, planted_zeros=None):
     v = nnls.kkt_violation(M, f, x)
     tau = nnls.default_tol(M)
     assert v["dual_off"] <= 1e3 * tau
+    # the returned dual vector is M^T (f - M x) of the returned x
+    M64 = M.astype(np.float64)
+    w_host = M64.T @ (f.astype(np.float64) - M64 @ x)
+    scale = np.abs(M64).sum(axis=0).max() * max(np.abs(f).max(), 1.0)
+    assert np.max(np.abs(sol.w.cpu().numpy() - w_host)) <= 1e-10 * scale
     # x itself when the passive system is well conditioned
     P = ref.x > 0
     if P.any() and np.linalg.cond(M[:, P].astype(np.float64)) < 1e4:
@@ -195,7 +200,8 @@ def _solve_case(m, d, seed, planted_zeros=None):
 
 @pytest.mark.parametrize("m,d,seed,zeros", [
     (50, 1, 1, None), (200, 5, 2, 2), (300, 16, 3, 8), (600, 40, 4, 15),
-    (1000, 64, 5, 20), (2000, 96, 6, 30), (3000, 128, 7, 40), (130, 128, 8, 60),
+    (1000, 64, 5, 20), (1000, 66, 5, 20), (1000, 70, 5, 20), (2000, 96, 6, 30),
+    (3000, 128, 7, 40), (130, 128, 8, 60),
 ])
 def test_nnls_solve_matches_oracle(m, d, seed, zeros):
     print(f"solve m={m} d={d}", flush=True)
