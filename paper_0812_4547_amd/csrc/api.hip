@@ -62,7 +62,7 @@ int row_capacity(int r, const Opts& o) {
 // Workspace layout; every region 256-byte aligned.
 struct Layout {
   size_t rows = 0, count = 0, status = 0, signs = 0, bern = 0, partials = 0, sa = 0, sb = 0,
-         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, total = 0;
+         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, lh = 0, total = 0;
 };
 
 size_t put(size_t& off, size_t bytes) {
@@ -95,6 +95,7 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
     L.q = put(off, sizeof(double) * (size_t)z.d);
     L.cc = put(off, sizeof(double));
     L.colabs = put(off, sizeof(double) * (size_t)z.d);
+    L.lh = put(off, lh_global_scratch_bytes(z.d, 1));
   }
   L.total = off;
   return L;
@@ -108,6 +109,7 @@ Layout layout_solve(const Sizes& z) {
   L.q = put(off, sizeof(double) * (size_t)z.d);
   L.cc = put(off, sizeof(double));
   L.colabs = put(off, sizeof(double) * (size_t)z.d);
+  L.lh = put(off, lh_global_scratch_bytes(z.d, 1));
   L.total = off;
   return L;
 }
@@ -242,7 +244,7 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   if (rc) return rc;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
   return launch_lawson_hanson(d, G, q, cc, colabs, m, m_dev, o.tol, max_iter, x, w, rnorm, iters,
-                              status, nullptr, 1, s);
+                              status, nullptr, 1, at<double>(ws, L.lh), s);
 }
 
 int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A, int64_t lda,
@@ -283,7 +285,7 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   if (rc) return rc;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
   return launch_lawson_hanson(d, G, q, cc, colabs, z.r_cap, cnt, o.tol, max_iter, x, nullptr, rnorm,
-                              iters, status, st, 1, s);
+                              iters, status, st, 1, at<double>(ws, L.lh), s);
 }
 
 }  // extern "C"

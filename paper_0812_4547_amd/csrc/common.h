@@ -115,11 +115,15 @@ int launch_moments(const MomentsPlan& p, const float* M, int64_t ldm, const floa
 // Lawson-Hanson on (G, q, c) for nprob problems stored back to back (G at
 // d*d, q, colabs, x, w at d, c, rnorm, iters, status at 1 per problem).  The
 // tolerance is tol when > 0, else 10 eps max(colabs) max(m_eff, d).
+// Wide problems keep Q[:, P] in global scratch (lh_global_scratch_bytes, 0 when
+// it fits in LDS).
 size_t lh_lds_bytes(int d);
+size_t lh_global_scratch_bytes(int d, int nprob);
 int launch_lawson_hanson(int d, const double* G, const double* q, const double* cc,
                          const double* colabs, int64_t m, const int32_t* m_dev, double tol,
                          int max_iter, double* x, double* w, double* rnorm, int32_t* iters,
-                         int32_t* status, const int32_t* pre_status, int nprob, hipStream_t s);
+                         int32_t* status, const int32_t* pre_status, int nprob,
+                         double* global_scratch, hipStream_t s);
 
 int device_cus();
 

@@ -10,13 +10,16 @@
 //
 // Passive columns live in "slots" (0 <= slot < d): B is indexed by slot, a
 // freed slot has a zero row and column in B, and new columns take the lowest
-// free slot.  B is stored in full in LDS with an odd leading dimension (lane s
-// reads row s, so a fixed column hits distinct banks) plus one dummy row that
-// out-of-range lanes read and write.  Q sits in LDS the same way when both
-// fit (d <= 96), otherwise it is read from global memory (L2-resident).
-// Vectors indexed by slot or by column live in registers, lane l holding
-// entries l and l+64.  Every hot loop has a wave-uniform trip count and no
-// branch in its body, so LDS reads of consecutive iterations overlap.
+// free slot.  QP = Q[:, P] is kept by slot as well (QP[col][slot]), so the dual
+// vector w = q - QP x_P, the candidate column g = QP[t][.] and the refinement
+// residual are all "one row per lane times a broadcast vector".  Each lane
+// owns a contiguous row (reads at fixed offsets, odd leading dimension so a
+// fixed column hits distinct banks); the broadcast vector is staged in LDS and
+// read by all lanes at one address.  Out-of-range lanes use a dummy row.
+// B and QP sit in LDS when both fit, otherwise QP lives in a global scratch
+// buffer (L2-resident).  Slot- and column-indexed vectors live in registers,
+// lane l holding entries l and l+64 (d <= 128).  Loop trip counts and the
+// results of wave reductions are scalar, so control flow stays uniform.
 //
 // Steps (the same readings as the oracle: tolerance tau, lowest index on ties,
 // refusal of dependent or non-positive entering columns, outer cap):
@@ -41,28 +44,20 @@ namespace {
 constexpr int kW = 64;
 constexpr double kDependence = 1e-14;
 constexpr int kNone = 0x7fffffff;
-constexpr int kMaxLdsBytes = 160 * 1024;
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 
-// Values every lane already agrees on (results of a full shuffle reduction)
-// are moved to scalar registers so branches on them stay wave-uniform.
+__host__ __device__ inline int lds_ld(int d) { return d | 1; }
+
+// Values every lane already agrees on are moved to scalar registers so that
+// branches on them stay wave-uniform.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-// every lane's predicate holds (ballot is an intrinsic the compiler knows to
-// be uniform, unlike the library vote call)
-__device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
 __device__ __forceinline__ double uni(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
-
-template <int H>
-__device__ __forceinline__ double bcast(const double (&v)[H], int k) {
-  const double e = (H == 1 || k < kW) ? v[0] : v[H - 1];
-  const int l = k & (kW - 1);
-  const int lo = __builtin_amdgcn_readlane(__double2loint(e), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(e), l);
-  return __hiloint2double(hi, lo);
-}
+// every lane's predicate holds (ballot is an intrinsic known to be uniform)
+__device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
 
 template <int H>
 __device__ __forceinline__ int bcast(const int (&v)[H], int k) {
@@ -99,192 +94,218 @@ __device__ __forceinline__ double wave_sum(double v) {
   return lane63(v);
 }
 
-// (value, index) pairs ordered by value, lower index first on ties; MAX picks
-// the largest value, otherwise the smallest
+// two sums at once (their DPP chains interleave)
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+#define RNNLS_SUM2_STEP(C, R) \
+  {                           \
+    const double oa = dpp<C, R>(0.0, a); \
+    const double ob = dpp<C, R>(0.0, b); \
+    a += oa;                  \
+    b += ob;                  \
+  }
+  RNNLS_DPP_STEPS(RNNLS_SUM2_STEP)
+#undef RNNLS_SUM2_STEP
+  a = lane63(a);
+  b = lane63(b);
+}
+
 template <bool MAX>
-__device__ __forceinline__ void wave_arg(double& v, int& idx) {
+__device__ __forceinline__ double wave_extreme(double v) {
   const double ident = MAX ? -DBL_MAX : DBL_MAX;
-#define RNNLS_ARG_STEP(C, R)                                                   \
-  {                                                                            \
-    const double ov = dpp<C, R>(ident, v);                                     \
-    const int oi = dpp<C, R>(kNone, idx);                                      \
-    const bool better = MAX ? (ov > v || (ov == v && oi < idx))                \
-                            : (ov < v || (ov == v && oi < idx));               \
-    v = better ? ov : v;                                                       \
-    idx = better ? oi : idx;                                                   \
+#define RNNLS_EXT_STEP(C, R)                 \
+  {                                          \
+    const double o = dpp<C, R>(ident, v);    \
+    v = MAX ? fmax(v, o) : fmin(v, o);       \
   }
-  RNNLS_DPP_STEPS(RNNLS_ARG_STEP)
-#undef RNNLS_ARG_STEP
-  v = lane63(v);
-  idx = __builtin_amdgcn_readlane(idx, kW - 1);
+  RNNLS_DPP_STEPS(RNNLS_EXT_STEP)
+#undef RNNLS_EXT_STEP
+  return lane63(v);
 }
 
-// Loop over k < n with a 4-wide body, then the remainder (readlane keeps the
-// compiler from unrolling a loop of unknown trip count by itself).
-template <class F>
-__device__ __forceinline__ void loop4(int n, F&& f) {
+// Lowest index holding the largest (MAX) or smallest value among the lanes'
+// candidates v[h] (index lane + 64 h, only where ok[h]); kNone if none.
+template <bool MAX, int H>
+__device__ __forceinline__ int wave_arg(const double (&v)[H], const bool (&ok)[H],
+                                        double& best) {
+  const double ident = MAX ? -DBL_MAX : DBL_MAX;
+  double mine = ident;
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+    if (ok[h]) mine = MAX ? fmax(mine, v[h]) : fmin(mine, v[h]);
+  best = wave_extreme<MAX>(mine);
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const uint64_t hit = __ballot(ok[h] && v[h] == best);
+    if (hit) return h * kW + (int)__builtin_ctzll(hit);
+  }
+  return kNone;
+}
+
+// Order LDS traffic of the (single) wavefront: its DS operations complete in
+// issue order, so only the compiler must not move them across this point.
+template <bool GLOBAL>
+__device__ __forceinline__ void lh_sync() {
+  if (GLOBAL) {
+    __syncthreads();  // global scratch: wait for the stores as well
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Stage a slot- or column-indexed vector in LDS for broadcast reads.
+template <int H>
+__device__ __forceinline__ void stage(double* vb, const double (&v)[H]) {
+#pragma unroll
+  for (int h = 0; h < H; ++h) vb[threadIdx.x + h * kW] = v[h];
+  lh_sync<false>();
+}
+
+// u[h] = sum_{k < n} row[h][k] * vb[k]  (two accumulators per row).  Blocks
+// of 16: all loads of a block are issued before its FMAs.
+template <int H, class Ptr>
+__device__ __forceinline__ void mv(const Ptr (&row)[H], const double* vb, int n,
+                                   double (&u)[H]) {
+  double a[H][2];
+#pragma unroll
+  for (int h = 0; h < H; ++h) a[h][0] = a[h][1] = 0.0;
   int k = 0;
+  for (; k + 16 <= n; k += 16) {
+    double2 v2[8];
+    double r[H][16];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) r[h][i] = row[h][k + i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v2[i] = *reinterpret_cast<const double2*>(vb + k + 2 * i);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        a[h][0] = fma(r[h][2 * i], v2[i].x, a[h][0]);
+        a[h][1] = fma(r[h][2 * i + 1], v2[i].y, a[h][1]);
+      }
+  }
   for (; k + 4 <= n; k += 4) {
-    f(k, 0);
-    f(k + 1, 1);
-    f(k + 2, 0);
-    f(k + 3, 1);
+    double r[H][4];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r[h][i] = row[h][k + i];
+    const double2 v0 = *reinterpret_cast<const double2*>(vb + k);
+    const double2 v1 = *reinterpret_cast<const double2*>(vb + k + 2);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      a[h][0] = fma(r[h][0], v0.x, a[h][0]);
+      a[h][1] = fma(r[h][1], v0.y, a[h][1]);
+      a[h][0] = fma(r[h][2], v1.x, a[h][0]);
+      a[h][1] = fma(r[h][3], v1.y, a[h][1]);
+    }
   }
-  for (; k < n; ++k) f(k, k & 1);
-}
-
-template <int H, bool QG>
-struct Ctx {
-  const double* Q;  // LDS (leading dim ldq) or global (leading dim d)
-  double* B;        // LDS, (d+1) x ldb, row d is a dummy
-  const double* q;  // LDS
-  int d, ldq, ldb;
-  int row[H];       // this lane's slot/column index, clamped: out-of-range -> d
-  int rowq[H];      // same, clamped to d-1 for Q reads
-
-  __device__ __forceinline__ double Qv(int i, int j) const { return Q[i * ldq + j]; }
-};
-
-// u = B v over slots [0, hwm); two accumulators per row (even/odd k)
-template <int H, bool QG>
-__device__ __forceinline__ void mv_B(const Ctx<H, QG>& c, int hwm, const double (&v)[H],
-                                     double (&u)[H]) {
-  double acc[H][2];
+  for (; k < n; ++k) {
+    const double vk = vb[k];
 #pragma unroll
-  for (int h = 0; h < H; ++h) acc[h][0] = acc[h][1] = 0.0;
-  const double* b[H];
-#pragma unroll
-  for (int h = 0; h < H; ++h) b[h] = c.B + c.row[h] * c.ldb;
-  loop4(hwm, [&](int k, int par) {
-    const double vk = bcast(v, k);
-#pragma unroll
-    for (int h = 0; h < H; ++h) acc[h][par] = fma(b[h][k], vk, acc[h][par]);
-  });
-#pragma unroll
-  for (int h = 0; h < H; ++h) u[h] = acc[h][0] + acc[h][1];
-}
-
-// B += a y y^T over slots [0, hwm) (both triangles: lane s updates row s)
-template <int H, bool QG>
-__device__ __forceinline__ void rank1(const Ctx<H, QG>& c, int hwm, const double (&y)[H],
-                                      double a) {
-  double* b[H];
-  double ya[H];
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    b[h] = c.B + c.row[h] * c.ldb;
-    ya[h] = a * y[h];
+    for (int h = 0; h < H; ++h) a[h][k & 1] = fma(row[h][k], vk, a[h][k & 1]);
   }
-  loop4(hwm, [&](int k, int) {
-    const double yk = bcast(y, k);
 #pragma unroll
-    for (int h = 0; h < H; ++h) b[h][k] = fma(ya[h], yk, b[h][k]);
-  });
+  for (int h = 0; h < H; ++h) u[h] = a[h][0] + a[h][1];
 }
 
-// w = q - Q x over columns (x given by slot: scol / xs)
-template <int H, bool QG>
-__device__ __forceinline__ void dual(const Ctx<H, QG>& c, int hwm, const int (&scol)[H],
-                                     const double (&xs)[H], double (&w)[H]) {
-  double acc[H][2];
+// row[h][k] += ya[h] * vb[k] for k < n (lane s updates its own row)
+template <int H>
+__device__ __forceinline__ void rank1(double* const (&row)[H], const double (&ya)[H],
+                                      const double* vb, int n) {
+  int k = 0;
+  for (; k + 16 <= n; k += 16) {
+    double2 v2[8];
+    double r[H][16];
 #pragma unroll
-  for (int h = 0; h < H; ++h) {
-    acc[h][0] = c.q[c.rowq[h]];
-    acc[h][1] = 0.0;
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) r[h][i] = row[h][k + i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v2[i] = *reinterpret_cast<const double2*>(vb + k + 2 * i);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        row[h][k + 2 * i] = fma(ya[h], v2[i].x, r[h][2 * i]);
+        row[h][k + 2 * i + 1] = fma(ya[h], v2[i].y, r[h][2 * i + 1]);
+      }
   }
-  loop4(hwm, [&](int k, int par) {
-    const int ck = max(bcast(scol, k), 0);
-    const double xk = bcast(xs, k);  // zero for free slots
+  for (; k + 4 <= n; k += 4) {
+    double r[H][4];
 #pragma unroll
-    for (int h = 0; h < H; ++h) acc[h][par] = fma(-c.Qv(ck, c.rowq[h]), xk, acc[h][par]);
-  });
+    for (int h = 0; h < H; ++h)
 #pragma unroll
-  for (int h = 0; h < H; ++h) w[h] = acc[h][0] + acc[h][1];
+      for (int i = 0; i < 4; ++i) r[h][i] = row[h][k + i];
+    const double2 v0 = *reinterpret_cast<const double2*>(vb + k);
+    const double2 v1 = *reinterpret_cast<const double2*>(vb + k + 2);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      row[h][k] = fma(ya[h], v0.x, r[h][0]);
+      row[h][k + 1] = fma(ya[h], v0.y, r[h][1]);
+      row[h][k + 2] = fma(ya[h], v1.x, r[h][2]);
+      row[h][k + 3] = fma(ya[h], v1.y, r[h][3]);
+    }
+  }
+  for (; k < n; ++k) {
+    const double vk = vb[k];
+#pragma unroll
+    for (int h = 0; h < H; ++h) row[h][k] = fma(ya[h], vk, row[h][k]);
+  }
 }
 
-// z += B (q_P - Q[P,P] z)
-template <int H, bool QG>
-__device__ __forceinline__ void refine(const Ctx<H, QG>& c, int hwm, const int (&scol)[H],
-                                       double (&z)[H]) {
-  double r[H][2], rr[H], dz[H];
-  int sc[H];
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    sc[h] = max(scol[h], 0);
-    r[h][0] = c.q[sc[h]];
-    r[h][1] = 0.0;
-  }
-  loop4(hwm, [&](int k, int par) {
-    const int ck = max(bcast(scol, k), 0);
-    const double zk = bcast(z, k);  // zero for free slots
-#pragma unroll
-    for (int h = 0; h < H; ++h) r[h][par] = fma(-c.Qv(sc[h], ck), zk, r[h][par]);
-  });
-#pragma unroll
-  for (int h = 0; h < H; ++h) rr[h] = scol[h] < 0 ? 0.0 : r[h][0] + r[h][1];
-  mv_B(c, hwm, rr, dz);
-#pragma unroll
-  for (int h = 0; h < H; ++h) z[h] += dz[h];
-}
+__host__ __device__ inline size_t lh_matrix_words(int d) { return (size_t)(d + 1) * lds_ld(d); }
+__host__ __device__ inline size_t lh_vector_words(int d) { return 2 * kW + 3 * (size_t)d; }
 
 }  // namespace
 
-// LDS bytes for B (and Q when it fits), plus q and x.
-__host__ __device__ static inline int lds_ld(int d) { return d | 1; }
-static bool q_in_lds(int d) {
-  const size_t bq = 2 * (size_t)(d + 1) * lds_ld(d) * sizeof(double) + 2 * (size_t)d * sizeof(double);
-  return bq <= (size_t)kMaxLdsBytes;
+static bool qp_in_lds(int d) {
+  return (2 * lh_matrix_words(d) + lh_vector_words(d)) * sizeof(double) <= kMaxLdsBytes;
 }
+
 size_t lh_lds_bytes(int d) {
-  const size_t b = (size_t)(d + 1) * lds_ld(d) * sizeof(double);
-  return (q_in_lds(d) ? 2 * b : b) + 2 * (size_t)d * sizeof(double);
+  return ((qp_in_lds(d) ? 2 : 1) * lh_matrix_words(d) + lh_vector_words(d)) * sizeof(double);
+}
+
+size_t lh_global_scratch_bytes(int d, int nprob) {
+  return qp_in_lds(d) ? 0 : (size_t)nprob * lh_matrix_words(d) * sizeof(double);
 }
 
 // Problem `prob` reads Q at Qall + prob*d*d (full row-major), q at qall + prob*d,
 // c at cc_all[prob] and the column 1-norms of M at colabs_all + prob*d.
-template <int H, bool QG>
+template <int H, bool QPG>
 __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
     int d, const double* __restrict__ Qall, const double* __restrict__ qall,
     const double* __restrict__ cc_all, const double* __restrict__ colabs_all, int64_t m,
     const int32_t* __restrict__ m_dev, double tol, int max_iter, double* __restrict__ x_out,
     double* __restrict__ w_out, double* __restrict__ rnorm_out, int32_t* __restrict__ iters_out,
-    int32_t* __restrict__ status_out, const int32_t* __restrict__ pre_status) {
-  extern __shared__ double lh_lds[];
+    int32_t* __restrict__ status_out, const int32_t* __restrict__ pre_status,
+    double* __restrict__ qp_global) {
+  extern __shared__ __attribute__((aligned(16))) double lh_lds[];
   const int lane = threadIdx.x;
   const int prob = blockIdx.x;
   const double* Qg = Qall + (int64_t)prob * d * d;
   const double* qg = qall + (int64_t)prob * d;
   const int ld = lds_ld(d);
-  double* Bs = lh_lds;
-  double* Qs = QG ? nullptr : Bs + (d + 1) * ld;
-  double* qs = (QG ? Bs : Qs) + (d + 1) * ld;
-  double* xcol = qs + d;
+  const int mw = (int)lh_matrix_words(d);
+  double* vb = lh_lds;  // broadcast staging, 2*kW
+  double* Bs = vb + 2 * kW;
+  double* QP = QPG ? qp_global + (int64_t)prob * mw : Bs + mw;
+  double* qs = (QPG ? Bs + mw : QP + mw);
+  double* dq = qs + d;
+  double* xcol = dq + d;
 
-  Ctx<H, QG> cx;
-  cx.B = Bs;
-  cx.q = qs;
-  cx.d = d;
-  cx.ldb = ld;
-  cx.Q = QG ? Qg : Qs;
-  cx.ldq = QG ? d : ld;
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    const int s = lane + h * kW;
-    cx.row[h] = s < d ? s : d;
-    cx.rowq[h] = s < d ? s : d - 1;
-  }
-
-  for (int e = lane; e < (d + 1) * ld; e += kW) Bs[e] = 0.0;
-  if (!QG) {
-#pragma unroll 4
-    for (int i = 0; i < d; ++i)
-#pragma unroll
-      for (int h = 0; h < H; ++h)
-        if (lane + h * kW < d) Qs[i * ld + lane + h * kW] = Qg[(int64_t)i * d + lane + h * kW];
+  for (int e = lane; e < mw; e += kW) {
+    Bs[e] = 0.0;
+    QP[e] = 0.0;
   }
   double amax = 0.0;
   for (int j = lane; j < d; j += kW) {
     qs[j] = qg[j];
+    dq[j] = Qg[(int64_t)j * d + j];
     xcol[j] = 0.0;
     amax = fmax(amax, colabs_all[(int64_t)prob * d + j]);
   }
@@ -294,6 +315,18 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
   const int64_t m_eff = m_dev ? (int64_t)m_dev[prob] : m;
   const double tau =
       uni(tol > 0.0 ? tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
+
+  // per-lane rows: B by slot, QP by column (dummy row d when out of range)
+  double* brow[H];
+  const double* qrow[H];
+  bool valid[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int s = lane + h * kW;
+    valid[h] = s < d;
+    brow[h] = Bs + (valid[h] ? s : d) * ld;
+    qrow[h] = QP + (valid[h] ? s : d) * ld;
+  }
   __syncthreads();
 
   // slot-distributed state
@@ -313,44 +346,47 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
   int status = RNNLS_SOLVE_OK;
 
   for (;;) {
-    // ---- outer step
+    // ---- outer step: w = q - QP x_P
     double w[H];
-    dual(cx, hwm, scol, xs, w);
+    stage(vb, xs);
+    mv(qrow, vb, hwm, w);
+#pragma unroll
+    for (int h = 0; h < H; ++h) w[h] = (valid[h] ? qs[lane + h * kW] : 0.0) - w[h];
     bool refused[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) refused[h] = false;
     int t = -1;
-    double u[H], g[H], zt = 0.0, sval = 0.0;
+    double u[H], g[H], qnew[H], zt = 0.0, sval = 0.0, sinv = 0.0;
     for (;;) {
-      double best = -DBL_MAX;
-      int bidx = kNone;
+      bool cand[H];
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int col = lane + h * kW;
-        if (col < d && cslot[h] < 0 && !refused[h] && w[h] > best) {
-          best = w[h];
-          bidx = col;
-        }
-      }
-      wave_arg<true>(best, bidx);
-      bidx = uni(bidx);
-      best = uni(best);
+      for (int h = 0; h < H; ++h) cand[h] = valid[h] && cslot[h] < 0 && !refused[h];
+      double best;
+      const int bidx = uni(wave_arg<true>(w, cand, best));
       if (bidx == kNone || !(best > tau)) break;
-      // candidate: g = Q[P, t], u = B g, Schur complement and coefficient
+      // the entering column of Q (read from global memory now, used when
+      // QP gains it, so its latency overlaps the candidate test)
 #pragma unroll
-      for (int h = 0; h < H; ++h) g[h] = scol[h] >= 0 ? cx.Qv(max(scol[h], 0), bidx) : 0.0;
-      mv_B(cx, hwm, g, u);
-      const double qtt = uni(cx.Qv(bidx, bidx));
+      for (int h = 0; h < H; ++h) qnew[h] = valid[h] ? Qg[(int64_t)bidx * d + lane + h * kW] : 0.0;
+      // candidate: g = Q[P, t] = QP[t][slot], u = B g, Schur complement s,
+      // coefficient z_t
+#pragma unroll
+      for (int h = 0; h < H; ++h) g[h] = valid[h] ? QP[bidx * ld + lane + h * kW] : 0.0;
+      stage(vb, g);
+      const double qtt = uni(dq[bidx]);
+      const double qt = uni(qs[bidx]);
+      mv(brow, vb, hwm, u);
       double gu = 0.0, gx = 0.0;
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         gu += g[h] * u[h];
         gx += g[h] * xs[h];
       }
-      sval = uni(qtt - wave_sum(gu));
-      zt = uni((qs[bidx] - wave_sum(gx)) / sval);
-      const bool ok = (sval > kDependence * qtt) && (zt > 0.0);
-      if (!ok) {
+      wave_sum2(gu, gx);
+      sval = uni(qtt - gu);
+      sinv = uni(1.0 / sval);
+      zt = uni((qt - gx) * sinv);
+      if (!((sval > kDependence * qtt) && (zt > 0.0))) {
 #pragma unroll
         for (int h = 0; h < H; ++h)
           if (lane + h * kW == bidx) refused[h] = true;
@@ -365,23 +401,27 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
       break;
     }
     ++iters;
-    // ---- border B with t in the lowest free slot j
-    const uint64_t free0 = __ballot(scol[0] < 0 && lane < d);
-    const uint64_t free1 = H == 2 ? __ballot(scol[H - 1] < 0 && lane + kW < d) : 0ull;
+    // ---- border B with t in the lowest free slot j; QP gains column t
+    const uint64_t free0 = __ballot(scol[0] < 0 && valid[0]);
+    const uint64_t free1 = H == 2 ? __ballot(scol[H - 1] < 0 && valid[H - 1]) : 0ull;
     const int j = uni(free0 ? __ffsll((unsigned long long)free0) - 1
                             : kW + __ffsll((unsigned long long)free1) - 1);
-    rank1(cx, hwm, u, 1.0 / sval);
-    __syncthreads();
     {
-      const double inv = 1.0 / sval;
+      const double inv = sinv;
+      double ua[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) ua[h] = u[h] * inv;
+      stage(vb, u);  // u is zero on free slots and on slot j
+      rank1(brow, ua, vb, hwm);
+      lh_sync<QPG>();
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int s = lane + h * kW;
-        if (s < d && s != j) {
-          const double v = -u[h] * inv;  // zero for free slots
-          Bs[s * ld + j] = v;
-          Bs[j * ld + s] = v;
+        if (valid[h] && s != j) {
+          Bs[s * ld + j] = -ua[h];
+          Bs[j * ld + s] = -ua[h];
         }
+        if (valid[h]) QP[s * ld + j] = qnew[h];
       }
       if (lane == 0) Bs[j * ld + j] = inv;
     }
@@ -397,7 +437,7 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
     }
     hwm = uni(j + 1 > hwm ? j + 1 : hwm);
     ++np;
-    __syncthreads();
+    lh_sync<QPG>();
     // ---- inner loop
     for (;;) {
       bool allpos = true;
@@ -409,26 +449,20 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
         for (int h = 0; h < H; ++h) xs[h] = z[h];
         break;
       }
-      double ratio = DBL_MAX;
-      int ridx = kNone;
+      double rat[H];
+      bool neg[H];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        const int s = lane + h * kW;
-        if (scol[h] >= 0 && !(z[h] > 0.0)) {
-          const double den = xs[h] - z[h];
-          const double rr = den > 0.0 ? xs[h] / den : 0.0;
-          if (rr < ratio || (rr == ratio && s < ridx)) {
-            ratio = rr;
-            ridx = s;
-          }
-        }
+        neg[h] = scol[h] >= 0 && !(z[h] > 0.0);
+        const double den = xs[h] - z[h];
+        rat[h] = den > 0.0 ? xs[h] / den : 0.0;
       }
-      wave_arg<false>(ratio, ridx);
-      ridx = uni(ridx);
+      double ratio;
+      const int ridx = uni(wave_arg<false>(rat, neg, ratio));
       // non-finite data can leave no valid ratio: then stay put and drop every
       // nonpositive coefficient, so each pass removes at least one index
       const bool stuck = (ridx == kNone);
-      const double alpha = stuck ? 0.0 : uni(ratio);
+      const double alpha = stuck ? 0.0 : ratio;
       bool drop[H];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
@@ -447,22 +481,24 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
                               : kW + __ffsll((unsigned long long)m1) - 1);
         if (jd < kW) m0 &= m0 - 1; else m1 &= m1 - 1;
         // downdate: B <- B - b b^T / b_jj with b = B[:, jd], then clear jd
-        double bvec[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) bvec[h] = Bs[cx.row[h] * ld + jd];
-        const double bjj = bcast(bvec, jd);
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (lane + h * kW == jd || lane + h * kW >= d) bvec[h] = 0.0;
-        __syncthreads();
-        rank1(cx, hwm, bvec, -1.0 / bjj);
-        __syncthreads();
+        const double bjj = uni(Bs[jd * ld + jd]);
+        double bvec[H], ba[H];
 #pragma unroll
         for (int h = 0; h < H; ++h) {
           const int s = lane + h * kW;
-          if (s < d) {
+          bvec[h] = (valid[h] && s != jd) ? brow[h][jd] : 0.0;
+          ba[h] = -bvec[h] / bjj;
+        }
+        stage(vb, bvec);
+        rank1(brow, ba, vb, hwm);
+        lh_sync<QPG>();
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const int s = lane + h * kW;
+          if (valid[h]) {
             Bs[s * ld + jd] = 0.0;
             Bs[jd * ld + s] = 0.0;
+            QP[s * ld + jd] = 0.0;
           }
         }
         const int col = uni(bcast(scol, jd));
@@ -475,20 +511,32 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
           if (lane + h * kW == col) cslot[h] = -1;
         }
         --np;
-        __syncthreads();
+        lh_sync<QPG>();
       }
       while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
       hwm = uni(hwm);
       if (np == 0) break;
-      // z = B q_P, refined
-      double qp[H];
+      // z = B q_P, then z += B (q_P - Q[P,P] z)
+      double qp[H], r[H], dz[H];
+      const double* prow[H];
 #pragma unroll
-      for (int h = 0; h < H; ++h) qp[h] = scol[h] >= 0 ? qs[max(scol[h], 0)] : 0.0;
-      mv_B(cx, hwm, qp, z);
+      for (int h = 0; h < H; ++h) {
+        qp[h] = scol[h] >= 0 ? qs[scol[h]] : 0.0;
+        prow[h] = QP + (scol[h] >= 0 ? scol[h] : d) * ld;
+      }
+      stage(vb, qp);
+      mv(brow, vb, hwm, z);
 #pragma unroll
       for (int h = 0; h < H; ++h)
         if (scol[h] < 0) z[h] = 0.0;
-      refine(cx, hwm, scol, z);
+      stage(vb, z);
+      mv(prow, vb, hwm, r);
+#pragma unroll
+      for (int h = 0; h < H; ++h) r[h] = scol[h] >= 0 ? qp[h] - r[h] : 0.0;
+      stage(vb, r);
+      mv(brow, vb, hwm, dz);
+#pragma unroll
+      for (int h = 0; h < H; ++h) z[h] += dz[h];
     }
   }
 
@@ -496,16 +544,16 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
 #pragma unroll
   for (int h = 0; h < H; ++h)
     if (scol[h] >= 0) xcol[scol[h]] = xs[h];
-  __syncthreads();
   double wf[H];
-  dual(cx, hwm, scol, xs, wf);
+  stage(vb, xs);
+  mv(qrow, vb, hwm, wf);
   bool ok = true;
   double xq = 0.0, xw = 0.0;
 #pragma unroll
   for (int h = 0; h < H; ++h) {
     const int col = lane + h * kW;
-    if (col < d) {
-      const double acc = wf[h];
+    if (valid[h]) {
+      const double acc = qs[col] - wf[h];
       const double xj = xcol[col];
       if (xj < 0.0) ok = false;
       if (xj > 0.0) {
@@ -535,15 +583,14 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
 int launch_lawson_hanson(int d, const double* G, const double* q, const double* cc,
                          const double* colabs, int64_t m, const int32_t* m_dev, double tol,
                          int max_iter, double* x, double* w, double* rnorm, int32_t* iters,
-                         int32_t* status, const int32_t* pre_status, int nprob, hipStream_t s) {
+                         int32_t* status, const int32_t* pre_status, int nprob,
+                         double* global_scratch, hipStream_t s) {
   const size_t lds = lh_lds_bytes(d);
-  const void* fn;
-  if (d <= kW)
-    fn = (const void*)lawson_hanson_kernel<1, false>;
-  else if (q_in_lds(d))
-    fn = (const void*)lawson_hanson_kernel<2, false>;
-  else
-    fn = (const void*)lawson_hanson_kernel<2, true>;
+  const bool qpg = !qp_in_lds(d);
+  if (qpg && !global_scratch) return RNNLS_E_WORKSPACE;
+  const void* fn = d <= kW ? (const void*)lawson_hanson_kernel<1, false>
+                   : !qpg  ? (const void*)lawson_hanson_kernel<2, false>
+                           : (const void*)lawson_hanson_kernel<2, true>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess)
     return RNNLS_E_HIP;
@@ -552,15 +599,15 @@ int launch_lawson_hanson(int d, const double* G, const double* q, const double* 
   if (d <= kW)
     hipLaunchKernelGGL((lawson_hanson_kernel<1, false>), dim3(nprob), dim3(kW), lds, s, d, G, q,
                        cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status);
-  else if (q_in_lds(d))
+                       pre_status, global_scratch);
+  else if (!qpg)
     hipLaunchKernelGGL((lawson_hanson_kernel<2, false>), dim3(nprob), dim3(kW), lds, s, d, G, q,
                        cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status);
+                       pre_status, global_scratch);
   else
     hipLaunchKernelGGL((lawson_hanson_kernel<2, true>), dim3(nprob), dim3(kW), lds, s, d, G, q,
                        cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status);
+                       pre_status, global_scratch);
   timer_end(RNNLS_TIMER_SOLVE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
