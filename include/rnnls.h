@@ -176,6 +176,22 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
                     int32_t* r_out, const rnnls_opts* opts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ---- launch tuning ------------------------------------------------------
+ * Process-wide launch shape of the sketch kernel (all fields 0 = automatic).
+ *  srht_log_tile   log2 of the rows one workgroup transforms at a time:
+ *                  12..15 (capped at log2 n'); workgroups have 2^(tile-5) threads
+ *  srht_wgs_per_cu persistent workgroups per compute unit, 1..16
+ * Returns RNNLS_OK or -(1-based field number) for an invalid field; NULL
+ * restores the automatic choice.  Not synchronised with calls in flight on
+ * other host threads. */
+typedef struct rnnls_tuning {
+  int32_t srht_log_tile;
+  int32_t srht_wgs_per_cu;
+} rnnls_tuning;
+
+int rnnls_set_tuning(const rnnls_tuning* tuning);
+int rnnls_get_tuning(rnnls_tuning* tuning);
+
 /* ---- kernel timing ------------------------------------------------------
  * Off by default.  When on, the library brackets every launch of the timed
  * kernels with two HIP events recorded on the launch stream (no extra

@@ -134,11 +134,12 @@ int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n
 
 int sketch_core(const Sizes& z, const Opts& o, uint64_t seed, const float* A, int64_t lda,
                 const float* b, float* SA, int64_t ldsa, float* Sb, int32_t* rows,
-                int32_t* count, uint32_t* signs, int32_t* status, uint32_t* stream_scratch,
+                int32_t* count, uint32_t* signs, uint32_t* sign_export, int32_t* status,
+                uint32_t* stream_scratch,
                 float* partials, hipStream_t s) {
   const int m = ilog2_exact((uint64_t)z.n_pad);
-  int rc = launch_streams(seed, m, z.r, z.r_cap, o.sample_mode, signs, rows, count, status,
-                          stream_scratch, s);
+  int rc = launch_streams(seed, m, z.r, z.r_cap, o.sample_mode, z.sp.log_t, signs, sign_export,
+                          rows, count, status, stream_scratch, s);
   if (rc) return rc;
   const double inv_sqrt_r = 1.0 / sqrt((double)z.r);
   return launch_srht(z.sp, A, lda, b, signs, rows, count, 0.0f, partials, SA, ldsa, Sb, z.d,
@@ -147,6 +148,15 @@ int sketch_core(const Sizes& z, const Opts& o, uint64_t seed, const float* A, in
 
 bool ws_ok(void* ws, size_t ws_bytes, size_t need) {
   return need == 0 || (ws != nullptr && ((uintptr_t)ws % 256) == 0 && ws_bytes >= need);
+}
+
+// A sketch workspace serves calls with and without b.
+size_t sketch_ws_need(Sizes z, const Opts& o, int64_t n, int cus) {
+  z.sp = srht_plan(n, z.d + 1, z.r_cap, cus);
+  const size_t with_b = layout_sketch(z, o, false, true).total;
+  z.sp = srht_plan(n, z.d, z.r_cap, cus);
+  const size_t without_b = layout_sketch(z, o, false, false).total;
+  return with_b > without_b ? with_b : without_b;
 }
 
 template <class T>
@@ -165,6 +175,10 @@ int rnnls_version(void) { return 10000; }
 
 int rnnls_device_cus(void) { return device_cus(); }
 
+int rnnls_set_tuning(const rnnls_tuning* tuning) { return set_tuning(tuning); }
+
+int rnnls_get_tuning(rnnls_tuning* tuning) { return get_tuning(tuning); }
+
 size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
                              const rnnls_opts* opts) {
   const Opts o = read_opts(opts);
@@ -179,9 +193,12 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
   }
   if (op != RNNLS_OP_SKETCH && op != RNNLS_OP_RAND_NNLS) return 0;
   if (check_sketch_sizes(n, d, r, o, 1, 2, 3, 4, &z)) return 0;
-  z.sp = srht_plan(n, d + 1, z.r_cap, cus);
   z.mp = moments_plan(z.r_cap, d, cus);
-  return layout_sketch(z, o, op == RNNLS_OP_RAND_NNLS, true).total;
+  if (op == RNNLS_OP_RAND_NNLS) {
+    z.sp = srht_plan(n, d + 1, z.r_cap, cus);
+    return layout_sketch(z, o, true, true).total;
+  }
+  return sketch_ws_need(z, o, n, cus);
 }
 
 int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A,
@@ -200,18 +217,14 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed, const floa
   if (b && !Sb) return -10;
   const int cus = device_cus();
   if (cus < 0) return cus;
+  if (!ws_ok(ws, ws_bytes, sketch_ws_need(z, o, n, cus))) return RNNLS_E_WORKSPACE;
   z.sp = srht_plan(n, d + (b ? 1 : 0), z.r_cap, cus);
-  // the workspace query sizes for b present; that bound also covers b == NULL
-  Sizes zq = z;
-  zq.sp = srht_plan(n, d + 1, z.r_cap, cus);
-  const Layout Lq = layout_sketch(zq, o, false, true);
-  if (!ws_ok(ws, ws_bytes, Lq.total)) return RNNLS_E_WORKSPACE;
   const Layout L = layout_sketch(z, o, false, b != nullptr);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return sketch_core(z, o, seed, A, lda, b, SA, ldsa, Sb,
                      rows ? rows : at<int32_t>(ws, L.rows),
                      r_out ? r_out : at<int32_t>(ws, L.count),
-                     sign_bits ? sign_bits : at<uint32_t>(ws, L.signs),
+                     at<uint32_t>(ws, L.signs), sign_bits,
                      status ? status : at<int32_t>(ws, L.status), at<uint32_t>(ws, L.bern),
                      at<float>(ws, L.partials), s);
 }
@@ -274,7 +287,7 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   int32_t* cnt = r_out ? r_out : at<int32_t>(ws, L.count);
   int32_t* st = status ? status : at<int32_t>(ws, L.status);
   rc = sketch_core(z, o, seed, A, lda, b, sa, ld, sb, rows ? rows : at<int32_t>(ws, L.rows), cnt,
-                   at<uint32_t>(ws, L.signs), st, at<uint32_t>(ws, L.bern),
+                   at<uint32_t>(ws, L.signs), nullptr, st, at<uint32_t>(ws, L.bern),
                    at<float>(ws, L.partials), s);
   if (rc) return rc;
   double* G = at<double>(ws, L.G);

@@ -71,14 +71,18 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- launchers
 // Each returns RNNLS_OK or RNNLS_E_HIP.  Pointers are device memory.
 
-// Signs and kept rows for n' = 2^m.  sign_words: bit (j % 32) of word j / 32
-// set iff D_jj = -1.  rows: kept rows ascending (at most r_cap written);
-// *count = kept rows (clamped to r_cap); *status = RNNLS_SOLVE_OK, _NO_ROWS or
-// _OVERFLOW.  scratch holds streams_scratch_words(n') uint32.
+// Signs and kept rows for n' = 2^m.  sign_words (n'/32 words): with
+// sign_log_t = 0 bit (j % 32) of word j / 32 is set iff D_jj = -1; with
+// sign_log_t = tau > 0 the words follow the sketch kernel's tile-major order
+// (word tile*(T/32) + tid, bit 4k+e = row tile*T + k*T/8 + 4*tid + e).
+// sign_export (nullable) receives the natural layout.  rows: kept rows
+// ascending (at most r_cap written); *count = kept rows (clamped to r_cap);
+// *status = RNNLS_SOLVE_OK, _NO_ROWS or _OVERFLOW.  scratch holds
+// streams_scratch_words(n') uint32.
 size_t streams_scratch_words(int64_t n_pad);
-int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode,
-                   uint32_t* sign_words, int32_t* rows, int32_t* count, int32_t* status,
-                   uint32_t* scratch, hipStream_t s);
+int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode, int sign_log_t,
+                   uint32_t* sign_words, uint32_t* sign_export, int32_t* rows, int32_t* count,
+                   int32_t* status, uint32_t* scratch, hipStream_t s);
 
 // The sketch transform (steps 1-4).  Partial sums go to `partials`; sizes
 // come from srht_plan.
@@ -86,13 +90,16 @@ struct SrhtPlan {
   int64_t n, n_pad;
   int ncols;        // d + (b != nullptr)
   int log_t;        // tile size T = 2^log_t (0: direct kernel for small n')
-  int64_t tiles;    // n_pad / T per column
-  int grid;         // persistent workgroups
-  int pieces;       // partial slots per column
+  int64_t tiles;    // tiles per column fully inside A (n / T)
+  int rag;          // 1 if a tile straddles row n
+  int grid;         // persistent workgroups of the main launch
+  int pieces;       // partial slots per column (main launch + rag)
   int spt;          // samples per thread
   int r_cap;
 };
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus);
+int set_tuning(const rnnls_tuning* t);
+int get_tuning(rnnls_tuning* t);
 size_t srht_partials_bytes(const SrhtPlan& p);
 int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
                 const uint32_t* sign_words, const int32_t* rows, const int32_t* count,

@@ -19,12 +19,19 @@
 // LDS is padded by 4 words every 128 words so that the pass-2 gathers (stride
 // 4 words across 32 elements, 128 words across lanes) hit distinct banks.
 //
+// Tiles entirely past row n hold zeros and are skipped.  Tiles fully inside A
+// go through the main launch (unguarded 16-byte loads); the one tile per
+// column that straddles row n (if n is not a multiple of T) goes through a
+// second, guarded launch with its own partial slot.
+//
 // Scheduling: the (column, tile) items of all columns form one sequence,
 // split into `grid` contiguous ranges of nearly equal length; workgroup w walks
 // its range in order, carrying the per-row sums while consecutive tiles belong
 // to the same column and writing one partial vector per (column, workgroup)
 // touch.  A second kernel adds the partials of each column in a fixed order
 // (deterministic: no atomics) and applies the 1/sqrt(r) scale.
+#include <atomic>
+
 #include "common.h"
 
 namespace rnnls {
@@ -66,10 +73,12 @@ struct TiledArgs {
   const float* b;
   int d;           // columns of A; column index d means b
   int64_t n;       // true rows (rows >= n read as zero)
-  int64_t tiles;   // tiles per column
+  int64_t tiles;   // tiles per column in this launch
+  int64_t tile0;   // global index of this launch's first tile
   int64_t items;   // ncols * tiles
   int64_t grid;
-  int pieces;
+  int pieces;      // partial slots per column (all launches)
+  int piece0;      // first slot of this launch
   int r_cap;
   const uint32_t* sign_words;
   const int32_t* rows;
@@ -77,32 +86,39 @@ struct TiledArgs {
   float* partials;  // [ncols][pieces][r_cap]
 };
 
-template <int LOG_T, bool VEC>
+template <int LOG_T, bool GUARD>
 __device__ __forceinline__ void load_tile(const TiledArgs& a, int col, int64_t tile,
-                                          float (&v)[kRegs], uint32_t (&sw)[8]) {
+                                          float (&v)[kRegs], uint32_t& sw) {
   constexpr int T = 1 << LOG_T;
   const int tid = threadIdx.x;
-  const float* src = (col < a.d) ? a.A + (int64_t)col * a.lda : a.b;
-  const int64_t row0 = tile * T + 4 * tid;
-  const bool full = (tile + 1) * T <= a.n;
+  // wave-uniform 64-bit bases; per-lane offsets stay 32-bit
+  const float* base = ((col < a.d) ? a.A + (int64_t)col * a.lda : a.b) + tile * T;
+  const int64_t rem = a.n - tile * T;
+  const int lim = rem < T ? (int)rem : T;  // rows of this tile inside A
+  // tile-major signs: bit 4k+e belongs to v[4k+e]
+  sw = (a.sign_words + tile * (T / kRegs))[(uint32_t)tid];
+  if (!GUARD) {  // whole tile inside A, 16-byte aligned: 8 vector loads back to back
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t r = row0 + (int64_t)k * (T / 8);
-    sw[k] = a.sign_words[r >> 5];
-    if (VEC && full) {
-      const float4 q = *reinterpret_cast<const float4*>(src + r);
+    for (int k = 0; k < 8; ++k) {
+      // unsigned 32-bit offsets from a scalar base (no 64-bit lane arithmetic)
+      const uint32_t off = 4u * (uint32_t)tid + (uint32_t)(k * (T / 8));
+      const float4 q = *reinterpret_cast<const float4*>(base + off);
       v[4 * k + 0] = q.x;
       v[4 * k + 1] = q.y;
       v[4 * k + 2] = q.z;
       v[4 * k + 3] = q.w;
-    } else {
+    }
+  } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * k + e] = (r + e < a.n) ? src[r + e] : 0.0f;
+    for (int k = 0; k < 8; ++k) {
+      const int off = 4 * tid + k * (T / 8);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * k + e] = (off + e < lim) ? base[off + e] : 0.0f;
     }
   }
 }
 
-template <int LOG_T, int SPT, bool VEC>
+template <int LOG_T, int SPT, bool GUARD>
 __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledArgs a) {
   constexpr int T = 1 << LOG_T;
   constexpr int NT = T / kRegs;
@@ -125,24 +141,19 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
   }
 
   float v[kRegs];
-  uint32_t sw[8];
+  uint32_t sw;
   int64_t item = item_begin;
   int col = (int)(item / a.tiles);
-  int64_t tile = item % a.tiles;
-  load_tile<LOG_T, VEC>(a, col, tile, v, sw);
+  int64_t tile = a.tile0 + item % a.tiles;
+  load_tile<LOG_T, GUARD>(a, col, tile, v, sw);
 
-  const int nib_shift = 4 * (tid & 7);
   const int p2_base = (tid & 3) + ((tid >> 2) << 7) + ((tid >> 2) << 2);
   const int p3_base = (tid & 127) + (tid >> 7) * (4096 + 128);
 
   while (item < item_end) {
     // step 4 of Algorithm 1: the sign flip, fused into the load
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t nib = sw[k] >> nib_shift;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * k + e] = flip(v[4 * k + e], (nib >> e) & 1u);
-    }
+    for (int e = 0; e < kRegs; ++e) v[e] = flip(v[e], (sw >> e) & 1u);
     // pass 1: bits {0,1} (within a float4) and {tau-3..tau-1} (the 8 loads)
     fwht_regs<31>(v);
 #pragma unroll
@@ -156,8 +167,8 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
     const int64_t cur_tile = tile;
     if (next < item_end) {
       col = (int)(next / a.tiles);
-      tile = next % a.tiles;
-      load_tile<LOG_T, VEC>(a, col, tile, v, sw);
+      tile = a.tile0 + next % a.tiles;
+      load_tile<LOG_T, GUARD>(a, col, tile, v, sw);
     }
     __syncthreads();
     {  // pass 2: bits 2..6
@@ -190,7 +201,7 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
     const bool last_of_col = (next >= item_end) || (col != cur_col);
     if (last_of_col) {
       const int64_t first_owner = owner_of((int64_t)cur_col * a.tiles, a.items, a.grid);
-      const int piece = (int)(w - first_owner);
+      const int piece = a.piece0 + (int)(w - first_owner);
       float* dst = a.partials + ((int64_t)cur_col * a.pieces + piece) * a.r_cap;
 #pragma unroll
       for (int s = 0; s < SPT; ++s) {
@@ -204,19 +215,24 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
 }
 
 // Fixed-order sum of the per-workgroup partials of each column, times 1/sqrt r.
+// Slots 0.. hold the main launch's pieces of the column (if it has full
+// tiles), slot `rag_slot` (>= 0) the straddling tile.
 __global__ void srht_reduce_kernel(const float* __restrict__ partials, int pieces, int r_cap,
-                                   int64_t tiles, int64_t items, int64_t grid,
+                                   int64_t tiles, int64_t items, int64_t grid, int rag_slot,
                                    const int32_t* __restrict__ count, int d,
                                    double inv_sqrt_r, float* __restrict__ SA, int64_t ldsa,
                                    float* __restrict__ Sb) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int col = blockIdx.y;
   if (l >= *count) return;
-  const int64_t w0 = owner_of((int64_t)col * tiles, items, grid);
-  const int64_t w1 = owner_of((int64_t)col * tiles + tiles - 1, items, grid);
   const float* p = partials + (int64_t)col * pieces * r_cap + l;
   float s = 0.0f;
-  for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * r_cap];
+  if (tiles > 0) {
+    const int64_t w0 = owner_of((int64_t)col * tiles, items, grid);
+    const int64_t w1 = owner_of((int64_t)col * tiles + tiles - 1, items, grid);
+    for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * r_cap];
+  }
+  if (rag_slot >= 0) s += p[(int64_t)rag_slot * r_cap];
   const float y = (float)((double)s * inv_sqrt_r);
   if (col < d)
     SA[(int64_t)col * ldsa + l] = y;
@@ -250,24 +266,34 @@ __global__ void srht_direct_kernel(const float* __restrict__ A, int64_t lda,
 }
 
 template <int LOG_T, int SPT>
-int launch_tiled_t(const SrhtPlan& p, const TiledArgs& a, bool vec, hipStream_t s) {
+int launch_tiled_t(const TiledArgs& a, bool guard, hipStream_t s) {
   constexpr int NT = (1 << LOG_T) / kRegs;
-  if (vec)
-    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, true>), dim3(p.grid), dim3(NT), 0, s, a);
+  if (!guard)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, false>), dim3(a.grid), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, false>), dim3(p.grid), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, true>), dim3(a.grid), dim3(NT), 0, s, a);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
 template <int LOG_T>
-int launch_tiled_spt(const SrhtPlan& p, const TiledArgs& a, bool vec, hipStream_t s) {
-  switch (p.spt) {
-    case 1: return launch_tiled_t<LOG_T, 1>(p, a, vec, s);
-    case 2: return launch_tiled_t<LOG_T, 2>(p, a, vec, s);
-    case 4: return launch_tiled_t<LOG_T, 4>(p, a, vec, s);
-    case 8: return launch_tiled_t<LOG_T, 8>(p, a, vec, s);
-    case 16: return launch_tiled_t<LOG_T, 16>(p, a, vec, s);
-    case 32: return launch_tiled_t<LOG_T, 32>(p, a, vec, s);
+int launch_tiled_spt(int spt, const TiledArgs& a, bool guard, hipStream_t s) {
+  switch (spt) {
+    case 1: return launch_tiled_t<LOG_T, 1>(a, guard, s);
+    case 2: return launch_tiled_t<LOG_T, 2>(a, guard, s);
+    case 4: return launch_tiled_t<LOG_T, 4>(a, guard, s);
+    case 8: return launch_tiled_t<LOG_T, 8>(a, guard, s);
+    case 16: return launch_tiled_t<LOG_T, 16>(a, guard, s);
+    case 32: return launch_tiled_t<LOG_T, 32>(a, guard, s);
+    default: return RNNLS_E_UNSUPPORTED;
+  }
+}
+
+int launch_tiled(int log_t, int spt, const TiledArgs& a, bool guard, hipStream_t s) {
+  switch (log_t) {
+    case 12: return launch_tiled_spt<12>(spt, a, guard, s);
+    case 13: return launch_tiled_spt<13>(spt, a, guard, s);
+    case 14: return launch_tiled_spt<14>(spt, a, guard, s);
+    case 15: return launch_tiled_spt<15>(spt, a, guard, s);
     default: return RNNLS_E_UNSUPPORTED;
   }
 }
@@ -281,7 +307,35 @@ int wgs_per_cu(int log_t) {
   }
 }
 
+std::atomic<int> g_log_tile{0}, g_wgs_per_cu{0};
+
+rnnls_tuning current_tuning() {
+  rnnls_tuning t;
+  t.srht_log_tile = g_log_tile.load();
+  t.srht_wgs_per_cu = g_wgs_per_cu.load();
+  return t;
+}
+
 }  // namespace
+
+int set_tuning(const rnnls_tuning* t) {
+  if (!t) {
+    g_log_tile = 0;
+    g_wgs_per_cu = 0;
+    return RNNLS_OK;
+  }
+  if (t->srht_log_tile != 0 && (t->srht_log_tile < 12 || t->srht_log_tile > 15)) return -1;
+  if (t->srht_wgs_per_cu < 0 || t->srht_wgs_per_cu > 16) return -2;
+  g_log_tile = t->srht_log_tile;
+  g_wgs_per_cu = t->srht_wgs_per_cu;
+  return RNNLS_OK;
+}
+
+int get_tuning(rnnls_tuning* t) {
+  if (!t) return -1;
+  *t = current_tuning();
+  return RNNLS_OK;
+}
 
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   SrhtPlan p{};
@@ -294,24 +348,30 @@ SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
     p.log_t = 0;
     return p;
   }
-  p.log_t = m < 15 ? m : 15;
-  const int nt = (1 << p.log_t) / kRegs;
+  const rnnls_tuning tune = current_tuning();
+  p.log_t = tune.srht_log_tile > 0 ? tune.srht_log_tile : 15;
+  if (p.log_t > m) p.log_t = m;
   int spt = 1;
+  // at most 32 kept rows per thread: widen the tile when r needs it
+  while (((1 << p.log_t) / kRegs) * 32 < r_cap && p.log_t < 15 && p.log_t < m) ++p.log_t;
+  const int nt = (1 << p.log_t) / kRegs;
   while (spt * nt < r_cap) spt <<= 1;
   p.spt = spt;
-  p.tiles = p.n_pad >> p.log_t;
+  p.tiles = n >> p.log_t;                       // full tiles per column
+  p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;  // one straddling tile
   const int64_t items = (int64_t)ncols * p.tiles;
-  const int64_t cap = (int64_t)cus * wgs_per_cu(p.log_t);
+  const int per_cu = tune.srht_wgs_per_cu > 0 ? tune.srht_wgs_per_cu : wgs_per_cu(p.log_t);
+  const int64_t cap = (int64_t)cus * per_cu;
   p.grid = (int)(items < cap ? items : cap);
-  // most workgroups touching one column
+  // most workgroups of the main launch touching one column
   int pieces = 0;
-  for (int c = 0; c < ncols; ++c) {
+  for (int c = 0; c < ncols && items > 0; ++c) {
     const int64_t w0 = owner_of((int64_t)c * p.tiles, items, p.grid);
     const int64_t w1 = owner_of((int64_t)c * p.tiles + p.tiles - 1, items, p.grid);
     const int k = (int)(w1 - w0 + 1);
     if (k > pieces) pieces = k;
   }
-  p.pieces = pieces;
+  p.pieces = pieces + p.rag;
   return p;
 }
 
@@ -340,9 +400,6 @@ int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
   a.b = b;
   a.d = d;
   a.n = p.n;
-  a.tiles = p.tiles;
-  a.items = (int64_t)p.ncols * p.tiles;
-  a.grid = p.grid;
   a.pieces = p.pieces;
   a.r_cap = p.r_cap;
   a.sign_words = sign_words;
@@ -351,19 +408,30 @@ int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
   a.partials = partials;
   const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
                    (b == nullptr || (uintptr_t)b % 16 == 0);
-  int rc;
+  int rc = RNNLS_OK;
   timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
-  switch (p.log_t) {
-    case 12: rc = launch_tiled_spt<12>(p, a, vec, s); break;
-    case 13: rc = launch_tiled_spt<13>(p, a, vec, s); break;
-    case 14: rc = launch_tiled_spt<14>(p, a, vec, s); break;
-    case 15: rc = launch_tiled_spt<15>(p, a, vec, s); break;
-    default: rc = RNNLS_E_UNSUPPORTED;
+  if (p.tiles > 0) {  // tiles fully inside A
+    a.tiles = p.tiles;
+    a.tile0 = 0;
+    a.items = (int64_t)p.ncols * p.tiles;
+    a.grid = p.grid;
+    a.piece0 = 0;
+    rc = launch_tiled(p.log_t, p.spt, a, !vec, s);
+  }
+  if (rc == RNNLS_OK && p.rag) {  // the tile straddling row n, one per column
+    a.tiles = 1;
+    a.tile0 = p.tiles;
+    a.items = p.ncols;
+    a.grid = p.ncols;
+    a.piece0 = p.pieces - 1;
+    rc = launch_tiled(p.log_t, p.spt, a, true, s);
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
+  const int64_t main_items = (int64_t)p.ncols * p.tiles;
   hipLaunchKernelGGL(srht_reduce_kernel, rgrid, dim3(threads), 0, s, partials, p.pieces,
-                     p.r_cap, p.tiles, a.items, a.grid, count, d, inv_sqrt_r, SA, ldsa, Sb);
+                     p.r_cap, p.tiles, main_items, (int64_t)p.grid, p.rag ? p.pieces - 1 : -1,
+                     count, d, inv_sqrt_r, SA, ldsa, Sb);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

@@ -65,7 +65,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
 
 // signs + kept mask + per-block kept counts
 __global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(
-    KeepRule rule, uint64_t sign_key, int64_t n_pad, uint32_t* __restrict__ sign_words,
+    KeepRule rule, uint64_t sign_key, int64_t n_pad, int sign_log_t,
+    uint32_t* __restrict__ sign_words,
     uint32_t* __restrict__ kept_words, uint32_t* __restrict__ block_counts) {
   const int64_t w = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t nwords = (n_pad + 31) / 32;
@@ -75,10 +76,22 @@ __global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(
 #pragma unroll 4
     for (int k = 0; k < 32; ++k) {
       const uint64_t j = base + (uint64_t)k;
-      if ((int64_t)j < n_pad) {
-        sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << k;
-        if (kept(rule, (uint32_t)j)) kbits |= 1u << k;
-      }
+      if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << k;
+    }
+    // sign word w: natural layout (rows 32w..32w+31), or the tile-major
+    // layout of the sketch kernel: w = tile * (T/32) + tid, bit 4k+e holding
+    // row tile*T + k*(T/8) + 4*tid + e
+    uint64_t first = base;
+    int kstride = 4;
+    if (sign_log_t > 0) {
+      const int64_t nt = (1ll << sign_log_t) >> 5;
+      first = ((uint64_t)(w / nt) << sign_log_t) + 4ull * (uint64_t)(w % nt);
+      kstride = (int)((1ll << sign_log_t) >> 3);
+    }
+#pragma unroll 4
+    for (int b = 0; b < 32; ++b) {
+      const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
+      if ((int64_t)j < n_pad) sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
     }
     sign_words[w] = sbits;
     kept_words[w] = kbits;
@@ -129,6 +142,20 @@ __global__ __launch_bounds__(kThreads) void streams_write_rows_kernel(
   }
 }
 
+// Natural-layout sign words (bit j % 32 of word j / 32), for export.
+__global__ __launch_bounds__(kThreads) void sign_words_natural_kernel(
+    uint64_t sign_key, int64_t n_pad, uint32_t* __restrict__ words) {
+  const int64_t w = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (w >= (n_pad + 31) / 32) return;
+  uint32_t bits = 0;
+#pragma unroll 4
+  for (int k = 0; k < 32; ++k) {
+    const int64_t j = w * 32 + k;
+    if (j < n_pad) bits |= (uint32_t)(mix64(sign_key + (uint64_t)j) >> 63) << k;
+  }
+  words[w] = bits;
+}
+
 uint32_t inverse_odd(uint32_t a) {
   uint32_t x = a;  // Newton iteration for a^{-1} mod 2^32 (a odd)
   for (int i = 0; i < 5; ++i) x *= 2u - a * x;
@@ -143,9 +170,9 @@ size_t streams_scratch_words(int64_t n_pad) {
   return (size_t)(nwords + 2 * nblocks + 2);
 }
 
-int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode,
-                   uint32_t* sign_words, int32_t* rows, int32_t* count, int32_t* status,
-                   uint32_t* scratch, hipStream_t s) {
+int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode, int sign_log_t,
+                   uint32_t* sign_words, uint32_t* sign_export, int32_t* rows, int32_t* count,
+                   int32_t* status, uint32_t* scratch, hipStream_t s) {
   const int64_t n_pad = 1ll << m;
   const int64_t nwords = (n_pad + 31) / 32;
   const int64_t nblocks = (n_pad + kRowsPerBlock - 1) / kRowsPerBlock;
@@ -168,7 +195,11 @@ int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode,
   uint32_t* counts = scratch + nwords;
   uint32_t* offsets = counts + nblocks;
   hipLaunchKernelGGL(streams_scan_rows_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, s,
-                     rule, stream_key(seed, kStreamSign), n_pad, sign_words, kept_words, counts);
+                     rule, stream_key(seed, kStreamSign), n_pad, sign_log_t, sign_words, kept_words,
+                     counts);
+  if (sign_export && sign_export != sign_words)
+    hipLaunchKernelGGL(sign_words_natural_kernel, dim3((unsigned)((nwords + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, stream_key(seed, kStreamSign), n_pad, sign_export);
   hipLaunchKernelGGL(streams_offsets_kernel, dim3(1), dim3(kThreads), 0, s, nblocks, counts,
                      offsets, r_cap, count, status);
   hipLaunchKernelGGL(streams_write_rows_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, s,

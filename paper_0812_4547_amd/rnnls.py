@@ -27,6 +27,7 @@ MAX_D, MAX_R = 128, 32768
 EXPORTS = (
     "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
     "rnnls_nnls_solve", "rnnls_rand_nnls", "rnnls_timing_enable", "rnnls_timing_read",
+    "rnnls_set_tuning", "rnnls_get_tuning",
 )
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE = 0, 1, 2
 
@@ -35,6 +36,10 @@ class Opts(ctypes.Structure):
     _fields_ = [("sample_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("r_cap", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("srht_log_tile", ctypes.c_int32), ("srht_wgs_per_cu", ctypes.c_int32)]
 
 
 class RnnlsError(RuntimeError):
@@ -57,6 +62,8 @@ _SIGS = {
                          _p, _p, _p, _sz, _p], ctypes.c_int),
     "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
+    "rnnls_set_tuning": ([_p], ctypes.c_int),
+    "rnnls_get_tuning": ([_p], ctypes.c_int),
 }
 
 
@@ -240,3 +247,15 @@ def timing_read(which: int) -> tuple[float, int]:
     k = ctypes.c_int64(0)
     _check(load().rnnls_timing_read(which, ctypes.byref(ms), ctypes.byref(k)), "rnnls_timing_read")
     return ms.value, k.value
+
+
+def set_tuning(srht_log_tile: int = 0, srht_wgs_per_cu: int = 0) -> None:
+    """Launch shape of the sketch kernel (0 = automatic), process-wide."""
+    t = Tuning(int(srht_log_tile), int(srht_wgs_per_cu))
+    _check(load().rnnls_set_tuning(ctypes.byref(t)), "rnnls_set_tuning")
+
+
+def get_tuning() -> tuple[int, int]:
+    t = Tuning()
+    _check(load().rnnls_get_tuning(ctypes.byref(t)), "rnnls_get_tuning")
+    return t.srht_log_tile, t.srht_wgs_per_cu
