@@ -150,8 +150,9 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed,
  *  iters       output int32[1]: outer iterations; may be NULL
  *  status      output int32[1]: RNNLS_SOLVE_*; may be NULL
  * The solve runs in FP64: the Gram matrix M^T M and M^T f are accumulated in
- * FP64 from the FP32 inputs (products are exact), the passive-set systems are
- * solved by an updated Cholesky factor.
+ * FP64 from the FP32 inputs (products are exact); the passive-set systems are
+ * solved through an inverse of Q[P,P] updated as columns enter and leave,
+ * with a step of iterative refinement after every removal.
  */
 int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm,
                      const float* f, const int32_t* m_dev,
@@ -176,6 +177,91 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
                     int32_t* r_out, const rnnls_opts* opts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ---- many right-hand sides sharing one A -------------------------------
+ * rnnls_rand_nnls_multi -- Algorithm 1 for the k problems min ||A x_j - b_j||,
+ * x_j >= 0, j < k, that share A (the extension Section 5 names, e.g. the
+ * alternating updates of a nonnegative matrix factorisation).  One sketch
+ * [SA | SB] = (1/sqrt r) (H_n' D [A | B])[rows, :] with the same D and rows
+ * for all columns, one Gram matrix G = SA^T SA, then k Lawson-Hanson solves
+ * sharing G.
+ *
+ *  n, d, r, seed, A, lda   as rnnls_rand_nnls
+ *  k           right-hand sides, 1 <= k <= RNNLS_MAX_K
+ *  B, ldb      input, column-major n x k, ldb >= n
+ *  X, ldx      output, column-major d x k (FP64), ldx >= d
+ *  rnorm       output double[k] (sketched residuals); may be NULL
+ *  iters, status  output int32[k]; may be NULL
+ * Workspace: rnnls_multi_workspace_bytes(n, d, k, r, opts).
+ */
+#define RNNLS_MAX_K 4096
+
+size_t rnnls_multi_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t r,
+                                   const rnnls_opts* opts);
+int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t seed,
+                          const float* A, int64_t lda, const float* B, int64_t ldb,
+                          double* X, int64_t ldx, double* rnorm, int32_t* iters,
+                          int32_t* status, const rnnls_opts* opts,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* ---- batches of independent problems ----------------------------------
+ * A batch plan runs Algorithm 1 on `count` independent problems of different
+ * sizes with a fixed number of fused launches (random streams, sketch per
+ * tile-size group, reduce, moments, Lawson-Hanson), whatever the count.
+ *
+ * rnnls_problem: one problem; sizes and limits as rnnls_rand_nnls (A, b and x
+ * required, rnorm, iters, status may be NULL).  All pointers are device
+ * memory and must stay valid, with the same addresses, for the plan's life.
+ *
+ * rnnls_batch_workspace_bytes  workspace for rnnls_batch_create (covers every
+ *              tile shape rnnls_batch_autotune tries); 0 for invalid input.
+ * rnnls_batch_create  validates the problems (returns -3 if one is invalid;
+ *              *bad_index, if not NULL, receives its index), plans the
+ *              launches and binds `ws` (device, 256-byte aligned, caller
+ *              owned, kept until destroy).  Allocates the plan's device-side
+ *              descriptor tables (hipMalloc) and uploads them synchronously.
+ * rnnls_batch_run     enqueues one pass over all problems on `stream`.
+ * rnnls_batch_autotune  times every candidate tile shape of the sketch on
+ *              the plan's own problems (synchronising `stream`), keeps the
+ *              fastest for this plan and reports it in *chosen (may be NULL).
+ * rnnls_batch_capture records one pass into a HIP graph held by the plan
+ *              (replaced by a later capture, dropped by autotune).
+ * rnnls_batch_launch  replays the captured graph on `stream`
+ *              (RNNLS_E_UNSUPPORTED if nothing was captured).
+ * rnnls_batch_destroy waits for the device, frees the plan and its graph.
+ * Calls on one plan must not overlap (they share the workspace).
+ */
+typedef struct rnnls_tuning {
+  int32_t srht_log_tile;
+  int32_t srht_wgs_per_cu;
+} rnnls_tuning;
+
+typedef struct rnnls_problem {
+  int64_t n;
+  int32_t d;
+  int32_t r;
+  uint64_t seed;
+  const float* A;
+  int64_t lda;
+  const float* b;
+  double* x;
+  double* rnorm;
+  int32_t* iters;
+  int32_t* status;
+} rnnls_problem;
+
+typedef struct rnnls_batch rnnls_batch;
+
+size_t rnnls_batch_workspace_bytes(int32_t count, const rnnls_problem* probs,
+                                   const rnnls_opts* opts);
+int rnnls_batch_create(rnnls_batch** plan, int32_t count, const rnnls_problem* probs,
+                       const rnnls_opts* opts, void* ws, size_t ws_bytes,
+                       int32_t* bad_index);
+int rnnls_batch_run(rnnls_batch* plan, void* stream);
+int rnnls_batch_autotune(rnnls_batch* plan, void* stream, rnnls_tuning* chosen);
+int rnnls_batch_capture(rnnls_batch* plan);
+int rnnls_batch_launch(rnnls_batch* plan, void* stream);
+int rnnls_batch_destroy(rnnls_batch* plan);
+
 /* ---- launch tuning ------------------------------------------------------
  * Process-wide launch shape of the sketch kernel (all fields 0 = automatic).
  *  srht_log_tile   log2 of the rows one workgroup transforms at a time:
@@ -184,10 +270,6 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
  * Returns RNNLS_OK or -(1-based field number) for an invalid field; NULL
  * restores the automatic choice.  Not synchronised with calls in flight on
  * other host threads. */
-typedef struct rnnls_tuning {
-  int32_t srht_log_tile;
-  int32_t srht_wgs_per_cu;
-} rnnls_tuning;
 
 int rnnls_set_tuning(const rnnls_tuning* tuning);
 int rnnls_get_tuning(rnnls_tuning* tuning);

@@ -101,6 +101,28 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
   return L;
 }
 
+// many right-hand sides: sb holds r_cap x k, q holds d x k, cc holds k
+Layout layout_multi(const Sizes& z, int k) {
+  Layout L;
+  size_t off = 0;
+  L.rows = put(off, sizeof(int32_t) * z.r_cap);
+  L.count = put(off, sizeof(int32_t));
+  L.status = put(off, sizeof(int32_t));
+  L.signs = put(off, sizeof(uint32_t) * (size_t)((z.n_pad + 31) / 32));
+  L.bern = put(off, sizeof(uint32_t) * streams_scratch_words(z.n_pad));
+  L.partials = put(off, srht_partials_bytes(z.sp));
+  L.sa = put(off, sizeof(float) * (size_t)z.d * z.r_cap);
+  L.sb = put(off, sizeof(float) * (size_t)k * z.r_cap);
+  L.mom = put(off, moments_scratch_bytes(z.mp));
+  L.G = put(off, sizeof(double) * (size_t)z.d * z.d);
+  L.q = put(off, sizeof(double) * (size_t)z.d * k);
+  L.cc = put(off, sizeof(double) * (size_t)k);
+  L.colabs = put(off, sizeof(double) * (size_t)z.d);
+  L.lh = put(off, lh_global_scratch_bytes(z.d, k));
+  L.total = off;
+  return L;
+}
+
 Layout layout_solve(const Sizes& z) {
   Layout L;
   size_t off = 0;
@@ -135,15 +157,85 @@ int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n
 int sketch_core(const Sizes& z, const Opts& o, uint64_t seed, const float* A, int64_t lda,
                 const float* b, float* SA, int64_t ldsa, float* Sb, int32_t* rows,
                 int32_t* count, uint32_t* signs, uint32_t* sign_export, int32_t* status,
-                uint32_t* stream_scratch,
-                float* partials, hipStream_t s) {
-  const int m = ilog2_exact((uint64_t)z.n_pad);
-  int rc = launch_streams(seed, m, z.r, z.r_cap, o.sample_mode, z.sp.log_t, signs, sign_export,
-                          rows, count, status, stream_scratch, s);
+                uint32_t* stream_scratch, float* partials, hipStream_t s) {
+  StreamJob sj{};
+  sj.seed = seed;
+  sj.m = ilog2_exact((uint64_t)z.n_pad);
+  sj.r = z.r;
+  sj.r_cap = z.r_cap;
+  sj.mode = o.sample_mode;
+  sj.sign_log_t = z.sp.log_t;
+  sj.sign_words = signs;
+  sj.sign_export = sign_export;
+  sj.scratch = stream_scratch;
+  sj.rows = rows;
+  sj.count = count;
+  sj.status = status;
+  int rc = launch_streams(sj, s);
   if (rc) return rc;
-  const double inv_sqrt_r = 1.0 / sqrt((double)z.r);
-  return launch_srht(z.sp, A, lda, b, signs, rows, count, 0.0f, partials, SA, ldsa, Sb, z.d,
-                     inv_sqrt_r, s);
+  SketchJob kj{};
+  kj.A = A;
+  kj.lda = lda;
+  kj.B = b;
+  kj.ldb = z.n;
+  kj.d = z.d;
+  kj.sign_words = signs;
+  kj.rows = rows;
+  kj.count = count;
+  kj.partials = partials;
+  kj.SA = SA;
+  kj.ldsa = ldsa;
+  kj.SB = Sb;
+  kj.ldsb = z.r_cap;
+  kj.inv_sqrt_r = 1.0 / sqrt((double)z.r);
+  return launch_srht(z.sp, kj, s);
+}
+
+MomentJob moment_job(const MomentsPlan& mp, const float* M, int64_t ldm, const float* F,
+                     int64_t ldf, const int32_t* m_dev, double* scratch, double* G, double* Q,
+                     int64_t ldq, double* c, double* colabs) {
+  MomentJob j{};
+  j.M = M;
+  j.ldm = ldm;
+  j.F = F;
+  j.ldf = ldf;
+  j.m_dev = m_dev;
+  j.part = scratch;
+  j.part_abs = scratch + align256((size_t)mp.chunks * mp.pairs * 1024 * sizeof(double)) /
+                             sizeof(double);
+  j.G = G;
+  j.Q = Q;
+  j.ldq = ldq;
+  j.c = c;
+  j.colabs = colabs;
+  return j;
+}
+
+LhJob lh_job(int d, int64_t m, const int32_t* m_dev, const Opts& o, const double* G,
+             const double* q, const double* c, const double* colabs, const int32_t* pre_status,
+             double* x, double* w, double* rnorm, int32_t* iters, int32_t* status, double* qp) {
+  LhJob j{};
+  j.d = d;
+  j.max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
+  j.m = m;
+  j.tol = o.tol;
+  j.G = G;
+  j.q = q;
+  j.q_stride = d;
+  j.c = c;
+  j.c_stride = 1;
+  j.colabs = colabs;
+  j.m_dev = m_dev;
+  j.pre_status = pre_status;
+  j.x = x;
+  j.x_stride = d;
+  j.w = w;
+  j.w_stride = d;
+  j.rnorm = rnorm;
+  j.iters = iters;
+  j.status = status;
+  j.qp_global = qp;
+  return j;
 }
 
 bool ws_ok(void* ws, size_t ws_bytes, size_t need) {
@@ -188,12 +280,12 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
   if (op == RNNLS_OP_SOLVE) {
     if (n < 1 || d < 1 || d > RNNLS_MAX_D) return 0;
     z.d = d;
-    z.mp = moments_plan(n, d, cus);
+    z.mp = moments_plan(n, d, 1, cus);
     return layout_solve(z).total;
   }
   if (op != RNNLS_OP_SKETCH && op != RNNLS_OP_RAND_NNLS) return 0;
   if (check_sketch_sizes(n, d, r, o, 1, 2, 3, 4, &z)) return 0;
-  z.mp = moments_plan(z.r_cap, d, cus);
+  z.mp = moments_plan(z.r_cap, d, 1, cus);
   if (op == RNNLS_OP_RAND_NNLS) {
     z.sp = srht_plan(n, d + 1, z.r_cap, cus);
     return layout_sketch(z, o, true, true).total;
@@ -245,7 +337,7 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   if (cus < 0) return cus;
   Sizes z;
   z.d = d;
-  z.mp = moments_plan(m, d, cus);
+  z.mp = moments_plan(m, d, 1, cus);
   const Layout L = layout_solve(z);
   if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -253,11 +345,12 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   double* q = at<double>(ws, L.q);
   double* cc = at<double>(ws, L.cc);
   double* colabs = at<double>(ws, L.colabs);
-  int rc = launch_moments(z.mp, M, ldm, f, m_dev, at<double>(ws, L.mom), G, q, cc, colabs, s);
+  int rc = launch_moments(
+      z.mp, moment_job(z.mp, M, ldm, f, m, m_dev, at<double>(ws, L.mom), G, q, d, cc, colabs), s);
   if (rc) return rc;
-  const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
-  return launch_lawson_hanson(d, G, q, cc, colabs, m, m_dev, o.tol, max_iter, x, w, rnorm, iters,
-                              status, nullptr, 1, at<double>(ws, L.lh), s);
+  return launch_lawson_hanson(lh_job(d, m, m_dev, o, G, q, cc, colabs, nullptr, x, w, rnorm, iters,
+                                     status, at<double>(ws, L.lh)),
+                              1, s);
 }
 
 int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A, int64_t lda,
@@ -277,7 +370,7 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   const int cus = device_cus();
   if (cus < 0) return cus;
   z.sp = srht_plan(n, d + 1, z.r_cap, cus);
-  z.mp = moments_plan(z.r_cap, d, cus);
+  z.mp = moments_plan(z.r_cap, d, 1, cus);
   const Layout L = layout_sketch(z, o, true, true);
   if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -294,11 +387,105 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   double* q = at<double>(ws, L.q);
   double* cc = at<double>(ws, L.cc);
   double* colabs = at<double>(ws, L.colabs);
-  rc = launch_moments(z.mp, sa, ld, sb, cnt, at<double>(ws, L.mom), G, q, cc, colabs, s);
+  rc = launch_moments(
+      z.mp, moment_job(z.mp, sa, ld, sb, z.r_cap, cnt, at<double>(ws, L.mom), G, q, d, cc, colabs),
+      s);
   if (rc) return rc;
-  const int max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
-  return launch_lawson_hanson(d, G, q, cc, colabs, z.r_cap, cnt, o.tol, max_iter, x, nullptr, rnorm,
-                              iters, status, st, 1, at<double>(ws, L.lh), s);
+  return launch_lawson_hanson(lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm,
+                                     iters, status, at<double>(ws, L.lh)),
+                              1, s);
+}
+
+size_t rnnls_multi_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t r,
+                                   const rnnls_opts* opts) {
+  const Opts o = read_opts(opts);
+  Sizes z;
+  const int cus = device_cus();
+  if (cus < 0 || k < 1 || k > RNNLS_MAX_K) return 0;
+  if (check_sketch_sizes(n, d, r, o, 1, 2, 4, 15, &z)) return 0;
+  z.sp = srht_plan(n, d + k, z.r_cap, cus);
+  z.mp = moments_plan(z.r_cap, d, k, cus);
+  return layout_multi(z, k).total;
+}
+
+int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t seed,
+                          const float* A, int64_t lda, const float* B, int64_t ldb, double* X,
+                          int64_t ldx, double* rnorm, int32_t* iters, int32_t* status,
+                          const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  const Opts o = read_opts(opts);
+  Sizes z;
+  if (k < 1 || k > RNNLS_MAX_K) return -3;
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 4, 15, &z);
+  if (rc) return rc;
+  if (o.precision != RNNLS_PREC_FP32) return RNNLS_E_UNSUPPORTED;
+  if (!A) return -6;
+  if (lda < n) return -7;
+  if (!B) return -8;
+  if (ldb < n) return -9;
+  if (!X) return -10;
+  if (ldx < d) return -11;
+  const int cus = device_cus();
+  if (cus < 0) return cus;
+  z.sp = srht_plan(n, d + k, z.r_cap, cus);
+  z.mp = moments_plan(z.r_cap, d, k, cus);
+  const Layout L = layout_multi(z, k);
+  if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float* sa = at<float>(ws, L.sa);
+  float* sb = at<float>(ws, L.sb);
+  int32_t* cnt = at<int32_t>(ws, L.count);
+  int32_t* st = at<int32_t>(ws, L.status);
+  int32_t* rows = at<int32_t>(ws, L.rows);
+  uint32_t* signs = at<uint32_t>(ws, L.signs);
+  StreamJob sj{};
+  sj.seed = seed;
+  sj.m = ilog2_exact((uint64_t)z.n_pad);
+  sj.r = z.r;
+  sj.r_cap = z.r_cap;
+  sj.mode = o.sample_mode;
+  sj.sign_log_t = z.sp.log_t;
+  sj.sign_words = signs;
+  sj.scratch = at<uint32_t>(ws, L.bern);
+  sj.rows = rows;
+  sj.count = cnt;
+  sj.status = st;
+  rc = launch_streams(sj, s);
+  if (rc) return rc;
+  SketchJob kj{};
+  kj.A = A;
+  kj.lda = lda;
+  kj.B = B;
+  kj.ldb = ldb;
+  kj.d = d;
+  kj.sign_words = signs;
+  kj.rows = rows;
+  kj.count = cnt;
+  kj.partials = at<float>(ws, L.partials);
+  kj.SA = sa;
+  kj.ldsa = z.r_cap;
+  kj.SB = sb;
+  kj.ldsb = z.r_cap;
+  kj.inv_sqrt_r = 1.0 / sqrt((double)z.r);
+  rc = launch_srht(z.sp, kj, s);
+  if (rc) return rc;
+  double* G = at<double>(ws, L.G);
+  double* Q = at<double>(ws, L.q);
+  double* cc = at<double>(ws, L.cc);
+  double* colabs = at<double>(ws, L.colabs);
+  rc = launch_moments(z.mp,
+                      moment_job(z.mp, sa, z.r_cap, sb, z.r_cap, cnt, at<double>(ws, L.mom), G,
+                                 Q, d, cc, colabs),
+                      s);
+  if (rc) return rc;
+  LhJob lj = lh_job(d, z.r_cap, cnt, o, G, Q, cc, colabs, st, X, nullptr, rnorm, iters, status,
+                    at<double>(ws, L.lh));
+  lj.G_stride = 0;        // one G for all right-hand sides
+  lj.colabs_stride = 0;
+  lj.m_dev_stride = 0;
+  lj.pre_stride = 0;
+  lj.q_stride = d;
+  lj.x_stride = ldx;
+  return launch_lawson_hanson(lj, k, s);
 }
 
 }  // extern "C"

@@ -1,0 +1,579 @@
+// Batch plans: Algorithm 1 on many independent problems of different sizes
+// with a fixed number of fused launches.
+//
+// Problems are grouped by the tile size their sketch uses (2^12..2^15, or the
+// direct kernel for n' <= 2048).  Per pass the plan launches: the random
+// streams of every problem (3 launches), per group the persistent sketch
+// kernel over all (problem, column, tile) items of the group, its ragged-tile
+// launch and its reduce, the moments of every problem (2 launches), and
+// Lawson-Hanson for every problem (one launch for d <= 64, one for d > 64;
+// one wavefront per problem).  Descriptors of every problem live in device
+// tables built once at plan time; the workspace is bound at plan time too, so
+// a pass is a fixed sequence of launches that a HIP graph can replay.
+//
+// The autotuner times the sketch launches of the plan's own problems for
+// each candidate (tile-size cap, workgroups per CU) and keeps the fastest.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+using namespace rnnls;
+
+struct Candidate {
+  int log_t_cap, wgs;
+};
+// LDS bounds the occupancy: 2^15-row tiles use 132 KB of the 160 KB per CU.
+const Candidate kCandidates[] = {{15, 1}, {14, 1}, {14, 2}, {13, 2}, {13, 4}, {12, 4}, {12, 8}};
+
+struct Settings {
+  int sample_mode = RNNLS_SAMPLE_EXACT;
+  int max_iter = 0;
+  int r_cap = 0;
+  double tol = 0.0;
+};
+
+int row_cap(int r, const Settings& o) {
+  if (o.sample_mode == RNNLS_SAMPLE_EXACT) return r;
+  if (o.r_cap > 0) return o.r_cap;
+  return r + 8 * (int)ceil(sqrt((double)r)) + 64;
+}
+
+int check_problem(const rnnls_problem& p, const Settings& o) {
+  if (p.n < 2 || p.n > (1ll << 30)) return -1;
+  if (p.d < 1 || p.d > RNNLS_MAX_D) return -1;
+  const int64_t n_pad = (int64_t)next_pow2((uint64_t)p.n);
+  if (p.r < 1 || (int64_t)p.r >= n_pad || p.r > RNNLS_MAX_R) return -1;
+  const int rc = row_cap(p.r, o);
+  if (rc < 1 || rc > RNNLS_MAX_R) return -1;
+  if (!p.A || p.lda < p.n || !p.b || !p.x) return -1;
+  return 0;
+}
+
+struct Group {
+  SrhtGroup g{};
+  std::vector<int> members;  // problem indices
+  std::vector<SketchJob> jobs;
+  SketchJob* dev = nullptr;
+};
+
+}  // namespace
+
+struct rnnls_batch {
+  int count = 0;
+  std::vector<rnnls_problem> probs;
+  Settings opts;
+  int cus = 0;
+  Candidate tune{0, 0};  // 0 = the library's default choice
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // device tables (one allocation)
+  void* dev_tables = nullptr;
+  std::vector<StreamJob> sjobs;
+  StreamJob* sdev = nullptr;
+  std::vector<Group> groups;
+  std::vector<MomentJob> mjobs;
+  MomentJob* mdev = nullptr;
+  int64_t m_chunks = 0, m_entries = 0;
+  int m_max_pairs = 0;
+  std::vector<LhJob> ljobs[2];  // d <= 64, d > 64
+  LhJob* ldev[2] = {nullptr, nullptr};
+  int l_max_d[2] = {0, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t put(size_t& off, size_t bytes) {
+  const size_t at = off;
+  off += align256(bytes);
+  return at;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p % 16) == 0; }
+
+// Workgroups per CU: the candidate's for the groups at its tile size, the
+// default for groups whose n' or r forced another tile size.
+int group_wgs(const Candidate& c, int log_t) {
+  if (c.wgs > 0 && c.log_t_cap == log_t) return c.wgs;
+  return srht_wgs_per_cu(log_t);
+}
+
+// Build every descriptor for candidate `c` laid out from ws (or only size the
+// layout when ws is NULL).  Returns the workspace bytes.
+size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
+  const int np = B.count;
+  const Settings& o = B.opts;
+  B.sjobs.assign(np, StreamJob{});
+  B.mjobs.assign(np, MomentJob{});
+  B.ljobs[0].clear();
+  B.ljobs[1].clear();
+  B.l_max_d[0] = B.l_max_d[1] = 0;
+  B.groups.clear();
+
+  // per-problem tile size and group
+  std::vector<int> log_t(np), rcap(np), m(np);
+  for (int i = 0; i < np; ++i) {
+    const rnnls_problem& p = B.probs[i];
+    m[i] = ilog2_exact(next_pow2((uint64_t)p.n));
+    rcap[i] = row_cap(p.r, o);
+    log_t[i] = srht_pref_log_t(m[i], rcap[i], c.log_t_cap);
+  }
+  const int group_keys[] = {15, 14, 13, 12, 0};
+  for (int key : group_keys) {
+    Group G;
+    G.g.log_t = key;
+    for (int i = 0; i < np; ++i)
+      if (log_t[i] == key) G.members.push_back(i);
+    if (!G.members.empty()) B.groups.push_back(std::move(G));
+  }
+
+  // grid of every group (needs the item count first)
+  for (Group& G : B.groups) {
+    int64_t items = 0, items_rag = 0, cols = 0;
+    int max_rc = 0;
+    bool vec = true;
+    for (int i : G.members) {
+      const rnnls_problem& p = B.probs[i];
+      const int ncols = p.d + 1;
+      if (G.g.log_t > 0) {
+        items += (int64_t)ncols * (p.n >> G.g.log_t);
+        items_rag += (p.n & ((1ll << G.g.log_t) - 1)) ? ncols : 0;
+      }
+      cols += ncols;
+      max_rc = std::max(max_rc, rcap[i]);
+      vec = vec && aligned16(p.A) && p.lda % 4 == 0 && aligned16(p.b);
+    }
+    G.g.items = items;
+    G.g.items_rag = items_rag;
+    G.g.cols = cols;
+    G.g.max_r_cap = max_rc;
+    G.g.vec = vec;
+    G.g.spt = G.g.log_t > 0 ? srht_spt(G.g.log_t, max_rc) : 0;
+    const int64_t cap = (int64_t)B.cus * (G.g.log_t > 0 ? group_wgs(c, G.g.log_t) : 1);
+    G.g.grid = (int)std::max<int64_t>(1, std::min(items, cap));
+  }
+
+  size_t off = 0;
+  std::vector<size_t> o_rows(np), o_cnt(np), o_st(np), o_signs(np), o_scr(np), o_part(np),
+      o_sa(np), o_sb(np), o_mom(np), o_G(np), o_q(np), o_c(np), o_abs(np), o_qp(np);
+  std::vector<int> pieces(np, 0);
+  std::vector<MomentsPlan> mp(np);
+  // sketch items and pieces per group
+  for (Group& G : B.groups) {
+    int64_t item0 = 0, item0_rag = 0, col0 = 0;
+    for (int i : G.members) {
+      const rnnls_problem& p = B.probs[i];
+      const int ncols = p.d + 1;
+      SketchJob j{};
+      j.n = p.n;
+      j.d = p.d;
+      j.ncols = ncols;
+      j.r_cap = rcap[i];
+      j.log_t = G.g.log_t;
+      j.col0 = col0;
+      col0 += ncols;
+      if (G.g.log_t > 0) {
+        j.tiles = p.n >> G.g.log_t;
+        j.rag = (p.n & ((1ll << G.g.log_t) - 1)) ? 1 : 0;
+        j.item0 = item0;
+        j.item0_rag = item0_rag;
+        item0 += (int64_t)ncols * j.tiles;
+        item0_rag += j.rag ? ncols : 0;
+        j.pieces = srht_owner_pieces(j.item0, j.tiles, ncols, G.g.items, G.g.grid) + j.rag;
+      }
+      pieces[i] = j.pieces;
+      G.jobs.push_back(j);
+    }
+  }
+  for (int i = 0; i < np; ++i) {
+    const rnnls_problem& p = B.probs[i];
+    const int64_t n_pad = 1ll << m[i];
+    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus);
+    o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
+    o_cnt[i] = put(off, sizeof(int32_t));
+    o_st[i] = put(off, sizeof(int32_t));
+    o_signs[i] = put(off, sizeof(uint32_t) * (size_t)((n_pad + 31) / 32));
+    o_scr[i] = put(off, sizeof(uint32_t) * streams_scratch_words(n_pad));
+    o_part[i] = put(off, sizeof(float) * (size_t)(p.d + 1) * pieces[i] * rcap[i]);
+    o_sa[i] = put(off, sizeof(float) * (size_t)p.d * rcap[i]);
+    o_sb[i] = put(off, sizeof(float) * (size_t)rcap[i]);
+    o_mom[i] = put(off, moments_scratch_bytes(mp[i]));
+    o_G[i] = put(off, sizeof(double) * (size_t)p.d * p.d);
+    o_q[i] = put(off, sizeof(double) * (size_t)p.d);
+    o_c[i] = put(off, sizeof(double));
+    o_abs[i] = put(off, sizeof(double) * (size_t)p.d);
+  }
+  // Lawson-Hanson: Q[:,P] goes to global memory when the launch's widest
+  // problem does not fit it in LDS
+  int maxd[2] = {0, 0};
+  for (int i = 0; i < np; ++i) {
+    const int h = B.probs[i].d > 64;
+    maxd[h] = std::max(maxd[h], B.probs[i].d);
+  }
+  for (int i = 0; i < np; ++i) {
+    const int h = B.probs[i].d > 64;
+    o_qp[i] = (maxd[h] > 0 && !lh_qp_in_lds(maxd[h]))
+                  ? put(off, sizeof(double) * (size_t)(B.probs[i].d + 1) * (B.probs[i].d | 1))
+                  : (size_t)-1;
+  }
+  const size_t total = off;
+  if (!ws) return total;
+
+  // fill pointers
+  int64_t blk0 = 0, chunk0 = 0, ent0 = 0;
+  int max_pairs = 0;
+  for (int i = 0; i < np; ++i) {
+    const rnnls_problem& p = B.probs[i];
+    StreamJob& s = B.sjobs[i];
+    s.seed = p.seed;
+    s.m = m[i];
+    s.r = p.r;
+    s.r_cap = rcap[i];
+    s.mode = o.sample_mode;
+    s.sign_log_t = log_t[i];
+    s.blk0 = blk0;
+    blk0 += streams_blocks(m[i]);
+    s.sign_words = at<uint32_t>(ws, o_signs[i]);
+    s.sign_export = nullptr;
+    s.scratch = at<uint32_t>(ws, o_scr[i]);
+    s.rows = at<int32_t>(ws, o_rows[i]);
+    s.count = at<int32_t>(ws, o_cnt[i]);
+    s.status = at<int32_t>(ws, o_st[i]);
+
+    MomentJob& mj = B.mjobs[i];
+    mj.M = at<float>(ws, o_sa[i]);
+    mj.ldm = rcap[i];
+    mj.F = at<float>(ws, o_sb[i]);
+    mj.ldf = rcap[i];
+    mj.m = rcap[i];
+    mj.m_dev = s.count;
+    mj.d = p.d;
+    mj.k = 1;
+    mj.chunks = mp[i].chunks;
+    mj.nbA = mp[i].nbA;
+    mj.nb = mp[i].nb;
+    mj.pairs = mp[i].pairs;
+    mj.chunk0 = chunk0;
+    mj.ent0 = ent0;
+    chunk0 += mp[i].chunks;
+    ent0 += (int64_t)mp[i].pairs * 1024 + p.d;
+    max_pairs = std::max(max_pairs, mp[i].pairs);
+    double* scr = at<double>(ws, o_mom[i]);
+    mj.part = scr;
+    mj.part_abs = scr + align256((size_t)mp[i].chunks * mp[i].pairs * 1024 * sizeof(double)) /
+                            sizeof(double);
+    mj.G = at<double>(ws, o_G[i]);
+    mj.Q = at<double>(ws, o_q[i]);
+    mj.ldq = p.d;
+    mj.c = at<double>(ws, o_c[i]);
+    mj.colabs = at<double>(ws, o_abs[i]);
+
+    LhJob lj{};
+    lj.d = p.d;
+    lj.max_iter = o.max_iter > 0 ? o.max_iter : 3 * p.d;
+    lj.m = rcap[i];
+    lj.tol = o.tol;
+    lj.G = mj.G;
+    lj.q = mj.Q;
+    lj.c = mj.c;
+    lj.colabs = mj.colabs;
+    lj.m_dev = s.count;
+    lj.pre_status = s.status;
+    lj.x = p.x;
+    lj.rnorm = p.rnorm;
+    lj.iters = p.iters;
+    lj.status = p.status;
+    lj.qp_global = o_qp[i] == (size_t)-1 ? nullptr : at<double>(ws, o_qp[i]);
+    const int h = p.d > 64;
+    B.ljobs[h].push_back(lj);
+    B.l_max_d[h] = std::max(B.l_max_d[h], p.d);
+  }
+  B.m_chunks = chunk0;
+  B.m_entries = ent0;
+  B.m_max_pairs = max_pairs;
+  for (Group& G : B.groups) {
+    for (size_t k = 0; k < G.members.size(); ++k) {
+      const int i = G.members[k];
+      const rnnls_problem& p = B.probs[i];
+      SketchJob& j = G.jobs[k];
+      j.A = p.A;
+      j.lda = p.lda;
+      j.B = p.b;
+      j.ldb = p.n;
+      j.sign_words = B.sjobs[i].sign_words;
+      j.rows = B.sjobs[i].rows;
+      j.count = B.sjobs[i].count;
+      j.partials = at<float>(ws, o_part[i]);
+      j.SA = at<float>(ws, o_sa[i]);
+      j.ldsa = rcap[i];
+      j.SB = at<float>(ws, o_sb[i]);
+      j.ldsb = rcap[i];
+      j.inv_sqrt_r = 1.0 / sqrt((double)p.r);
+    }
+  }
+  return total;
+}
+
+void free_tables(rnnls_batch& B) {
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  if (B.dev_tables) (void)hipFree(B.dev_tables);
+  B.dev_tables = nullptr;
+}
+
+// Build for candidate c against the bound workspace and upload the tables.
+int plan(rnnls_batch& B, const Candidate& c) {
+  free_tables(B);
+  const size_t need = build(B, c, nullptr);
+  if (need > B.ws_bytes) return RNNLS_E_WORKSPACE;
+  build(B, c, B.ws);
+  size_t bytes = 0;
+  const size_t o_s = bytes;
+  bytes += align256(sizeof(StreamJob) * B.sjobs.size());
+  std::vector<size_t> o_g;
+  for (Group& G : B.groups) {
+    o_g.push_back(bytes);
+    bytes += align256(sizeof(SketchJob) * G.jobs.size());
+  }
+  const size_t o_m = bytes;
+  bytes += align256(sizeof(MomentJob) * B.mjobs.size());
+  size_t o_l[2];
+  for (int h = 0; h < 2; ++h) {
+    o_l[h] = bytes;
+    bytes += align256(sizeof(LhJob) * B.ljobs[h].size());
+  }
+  if (hipMalloc(&B.dev_tables, bytes) != hipSuccess) {
+    B.dev_tables = nullptr;
+    return RNNLS_E_HIP;
+  }
+  std::vector<char> host(bytes, 0);
+  auto copy = [&](size_t off, const void* src, size_t n) {
+    if (n) memcpy(host.data() + off, src, n);
+  };
+  copy(o_s, B.sjobs.data(), sizeof(StreamJob) * B.sjobs.size());
+  for (size_t g = 0; g < B.groups.size(); ++g)
+    copy(o_g[g], B.groups[g].jobs.data(), sizeof(SketchJob) * B.groups[g].jobs.size());
+  copy(o_m, B.mjobs.data(), sizeof(MomentJob) * B.mjobs.size());
+  for (int h = 0; h < 2; ++h) copy(o_l[h], B.ljobs[h].data(), sizeof(LhJob) * B.ljobs[h].size());
+  if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return RNNLS_E_HIP;
+  char* base = static_cast<char*>(B.dev_tables);
+  B.sdev = reinterpret_cast<StreamJob*>(base + o_s);
+  for (size_t g = 0; g < B.groups.size(); ++g)
+    B.groups[g].dev = reinterpret_cast<SketchJob*>(base + o_g[g]);
+  B.mdev = reinterpret_cast<MomentJob*>(base + o_m);
+  for (int h = 0; h < 2; ++h) B.ldev[h] = reinterpret_cast<LhJob*>(base + o_l[h]);
+  B.tune = c;
+  return RNNLS_OK;
+}
+
+int run_sketch(rnnls_batch& B, hipStream_t s) {
+  for (Group& G : B.groups) {
+    const int rc = launch_srht_batch(G.g, G.dev, (int)G.jobs.size(), s);
+    if (rc) return rc;
+  }
+  return RNNLS_OK;
+}
+
+int run_all(rnnls_batch& B, hipStream_t s) {
+  int rc = launch_streams_batch(B.sjobs.data(), B.sdev, B.count, s);
+  if (rc) return rc;
+  rc = run_sketch(B, s);
+  if (rc) return rc;
+  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.m_entries, s);
+  if (rc) return rc;
+  for (int h = 0; h < 2; ++h) {
+    rc = launch_lawson_hanson_batch(B.ldev[h], (int)B.ljobs[h].size(), B.l_max_d[h], s);
+    if (rc) return rc;
+  }
+  return RNNLS_OK;
+}
+
+Settings read_settings(const rnnls_opts* o) {
+  Settings s;
+  if (o) {
+    s.sample_mode = o->sample_mode;
+    s.max_iter = o->max_iter;
+    s.r_cap = o->r_cap;
+    s.tol = o->tol;
+  }
+  return s;
+}
+
+bool settings_valid(const rnnls_opts* o) {
+  if (!o) return true;
+  return (o->sample_mode == RNNLS_SAMPLE_EXACT || o->sample_mode == RNNLS_SAMPLE_BERNOULLI) &&
+         o->precision == RNNLS_PREC_FP32;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rnnls_batch_workspace_bytes(int32_t count, const rnnls_problem* probs,
+                                   const rnnls_opts* opts) {
+  if (count < 1 || !probs || !settings_valid(opts)) return 0;
+  rnnls_batch B;
+  B.count = count;
+  B.probs.assign(probs, probs + count);
+  B.opts = read_settings(opts);
+  for (int i = 0; i < count; ++i)
+    if (check_problem(B.probs[i], B.opts)) return 0;
+  B.cus = device_cus();
+  if (B.cus < 0) return 0;
+  size_t most = build(B, Candidate{0, 0}, nullptr);
+  for (const Candidate& c : kCandidates) most = std::max(most, build(B, c, nullptr));
+  return most;
+}
+
+int rnnls_batch_create(rnnls_batch** out, int32_t count, const rnnls_problem* probs,
+                       const rnnls_opts* opts, void* ws, size_t ws_bytes, int32_t* bad_index) {
+  if (!out) return -1;
+  *out = nullptr;
+  if (count < 1) return -2;
+  if (!probs) return -3;
+  if (!settings_valid(opts)) return -4;
+  rnnls_batch* B = new rnnls_batch();
+  B->count = count;
+  B->probs.assign(probs, probs + count);
+  B->opts = read_settings(opts);
+  for (int i = 0; i < count; ++i) {
+    if (check_problem(B->probs[i], B->opts)) {
+      if (bad_index) *bad_index = i;
+      delete B;
+      return -3;
+    }
+  }
+  B->cus = device_cus();
+  if (B->cus < 0) {
+    const int rc = B->cus;
+    delete B;
+    return rc;
+  }
+  if (!ws || (uintptr_t)ws % 256 != 0) {
+    delete B;
+    return RNNLS_E_WORKSPACE;
+  }
+  B->ws = ws;
+  B->ws_bytes = ws_bytes;
+  const int rc = plan(*B, Candidate{0, 0});
+  if (rc) {
+    free_tables(*B);
+    delete B;
+    return rc;
+  }
+  *out = B;
+  return RNNLS_OK;
+}
+
+int rnnls_batch_run(rnnls_batch* B, void* stream) {
+  if (!B) return -1;
+  return run_all(*B, reinterpret_cast<hipStream_t>(stream));
+}
+
+int rnnls_batch_autotune(rnnls_batch* B, void* stream, rnnls_tuning* chosen) {
+  if (!B) return -1;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return RNNLS_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RNNLS_E_HIP;
+  }
+  int rc = RNNLS_OK;
+  float best = 1e30f;
+  Candidate best_c{0, 0};
+  for (const Candidate& c : kCandidates) {
+    rc = plan(*B, c);
+    if (rc == RNNLS_E_WORKSPACE) continue;
+    if (rc) break;
+    // streams once (the sketch reads their output), then the sketch timed
+    if ((rc = launch_streams_batch(B->sjobs.data(), B->sdev, B->count, s))) break;
+    if ((rc = run_sketch(*B, s))) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = RNNLS_E_HIP; break; }
+    const int reps = 3;
+    for (int k = 0; k < reps && !rc; ++k) rc = run_sketch(*B, s);
+    if (rc) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = RNNLS_E_HIP;
+      break;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = RNNLS_E_HIP; break; }
+    if (ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int rc2 = plan(*B, best_c);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (chosen) {
+    chosen->srht_log_tile = best_c.log_t_cap;
+    chosen->srht_wgs_per_cu = best_c.wgs;
+  }
+  return RNNLS_OK;
+}
+
+int rnnls_batch_capture(rnnls_batch* B) {
+  if (!B) return -1;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RNNLS_E_HIP;
+  int rc = RNNLS_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    rc = RNNLS_E_HIP;
+  } else {
+    rc = run_all(*B, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc == RNNLS_OK && (e != hipSuccess || !g)) rc = RNNLS_E_HIP;
+    if (rc == RNNLS_OK) {
+      if (hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        B->exec = nullptr;
+        rc = RNNLS_E_HIP;
+      }
+    }
+    if (rc == RNNLS_OK) B->graph = g;
+    else if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+int rnnls_batch_launch(rnnls_batch* B, void* stream) {
+  if (!B) return -1;
+  if (!B->exec) return RNNLS_E_UNSUPPORTED;
+  return hipGraphLaunch(B->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? RNNLS_OK
+             : RNNLS_E_HIP;
+}
+
+int rnnls_batch_destroy(rnnls_batch* B) {
+  if (!B) return RNNLS_OK;
+  const bool ok = hipDeviceSynchronize() == hipSuccess;
+  free_tables(*B);
+  delete B;
+  return ok ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+}  // extern "C"

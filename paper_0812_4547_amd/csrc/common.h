@@ -31,7 +31,7 @@ struct PermKeys {
   uint32_t shift;
 };
 
-inline PermKeys make_perm_keys(uint64_t seed, int m) {
+__host__ __device__ inline PermKeys make_perm_keys(uint64_t seed, int m) {
   PermKeys k;
   const uint64_t key = stream_key(seed, kStreamPerm);
   k.mask = (m >= 32) ? 0xFFFFFFFFu : ((1u << m) - 1u);
@@ -41,6 +41,13 @@ inline PermKeys make_perm_keys(uint64_t seed, int m) {
     k.kb[t] = (uint32_t)(mix64(key + 2ull * t + 1ull) & k.mask) | 1u;
   }
   return k;
+}
+
+// a^{-1} mod 2^32 for odd a (Newton iteration)
+__host__ __device__ inline uint32_t inverse_odd(uint32_t a) {
+  uint32_t x = a;
+  for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+  return x;
 }
 
 __device__ inline uint32_t perm_apply(const PermKeys& k, uint32_t x) {
@@ -68,10 +75,13 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
     if (err__ != hipSuccess) return RNNLS_E_HIP; \
   } while (0)
 
-// ---------------------------------------------------------------- launchers
-// Each returns RNNLS_OK or RNNLS_E_HIP.  Pointers are device memory.
+// ---------------------------------------------------------------- job descriptors
+// Every stage runs either one problem, whose descriptor travels by value in
+// the kernel arguments, or a batch, whose descriptors sit in a device table
+// (one per problem, sorted by their first block / item / column).  Pointers
+// are device memory.
 
-// Signs and kept rows for n' = 2^m.  sign_words (n'/32 words): with
+// Random streams of one problem, n' = 2^m.  sign_words (n'/32 words): with
 // sign_log_t = 0 bit (j % 32) of word j / 32 is set iff D_jj = -1; with
 // sign_log_t = tau > 0 the words follow the sketch kernel's tile-major order
 // (word tile*(T/32) + tid, bit 4k+e = row tile*T + k*T/8 + 4*tid + e).
@@ -79,16 +89,109 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // ascending (at most r_cap written); *count = kept rows (clamped to r_cap);
 // *status = RNNLS_SOLVE_OK, _NO_ROWS or _OVERFLOW.  scratch holds
 // streams_scratch_words(n') uint32.
-size_t streams_scratch_words(int64_t n_pad);
-int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode, int sign_log_t,
-                   uint32_t* sign_words, uint32_t* sign_export, int32_t* rows, int32_t* count,
-                   int32_t* status, uint32_t* scratch, hipStream_t s);
+struct StreamJob {
+  uint64_t seed;
+  int32_t m, r, r_cap, mode, sign_log_t, pad_;
+  int64_t blk0;  // first block in a batched launch
+  uint32_t* sign_words;
+  uint32_t* sign_export;
+  uint32_t* scratch;
+  int32_t* rows;
+  int32_t* count;
+  int32_t* status;
+};
 
-// The sketch transform (steps 1-4).  Partial sums go to `partials`; sizes
-// come from srht_plan.
+// Sketch of the columns of [A | B] (d + k columns, B nullable when k = 0).
+struct SketchJob {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  int64_t n;
+  int32_t d, ncols;
+  int64_t tiles;     // tiles per column fully inside A (n / T)
+  int32_t rag;       // 1 if a tile straddles row n
+  int32_t pieces;    // partial slots per column (main launch + rag)
+  int64_t item0;     // first item in the batched main launch
+  int64_t item0_rag; // first item in the batched ragged launch
+  int64_t col0;      // first column in the batched reduce / direct launch
+  int32_t r_cap, log_t;
+  const uint32_t* sign_words;
+  const int32_t* rows;
+  const int32_t* count;
+  float* partials;   // [ncols][pieces][r_cap]
+  float* SA;         // r_cap x d, column stride ldsa
+  int64_t ldsa;
+  float* SB;         // r_cap x k, column stride ldsb
+  int64_t ldsb;
+  double inv_sqrt_r;
+};
+
+// Gram form of [M | F] (d + k columns): G = M^T M (d x d), Q = M^T F (d x k,
+// column stride ldq), c_j = ||F_j||^2, column 1-norms of M; FP64.
+struct MomentJob {
+  const float* M;
+  int64_t ldm;
+  const float* F;
+  int64_t ldf;
+  int64_t m;
+  const int32_t* m_dev;  // nullable: rows actually present (<= m)
+  int32_t d, k;
+  int32_t chunks, nbA, nb, pairs;
+  int64_t chunk0;  // first chunk in a batched partial launch
+  int64_t ent0;    // first entry in a batched reduce launch
+  double* part;    // [chunks][pairs][32][32]
+  double* part_abs;  // [chunks][d]
+  double* G;
+  double* Q;
+  int64_t ldq;
+  double* c;
+  double* colabs;
+};
+
+// Lawson-Hanson problems.  A job describes nsub problems (one per workgroup
+// when launched alone) whose inputs sit at the given strides (stride 0:
+// shared, e.g. one G for many right-hand sides).  The tolerance is tol when
+// > 0, else 10 eps max(colabs) max(m_eff, d).
+struct LhJob {
+  int32_t d, max_iter;
+  int64_t m;
+  double tol;
+  const double* G;
+  int64_t G_stride;
+  const double* q;
+  int64_t q_stride;
+  const double* c;
+  int64_t c_stride;
+  const double* colabs;
+  int64_t colabs_stride;
+  const int32_t* m_dev;  // nullable
+  int64_t m_dev_stride;
+  const int32_t* pre_status;  // nullable: a non-OK value overrides the status
+  int64_t pre_stride;
+  double* x;
+  int64_t x_stride;
+  double* w;  // nullable
+  int64_t w_stride;
+  double* rnorm;    // nullable, stride 1
+  int32_t* iters;   // nullable, stride 1
+  int32_t* status;  // nullable, stride 1
+  double* qp_global;  // lh_matrix_words per problem when Q[:,P] is not in LDS
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns RNNLS_OK, RNNLS_E_HIP or RNNLS_E_UNSUPPORTED.  A batch launcher
+// takes the host copy (for sizes) and the device table of the same jobs.
+
+size_t streams_scratch_words(int64_t n_pad);
+int launch_streams(const StreamJob& j, hipStream_t s);
+int64_t streams_blocks(int m);
+int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs, hipStream_t s);
+
+// The sketch transform (steps 1-4).  Sizes come from srht_plan.
 struct SrhtPlan {
   int64_t n, n_pad;
-  int ncols;        // d + (b != nullptr)
+  int ncols;        // d + k
   int log_t;        // tile size T = 2^log_t (0: direct kernel for small n')
   int64_t tiles;    // tiles per column fully inside A (n / T)
   int rag;          // 1 if a tile straddles row n
@@ -98,43 +201,48 @@ struct SrhtPlan {
   int r_cap;
 };
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus);
+int srht_pref_log_t(int m, int r_cap, int log_t_cap);
+int srht_spt(int log_t, int r_cap);
+int srht_wgs_per_cu(int log_t);
 int set_tuning(const rnnls_tuning* t);
 int get_tuning(rnnls_tuning* t);
 size_t srht_partials_bytes(const SrhtPlan& p);
-int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
-                const uint32_t* sign_words, const int32_t* rows, const int32_t* count,
-                float r_scale_num, float* partials, float* SA, int64_t ldsa, float* Sb,
-                int d, double inv_sqrt_r, hipStream_t s);
+// j carries pointers and n/d/ncols/r_cap/inv_sqrt_r; launch_srht fills the plan fields.
+int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s);
+// A batched sketch group: every job has log_t = log_t of the group.
+struct SrhtGroup {
+  int log_t;  // 0: direct kernel
+  int spt;
+  int64_t items, items_rag, cols;
+  int grid;
+  int max_r_cap;
+  bool vec;   // every job 16-byte aligned (main launch without bounds checks)
+};
+int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipStream_t s);
+int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, int64_t grid);
 
-// Gram-form moments of [M | f]: G = M^T M (d x d), q = M^T f, c = f^T f and
-// the column 1-norms of M, all FP64.
 struct MomentsPlan {
   int64_t m;
-  int d;
-  int chunks;
+  int d, k;
+  int chunks, nbA, nb, pairs;
 };
-MomentsPlan moments_plan(int64_t m, int d, int cus);
+MomentsPlan moments_plan(int64_t m, int d, int k, int cus);
 size_t moments_scratch_bytes(const MomentsPlan& p);
-int launch_moments(const MomentsPlan& p, const float* M, int64_t ldm, const float* f,
-                   const int32_t* m_dev, double* scratch, double* G, double* q, double* cc,
-                   double* colabs, hipStream_t s);
+int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
+int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
+                         int64_t entries, hipStream_t s);
 
-// Lawson-Hanson on (G, q, c) for nprob problems stored back to back (G at
-// d*d, q, colabs, x, w at d, c, rnorm, iters, status at 1 per problem).  The
-// tolerance is tol when > 0, else 10 eps max(colabs) max(m_eff, d).
-// Wide problems keep Q[:, P] in global scratch (lh_global_scratch_bytes, 0 when
-// it fits in LDS).
 size_t lh_lds_bytes(int d);
 size_t lh_global_scratch_bytes(int d, int nprob);
-int launch_lawson_hanson(int d, const double* G, const double* q, const double* cc,
-                         const double* colabs, int64_t m, const int32_t* m_dev, double tol,
-                         int max_iter, double* x, double* w, double* rnorm, int32_t* iters,
-                         int32_t* status, const int32_t* pre_status, int nprob,
-                         double* global_scratch, hipStream_t s);
+bool lh_qp_in_lds(int d);
+int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);
+// every job of a batch has d <= max_d, one problem each
+int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s);
 
 int device_cus();
 
-// Event timing (timing.hip): no-ops unless rnnls_timing_enable(1).
+// Event timing (timing.hip): no-ops unless rnnls_timing_enable(1), and while
+// the stream is being captured into a graph.
 void timer_begin(int which, hipStream_t s, void** token);
 void timer_end(int which, hipStream_t s, void* token);
 

@@ -274,26 +274,33 @@ size_t lh_global_scratch_bytes(int d, int nprob) {
   return qp_in_lds(d) ? 0 : (size_t)nprob * lh_matrix_words(d) * sizeof(double);
 }
 
-// Problem `prob` reads Q at Qall + prob*d*d (full row-major), q at qall + prob*d,
-// c at cc_all[prob] and the column 1-norms of M at colabs_all + prob*d.
-template <int H, bool QPG>
-__global__ __launch_bounds__(kW) void lawson_hanson_kernel(
-    int d, const double* __restrict__ Qall, const double* __restrict__ qall,
-    const double* __restrict__ cc_all, const double* __restrict__ colabs_all, int64_t m,
-    const int32_t* __restrict__ m_dev, double tol, int max_iter, double* __restrict__ x_out,
-    double* __restrict__ w_out, double* __restrict__ rnorm_out, int32_t* __restrict__ iters_out,
-    int32_t* __restrict__ status_out, const int32_t* __restrict__ pre_status,
-    double* __restrict__ qp_global) {
+template <bool BATCH>
+__device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jobs) {
+  if constexpr (BATCH) return jobs[blockIdx.x];
+  else return one;
+}
+
+// The problem of workgroup blockIdx.x: job blockIdx.x of a batch table
+// (BATCH), or sub-problem blockIdx.x of the job `one`, whose inputs sit at the
+// job's strides.  Q (= G) is d x d row-major (symmetric).
+template <int H, bool QPG, bool BATCH>
+__global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJob* jobs) {
   extern __shared__ __attribute__((aligned(16))) double lh_lds[];
   const int lane = threadIdx.x;
-  const int prob = blockIdx.x;
-  const double* Qg = Qall + (int64_t)prob * d * d;
-  const double* qg = qall + (int64_t)prob * d;
+  const LhJob& J = lh_job<BATCH>(one, jobs);
+  const int64_t sub = BATCH ? 0 : blockIdx.x;
+  const int d = J.d;
+  const int max_iter = J.max_iter;
+  const double* Qg = J.G + sub * J.G_stride;
+  const double* qg = J.q + sub * J.q_stride;
+  const double* colabs_p = J.colabs + sub * J.colabs_stride;
+  double* x_out = J.x + sub * J.x_stride;
+  double* w_out = J.w ? J.w + sub * J.w_stride : nullptr;
   const int ld = lds_ld(d);
   const int mw = (int)lh_matrix_words(d);
   double* vb = lh_lds;  // broadcast staging, 2*kW
   double* Bs = vb + 2 * kW;
-  double* QP = QPG ? qp_global + (int64_t)prob * mw : Bs + mw;
+  double* QP = QPG ? J.qp_global + sub * mw : Bs + mw;
   double* qs = (QPG ? Bs + mw : QP + mw);
   double* dq = qs + d;
   double* xcol = dq + d;
@@ -307,14 +314,14 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
     qs[j] = qg[j];
     dq[j] = Qg[(int64_t)j * d + j];
     xcol[j] = 0.0;
-    amax = fmax(amax, colabs_all[(int64_t)prob * d + j]);
+    amax = fmax(amax, colabs_p[j]);
   }
 #pragma unroll
   for (int off = 1; off < kW; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, kW));
-  const double c = cc_all[prob];
-  const int64_t m_eff = m_dev ? (int64_t)m_dev[prob] : m;
+  const double c = J.c[sub * J.c_stride];
+  const int64_t m_eff = J.m_dev ? (int64_t)J.m_dev[sub * J.m_dev_stride] : J.m;
   const double tau =
-      uni(tol > 0.0 ? tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
+      uni(J.tol > 0.0 ? J.tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
 
   // per-lane rows: B by slot, QP by column (dummy row d when out of range)
   double* brow[H];
@@ -563,8 +570,8 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
       }
       xq += xj * qs[col];
       xw += xj * acc;
-      x_out[(int64_t)prob * d + col] = xj;
-      if (w_out) w_out[(int64_t)prob * d + col] = acc;
+      x_out[col] = xj;
+      if (w_out) w_out[col] = acc;
     }
   }
   ok = wave_all(ok);
@@ -572,44 +579,53 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(
   xw = wave_sum(xw);
   if (lane == 0) {
     if (status == RNNLS_SOLVE_OK && !ok) status = RNNLS_SOLVE_KKT_FAIL;
-    if (pre_status && pre_status[prob] != RNNLS_SOLVE_OK) status = pre_status[prob];
+    if (J.pre_status) {
+      const int32_t ps = J.pre_status[sub * J.pre_stride];
+      if (ps != RNNLS_SOLVE_OK) status = ps;
+    }
     const double r2 = c - xq - xw;
-    if (rnorm_out) rnorm_out[prob] = sqrt(r2 > 0.0 ? r2 : 0.0);
-    if (iters_out) iters_out[prob] = iters;
-    if (status_out) status_out[prob] = status;
+    if (J.rnorm) J.rnorm[sub] = sqrt(r2 > 0.0 ? r2 : 0.0);
+    if (J.iters) J.iters[sub] = iters;
+    if (J.status) J.status[sub] = status;
   }
 }
 
-int launch_lawson_hanson(int d, const double* G, const double* q, const double* cc,
-                         const double* colabs, int64_t m, const int32_t* m_dev, double tol,
-                         int max_iter, double* x, double* w, double* rnorm, int32_t* iters,
-                         int32_t* status, const int32_t* pre_status, int nprob,
-                         double* global_scratch, hipStream_t s) {
+bool lh_qp_in_lds(int d) { return qp_in_lds(d); }
+
+template <bool BATCH>
+int launch_lh(const LhJob& one, const LhJob* jobs, int nblocks, int d, hipStream_t s) {
   const size_t lds = lh_lds_bytes(d);
   const bool qpg = !qp_in_lds(d);
-  if (qpg && !global_scratch) return RNNLS_E_WORKSPACE;
-  const void* fn = d <= kW ? (const void*)lawson_hanson_kernel<1, false>
-                   : !qpg  ? (const void*)lawson_hanson_kernel<2, false>
-                           : (const void*)lawson_hanson_kernel<2, true>;
+  const void* fn = d <= kW ? (const void*)lawson_hanson_kernel<1, false, BATCH>
+                   : !qpg  ? (const void*)lawson_hanson_kernel<2, false, BATCH>
+                           : (const void*)lawson_hanson_kernel<2, true, BATCH>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess)
     return RNNLS_E_HIP;
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_SOLVE, s, &tok);
   if (d <= kW)
-    hipLaunchKernelGGL((lawson_hanson_kernel<1, false>), dim3(nprob), dim3(kW), lds, s, d, G, q,
-                       cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status, global_scratch);
+    hipLaunchKernelGGL((lawson_hanson_kernel<1, false, BATCH>), dim3(nblocks), dim3(kW), lds, s,
+                       one, jobs);
   else if (!qpg)
-    hipLaunchKernelGGL((lawson_hanson_kernel<2, false>), dim3(nprob), dim3(kW), lds, s, d, G, q,
-                       cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status, global_scratch);
+    hipLaunchKernelGGL((lawson_hanson_kernel<2, false, BATCH>), dim3(nblocks), dim3(kW), lds, s,
+                       one, jobs);
   else
-    hipLaunchKernelGGL((lawson_hanson_kernel<2, true>), dim3(nprob), dim3(kW), lds, s, d, G, q,
-                       cc, colabs, m, m_dev, tol, max_iter, x, w, rnorm, iters, status,
-                       pre_status, global_scratch);
+    hipLaunchKernelGGL((lawson_hanson_kernel<2, true, BATCH>), dim3(nblocks), dim3(kW), lds, s,
+                       one, jobs);
   timer_end(RNNLS_TIMER_SOLVE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s) {
+  if (!qp_in_lds(j.d) && !j.qp_global) return RNNLS_E_WORKSPACE;
+  return launch_lh<false>(j, nullptr, nsub, j.d, s);
+}
+
+int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s) {
+  if (njobs < 1) return RNNLS_OK;
+  LhJob none{};
+  return launch_lh<true>(none, dev, njobs, max_d, s);
 }
 
 }  // namespace rnnls

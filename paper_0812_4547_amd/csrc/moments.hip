@@ -3,12 +3,19 @@
 // (products of two FP32 values are exact in FP64), plus the column 1-norms of
 // M, which set the Lawson-Hanson tolerance.
 //
-// [M | f] is one m x (d+1) matrix.  Its Gram matrix is cut into 32 x 32
-// blocks; a workgroup of 256 threads (2 x 2 register tile each) computes one
-// upper block over one chunk of 64 rows staged in LDS, so even a 4096-row
-// sketch spreads over hundreds of workgroups.  The per-chunk partials are
-// then summed in a fixed order (one wavefront per entry, fixed lane
-// assignment and shuffle tree: deterministic).
+// [M | F] is one m x (d+k) matrix (k = 1 for a single right-hand side f, k
+// up to hundreds for many right-hand sides sharing M).  Its Gram matrix is
+// cut into 32 x 32 blocks; only the blocks that hold M^T M, M^T F and the
+// diagonal of F^T F are formed: block rows that contain columns of M (all
+// block columns to their right) plus the diagonal blocks of F.  A workgroup
+// of 256 threads (2 x 2 register tile each) computes one such block over one
+// chunk of rows staged in LDS 64 at a time, so even a 4096-row sketch spreads
+// over hundreds of workgroups.  The per-chunk partials are then summed in a
+// fixed order (one wavefront per entry, fixed lane assignment and shuffle
+// tree: deterministic).
+//
+// One problem travels by value in the kernel arguments; a batch of problems
+// (different m, d) reads its descriptors from a device table.
 #include "common.h"
 
 namespace rnnls {
@@ -18,37 +25,66 @@ namespace {
 constexpr int kBlk = 32;
 constexpr int kRows = 64;
 
-__device__ __forceinline__ float col_elem(const float* M, int64_t ldm, const float* f, int d,
-                                          int c, int64_t row) {
-  if (c < d) return M[(int64_t)c * ldm + row];
-  if (c == d) return f[row];
+__device__ __forceinline__ float col_elem(const MomentJob& J, int c, int64_t row) {
+  if (c < J.d) return J.M[(int64_t)c * J.ldm + row];
+  if (c < J.d + J.k) return J.F[(int64_t)(c - J.d) * J.ldf + row];
   return 0.0f;
 }
 
-// partial Gram of rows [chunk range) for block pair (bi <= bj)
-__global__ __launch_bounds__(256) void gram_partial_kernel(
-    const float* __restrict__ M, int64_t ldm, const float* __restrict__ f, int d, int64_t m,
-    const int32_t* __restrict__ m_dev, int chunks, int nb, double* __restrict__ part,
-    double* __restrict__ part_abs) {
+// block pair p -> (bi, bj): block rows of M first, then diagonal blocks of F
+__host__ __device__ __forceinline__ void pair_blocks(int p, int nbA, int nb, int& bi, int& bj) {
+  for (bi = 0; bi < nbA; ++bi) {
+    const int len = nb - bi;
+    if (p < len) {
+      bj = bi + p;
+      return;
+    }
+    p -= len;
+  }
+  bi = bj = nbA + p;
+}
+
+template <class Job>
+__device__ __forceinline__ int find_by(const Job* jobs, int njobs, int64_t x,
+                                       int64_t Job::*field) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].*field <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ const MomentJob& mjob(const MomentJob& one, const MomentJob* jobs,
+                                                 int njobs, int64_t g, int64_t MomentJob::*field,
+                                                 int64_t& local) {
+  if constexpr (BATCH) {
+    const int i = find_by(jobs, njobs, g, field);
+    local = g - jobs[i].*field;
+    return jobs[i];
+  } else {
+    local = g;
+    return one;
+  }
+}
+
+// partial Gram of one row chunk for one block pair (bi <= bj)
+template <bool BATCH>
+__global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const MomentJob* jobs,
+                                                           int njobs) {
   __shared__ double Xi[kRows][kBlk + 1];
   __shared__ double Xj[kRows][kBlk + 1];
-  const int D1 = d + 1;
-  int bi = 0, bj = 0;
-  {
-    int k = blockIdx.y;
-    for (bi = 0; bi < nb; ++bi) {
-      const int row_len = nb - bi;
-      if (k < row_len) {
-        bj = bi + k;
-        break;
-      }
-      k -= row_len;
-    }
-  }
-  const int64_t m_eff = m_dev ? (int64_t)*m_dev : m;
-  const int chunk = blockIdx.x;
-  const int64_t r0 = (m * chunk) / chunks;
-  const int64_t r1 = (m * (chunk + 1)) / chunks;
+  int64_t chunk64;
+  const MomentJob& J = mjob<BATCH>(one, jobs, njobs, blockIdx.x, &MomentJob::chunk0, chunk64);
+  const int p = blockIdx.y;
+  if (p >= J.pairs) return;
+  const int chunk = (int)chunk64;
+  int bi, bj;
+  pair_blocks(p, J.nbA, J.nb, bi, bj);
+  const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
+  const int64_t r0 = (J.m * chunk) / J.chunks;
+  const int64_t r1 = (J.m * (chunk + 1)) / J.chunks;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[2][2] = {};
   double abs_acc = 0.0;
@@ -57,8 +93,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
       const int rr = e % kRows, cc = e / kRows;  // rows fastest: coalesced
       const int64_t row = base + rr;
       const bool ok = row < r1 && row < m_eff;
-      Xi[rr][cc] = ok ? (double)col_elem(M, ldm, f, d, bi * kBlk + cc, row) : 0.0;
-      Xj[rr][cc] = ok ? (double)col_elem(M, ldm, f, d, bj * kBlk + cc, row) : 0.0;
+      Xi[rr][cc] = ok ? (double)col_elem(J, bi * kBlk + cc, row) : 0.0;
+      Xj[rr][cc] = ok ? (double)col_elem(J, bj * kBlk + cc, row) : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -70,75 +106,79 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
       acc[1][0] = fma(a1, b0, acc[1][0]);
       acc[1][1] = fma(a1, b1, acc[1][1]);
     }
-    if (bi == bj && threadIdx.x < kBlk) {
+    if (bi == bj && bi < J.nbA && threadIdx.x < kBlk) {
       for (int rr = 0; rr < kRows; ++rr) abs_acc += fabs(Xi[rr][threadIdx.x]);
     }
     __syncthreads();
   }
-  double* out = part + (int64_t)chunk * D1 * D1;
+  double* out = J.part + ((int64_t)chunk * J.pairs + p) * (kBlk * kBlk);
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int i = bi * kBlk + tx * 2 + u, j = bj * kBlk + ty * 2 + v;
-      if (i < D1 && j < D1) out[(int64_t)i * D1 + j] = acc[u][v];
-    }
-  if (bi == bj && threadIdx.x < kBlk) {
+    for (int v = 0; v < 2; ++v) out[(tx * 2 + u) * kBlk + ty * 2 + v] = acc[u][v];
+  if (bi == bj && bi < J.nbA && threadIdx.x < kBlk) {
     const int c = bi * kBlk + threadIdx.x;
-    if (c < D1) part_abs[(int64_t)chunk * D1 + c] = abs_acc;
+    if (c < J.d) J.part_abs[(int64_t)chunk * J.d + c] = abs_acc;
   }
 }
 
 // One wavefront per output entry: lanes take chunks lane, lane+64, ... in
-// order, then a fixed shuffle tree.  Entries e < D1*D1 are Gram entries
-// (upper triangle used), the next d are column 1-norms.
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part,
-                                                          const double* __restrict__ part_abs,
-                                                          int chunks, int d,
-                                                          double* __restrict__ G,
-                                                          double* __restrict__ q,
-                                                          double* __restrict__ cc,
-                                                          double* __restrict__ colabs) {
-  const int D1 = d + 1;
-  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+// order, then a fixed shuffle tree.  Entry e < pairs*1024 is element
+// (e/32 % 32, e % 32) of block pair e/1024; the next d are column 1-norms.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const MomentJob* jobs,
+                                                          int njobs) {
+  const int64_t eg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int64_t e64;
+  const MomentJob& J = mjob<BATCH>(one, jobs, njobs, eg, &MomentJob::ent0, e64);
   const int lane = threadIdx.x & 63;
-  const int nent = D1 * D1 + d;
-  if (e >= nent) return;
-  const bool gram = e < D1 * D1;
-  int i = 0, j = 0;
-  if (gram) {
-    i = e / D1;
-    j = e % D1;
-    if (i > j) return;  // the whole wavefront leaves together
+  const int nblk = J.pairs * kBlk * kBlk;
+  if (e64 >= nblk + J.d) return;
+  const int e = (int)e64;
+  const int D1 = J.d + J.k;
+  int i = 0, j = 0, kind = 3;  // 0 G, 1 Q, 2 c, 3 colabs
+  if (e < nblk) {
+    int bi, bj;
+    pair_blocks(e / (kBlk * kBlk), J.nbA, J.nb, bi, bj);
+    i = bi * kBlk + (e / kBlk) % kBlk;
+    j = bj * kBlk + e % kBlk;
+    if (i > j || j >= D1) return;  // the whole wavefront leaves together
+    if (j < J.d) kind = 0;
+    else if (i < J.d) kind = 1;
+    else if (i == j) kind = 2;
+    else return;
   }
   double s = 0.0;
-  if (gram) {
-    for (int c = lane; c < chunks; c += 64) s += part[(int64_t)c * D1 * D1 + e];
+  if (kind != 3) {
+    for (int c = lane; c < J.chunks; c += 64) s += J.part[(int64_t)c * nblk + e];
   } else {
-    const int col = e - D1 * D1;
-    for (int c = lane; c < chunks; c += 64) s += part_abs[(int64_t)c * D1 + col];
+    const int col = e - nblk;
+    for (int c = lane; c < J.chunks; c += 64) s += J.part_abs[(int64_t)c * J.d + col];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane != 0) return;
-  if (!gram) {
-    colabs[e - D1 * D1] = s;
-  } else if (j < d) {
-    G[(int64_t)i * d + j] = s;
-    G[(int64_t)j * d + i] = s;
-  } else if (i < d) {
-    q[i] = s;
-  } else {
-    cc[0] = s;
+  switch (kind) {
+    case 0:
+      J.G[(int64_t)i * J.d + j] = s;
+      J.G[(int64_t)j * J.d + i] = s;
+      break;
+    case 1: J.Q[(int64_t)(j - J.d) * J.ldq + i] = s; break;
+    case 2: J.c[i - J.d] = s; break;
+    default: J.colabs[e - nblk] = s;
   }
 }
 
 }  // namespace
 
-MomentsPlan moments_plan(int64_t m, int d, int cus) {
+MomentsPlan moments_plan(int64_t m, int d, int k, int cus) {
   MomentsPlan p;
   p.m = m;
   p.d = d;
+  p.k = k;
+  p.nbA = (d + kBlk - 1) / kBlk;
+  p.nb = (d + k + kBlk - 1) / kBlk;
+  p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
   const int64_t want = (m + kRows - 1) / kRows;
   const int64_t cap = 2 * (int64_t)cus;
   p.chunks = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
@@ -146,27 +186,40 @@ MomentsPlan moments_plan(int64_t m, int d, int cus) {
 }
 
 size_t moments_scratch_bytes(const MomentsPlan& p) {
-  const size_t D1 = (size_t)p.d + 1;
-  return align256((size_t)p.chunks * D1 * D1 * sizeof(double)) +
-         align256((size_t)p.chunks * D1 * sizeof(double));
+  return align256((size_t)p.chunks * p.pairs * kBlk * kBlk * sizeof(double)) +
+         align256((size_t)p.chunks * p.d * sizeof(double));
 }
 
-int launch_moments(const MomentsPlan& p, const float* M, int64_t ldm, const float* f,
-                   const int32_t* m_dev, double* scratch, double* G, double* q, double* cc,
-                   double* colabs, hipStream_t s) {
-  const int D1 = p.d + 1;
-  const int nb = (D1 + kBlk - 1) / kBlk;
-  const int pairs = nb * (nb + 1) / 2;
-  double* part = scratch;
-  double* part_abs =
-      scratch + align256((size_t)p.chunks * D1 * D1 * sizeof(double)) / sizeof(double);
+int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
+  j.m = p.m;
+  j.d = p.d;
+  j.k = p.k;
+  j.chunks = p.chunks;
+  j.nbA = p.nbA;
+  j.nb = p.nb;
+  j.pairs = p.pairs;
+  j.chunk0 = j.ent0 = 0;
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
-  hipLaunchKernelGGL(gram_partial_kernel, dim3(p.chunks, pairs), dim3(256), 0, s, M, ldm, f,
-                     p.d, p.m, m_dev, p.chunks, nb, part, part_abs);
-  const int nent = D1 * D1 + p.d;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nent + 3) / 4), dim3(256), 0, s, part, part_abs,
-                     p.chunks, p.d, G, q, cc, colabs);
+  hipLaunchKernelGGL(gram_partial_kernel<false>, dim3(p.chunks, p.pairs), dim3(256), 0, s, j,
+                     (const MomentJob*)nullptr, 1);
+  const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
+  hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 3) / 4)), dim3(256), 0, s,
+                     j, (const MomentJob*)nullptr, 1);
+  timer_end(RNNLS_TIMER_MOMENTS, s, tok);
+  return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
+                         int64_t entries, hipStream_t s) {
+  if (njobs < 1) return RNNLS_OK;
+  MomentJob none{};
+  void* tok = nullptr;
+  timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
+  hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)chunks, (unsigned)max_pairs),
+                     dim3(256), 0, s, none, dev, njobs);
+  hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)((entries + 3) / 4)), dim3(256), 0,
+                     s, none, dev, njobs);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }

@@ -67,59 +67,105 @@ __host__ __device__ __forceinline__ int64_t owner_of(int64_t x, int64_t I, int64
   return ((x + 1) * G - 1) / I;
 }
 
-struct TiledArgs {
-  const float* A;
-  int64_t lda;
-  const float* b;
-  int d;           // columns of A; column index d means b
-  int64_t n;       // true rows (rows >= n read as zero)
-  int64_t tiles;   // tiles per column in this launch
-  int64_t tile0;   // global index of this launch's first tile
-  int64_t items;   // ncols * tiles
+// One launch of the tiled kernel: a single problem (`one`, BATCH = false) or
+// the jobs of a batch group (device table, sorted by first item).
+struct TiledLaunch {
+  SketchJob one;
+  const SketchJob* jobs;
+  int njobs;
+  int64_t items;  // items of this launch
   int64_t grid;
-  int pieces;      // partial slots per column (all launches)
-  int piece0;      // first slot of this launch
-  int r_cap;
-  const uint32_t* sign_words;
-  const int32_t* rows;
-  const int32_t* count;
-  float* partials;  // [ncols][pieces][r_cap]
 };
 
-template <int LOG_T, bool GUARD>
-__device__ __forceinline__ void load_tile(const TiledArgs& a, int col, int64_t tile,
+template <bool BATCH>
+__device__ __forceinline__ const SketchJob& sjob(const TiledLaunch& L, int i) {
+  if constexpr (BATCH) return L.jobs[i];
+  else return L.one;
+}
+
+// Item layout of a launch: the main launch walks (column, full tile) items of
+// every job, the ragged launch (RAG) one item per column (its straddling tile).
+template <bool RAG>
+__device__ __forceinline__ int64_t job_item0(const SketchJob& J) {
+  return RAG ? J.item0_rag : J.item0;
+}
+template <bool RAG>
+__device__ __forceinline__ int64_t job_tiles(const SketchJob& J) {
+  return RAG ? 1 : J.tiles;
+}
+
+// Largest job whose first item is <= item (jobs with no items share the
+// first item of the next job and are passed over).
+template <bool RAG>
+__device__ __forceinline__ int find_sjob(const SketchJob* jobs, int njobs, int64_t item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (job_item0<RAG>(jobs[mid]) <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool BATCH, bool RAG>
+__device__ __forceinline__ void locate(const TiledLaunch& L, int64_t item, int& ji, int& col,
+                                       int64_t& tile) {
+  if constexpr (BATCH) {
+    while (ji + 1 < L.njobs && job_item0<RAG>(L.jobs[ji + 1]) <= item) ++ji;
+  }
+  const SketchJob& J = sjob<BATCH>(L, ji);
+  const int64_t local = item - job_item0<RAG>(J);
+  const int64_t tl = job_tiles<RAG>(J);
+  col = (int)(local / tl);
+  tile = RAG ? J.tiles : local % tl;
+}
+
+// Load modes: full tiles of 16-byte aligned columns (no bounds checks), the
+// straddling tile of aligned columns (vector loads up to row n, element loads
+// for the one float4 cut by n), and unaligned columns (element loads).
+enum LoadMode { kFullVec = 0, kEdgeVec = 1, kScalar = 2 };
+
+template <int LOG_T, int MODE>
+__device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t tile,
                                           float (&v)[kRegs], uint32_t& sw) {
   constexpr int T = 1 << LOG_T;
   const int tid = threadIdx.x;
   // wave-uniform 64-bit bases; per-lane offsets stay 32-bit
-  const float* base = ((col < a.d) ? a.A + (int64_t)col * a.lda : a.b) + tile * T;
-  const int64_t rem = a.n - tile * T;
+  const float* base =
+      ((col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb) + tile * T;
+  const int64_t rem = J.n - tile * T;
   const int lim = rem < T ? (int)rem : T;  // rows of this tile inside A
   // tile-major signs: bit 4k+e belongs to v[4k+e]
-  sw = (a.sign_words + tile * (T / kRegs))[(uint32_t)tid];
-  if (!GUARD) {  // whole tile inside A, 16-byte aligned: 8 vector loads back to back
+  sw = (J.sign_words + tile * (T / kRegs))[(uint32_t)tid];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      // unsigned 32-bit offsets from a scalar base (no 64-bit lane arithmetic)
-      const uint32_t off = 4u * (uint32_t)tid + (uint32_t)(k * (T / 8));
+  for (int k = 0; k < 8; ++k) {
+    // unsigned 32-bit offsets from a scalar base (no 64-bit lane arithmetic)
+    const uint32_t off = 4u * (uint32_t)tid + (uint32_t)(k * (T / 8));
+    if (MODE == kFullVec || (MODE == kEdgeVec && off + 4 <= (uint32_t)lim)) {
       const float4 q = *reinterpret_cast<const float4*>(base + off);
       v[4 * k + 0] = q.x;
       v[4 * k + 1] = q.y;
       v[4 * k + 2] = q.z;
       v[4 * k + 3] = q.w;
-    }
-  } else {
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int off = 4 * tid + k * (T / 8);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * k + e] = (off + e < lim) ? base[off + e] : 0.0f;
+      for (int e = 0; e < 4; ++e) v[4 * k + e] = (off + e < (uint32_t)lim) ? base[off + e] : 0.0f;
     }
   }
 }
 
-template <int LOG_T, int SPT, bool GUARD>
-__global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledArgs a) {
+template <int SPT, int NT>
+__device__ __forceinline__ int load_rows(const SketchJob& J, int32_t (&srow)[SPT]) {
+  const int count = *J.count;
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const int l = threadIdx.x + s * NT;
+    srow[s] = (l < count) ? J.rows[l] : 0;
+  }
+  return count;
+}
+
+template <int LOG_T, int SPT, int MODE, bool BATCH, bool RAG>
+__global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledLaunch L) {
   constexpr int T = 1 << LOG_T;
   constexpr int NT = T / kRegs;
   constexpr int LDS_WORDS = T + (T >> 5);
@@ -127,25 +173,26 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
 
   const int tid = threadIdx.x;
   const int64_t w = blockIdx.x;
-  const int64_t item_begin = (w * a.items) / a.grid;
-  const int64_t item_end = ((w + 1) * a.items) / a.grid;
-  const int count = *a.count;
+  const int64_t item_begin = (w * L.items) / L.grid;
+  const int64_t item_end = ((w + 1) * L.items) / L.grid;
+  if (item_begin >= item_end) return;
+
+  int ji = 0;
+  if constexpr (BATCH) ji = find_sjob<RAG>(L.jobs, L.njobs, item_begin);
+  int col;
+  int64_t tile;
+  locate<BATCH, RAG>(L, item_begin, ji, col, tile);
 
   int32_t srow[SPT];
   float acc[SPT];
+  int count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
 #pragma unroll
-  for (int s = 0; s < SPT; ++s) {
-    const int l = tid + s * NT;
-    srow[s] = (l < count) ? a.rows[l] : 0;
-    acc[s] = 0.0f;
-  }
+  for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
 
   float v[kRegs];
   uint32_t sw;
   int64_t item = item_begin;
-  int col = (int)(item / a.tiles);
-  int64_t tile = a.tile0 + item % a.tiles;
-  load_tile<LOG_T, GUARD>(a, col, tile, v, sw);
+  load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, v, sw);
 
   const int p2_base = (tid & 3) + ((tid >> 2) << 7) + ((tid >> 2) << 2);
   const int p3_base = (tid & 127) + (tid >> 7) * (4096 + 128);
@@ -164,11 +211,12 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
     // prefetch the next item while the LDS passes run
     const int64_t next = item + 1;
     const int cur_col = col;
+    const int cur_job = ji;
     const int64_t cur_tile = tile;
-    if (next < item_end) {
-      col = (int)(next / a.tiles);
-      tile = a.tile0 + next % a.tiles;
-      load_tile<LOG_T, GUARD>(a, col, tile, v, sw);
+    // (a ragged launch gives every workgroup exactly one item: no prefetch)
+    if (!RAG && next < item_end) {
+      locate<BATCH, RAG>(L, next, ji, col, tile);
+      load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, v, sw);
     }
     __syncthreads();
     {  // pass 2: bits 2..6
@@ -198,11 +246,14 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
       acc[s] += flip(z, par);
     }
     __syncthreads();
-    const bool last_of_col = (next >= item_end) || (col != cur_col);
+    const bool new_job = BATCH && !RAG && (next < item_end) && (ji != cur_job);
+    const bool last_of_col = RAG || (next >= item_end) || (col != cur_col) || new_job;
     if (last_of_col) {
-      const int64_t first_owner = owner_of((int64_t)cur_col * a.tiles, a.items, a.grid);
-      const int piece = a.piece0 + (int)(w - first_owner);
-      float* dst = a.partials + ((int64_t)cur_col * a.pieces + piece) * a.r_cap;
+      const SketchJob& J = sjob<BATCH>(L, cur_job);
+      const int64_t tl = job_tiles<RAG>(J);
+      const int64_t first = job_item0<RAG>(J) + (int64_t)cur_col * tl;
+      const int piece = (RAG ? J.pieces - 1 : 0) + (int)(w - owner_of(first, L.items, L.grid));
+      float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
 #pragma unroll
       for (int s = 0; s < SPT; ++s) {
         const int l = tid + s * NT;
@@ -210,100 +261,117 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledA
         acc[s] = 0.0f;
       }
     }
+    if (new_job) count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
     item = next;
   }
 }
 
+// Largest job whose first column is <= c (reduce and direct launches).
+__device__ __forceinline__ int find_col_job(const SketchJob* jobs, int njobs, int64_t c) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].col0 <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ const SketchJob& col_job(const SketchJob& one, const SketchJob* jobs,
+                                                    int njobs, int& col) {
+  if constexpr (BATCH) {
+    const int i = find_col_job(jobs, njobs, blockIdx.y);
+    col = (int)((int64_t)blockIdx.y - jobs[i].col0);
+    return jobs[i];
+  } else {
+    col = blockIdx.y;
+    return one;
+  }
+}
+
+__device__ __forceinline__ void store_out(const SketchJob& J, int col, int l, float y) {
+  if (col < J.d)
+    J.SA[(int64_t)col * J.ldsa + l] = y;
+  else
+    J.SB[(int64_t)(col - J.d) * J.ldsb + l] = y;
+}
+
 // Fixed-order sum of the per-workgroup partials of each column, times 1/sqrt r.
 // Slots 0.. hold the main launch's pieces of the column (if it has full
-// tiles), slot `rag_slot` (>= 0) the straddling tile.
-__global__ void srht_reduce_kernel(const float* __restrict__ partials, int pieces, int r_cap,
-                                   int64_t tiles, int64_t items, int64_t grid, int rag_slot,
-                                   const int32_t* __restrict__ count, int d,
-                                   double inv_sqrt_r, float* __restrict__ SA, int64_t ldsa,
-                                   float* __restrict__ Sb) {
+// tiles), the last slot the straddling tile (if any).
+template <bool BATCH>
+__global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, int njobs,
+                                   int64_t items, int64_t grid) {
+  int col;
+  const SketchJob& J = col_job<BATCH>(one, jobs, njobs, col);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int col = blockIdx.y;
-  if (l >= *count) return;
-  const float* p = partials + (int64_t)col * pieces * r_cap + l;
+  if (col >= J.ncols || l >= *J.count) return;
+  const float* p = J.partials + (int64_t)col * J.pieces * J.r_cap + l;
   float s = 0.0f;
-  if (tiles > 0) {
-    const int64_t w0 = owner_of((int64_t)col * tiles, items, grid);
-    const int64_t w1 = owner_of((int64_t)col * tiles + tiles - 1, items, grid);
-    for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * r_cap];
+  if (J.tiles > 0) {
+    const int64_t first = J.item0 + (int64_t)col * J.tiles;
+    const int64_t w0 = owner_of(first, items, grid);
+    const int64_t w1 = owner_of(first + J.tiles - 1, items, grid);
+    for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * J.r_cap];
   }
-  if (rag_slot >= 0) s += p[(int64_t)rag_slot * r_cap];
-  const float y = (float)((double)s * inv_sqrt_r);
-  if (col < d)
-    SA[(int64_t)col * ldsa + l] = y;
-  else
-    Sb[l] = y;
+  if (J.rag) s += p[(int64_t)(J.pieces - 1) * J.r_cap];
+  store_out(J, col, l, (float)((double)s * J.inv_sqrt_r));
 }
 
 // Small n' (<= 2048): every output straight from the definition, FP64 sums.
-__global__ void srht_direct_kernel(const float* __restrict__ A, int64_t lda,
-                                   const float* __restrict__ b, int d, int64_t n,
-                                   const uint32_t* __restrict__ sign_words,
-                                   const int32_t* __restrict__ rows,
-                                   const int32_t* __restrict__ count, double inv_sqrt_r,
-                                   float* __restrict__ SA, int64_t ldsa, float* __restrict__ Sb) {
+template <bool BATCH>
+__global__ void srht_direct_kernel(SketchJob one, const SketchJob* jobs, int njobs) {
+  int col;
+  const SketchJob& J = col_job<BATCH>(one, jobs, njobs, col);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int col = blockIdx.y;
-  if (l >= *count) return;
-  const float* src = (col < d) ? A + (int64_t)col * lda : b;
-  const uint32_t i = (uint32_t)rows[l];
+  if (col >= J.ncols || l >= *J.count) return;
+  const float* src = (col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb;
+  const uint32_t i = (uint32_t)J.rows[l];
   double acc = 0.0;
-  for (int64_t j = 0; j < n; ++j) {
-    const uint32_t sgn = ((sign_words[j >> 5] >> (j & 31)) ^ __popc(i & (uint32_t)j)) & 1u;
+  for (int64_t j = 0; j < J.n; ++j) {
+    const uint32_t sgn = ((J.sign_words[j >> 5] >> (j & 31)) ^ __popc(i & (uint32_t)j)) & 1u;
     const double x = (double)src[j];
     acc += sgn ? -x : x;
   }
-  const float y = (float)(acc * inv_sqrt_r);
-  if (col < d)
-    SA[(int64_t)col * ldsa + l] = y;
-  else
-    Sb[l] = y;
+  store_out(J, col, l, (float)(acc * J.inv_sqrt_r));
 }
 
-template <int LOG_T, int SPT>
-int launch_tiled_t(const TiledArgs& a, bool guard, hipStream_t s) {
+template <int LOG_T, int SPT, bool BATCH>
+int launch_tiled_t(const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
   constexpr int NT = (1 << LOG_T) / kRegs;
-  if (!guard)
-    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, false>), dim3(a.grid), dim3(NT), 0, s, a);
+  const dim3 g((unsigned)L.grid), b(NT);
+  if (rag && vec)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kEdgeVec, BATCH, true>), g, b, 0, s, L);
+  else if (rag)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kScalar, BATCH, true>), g, b, 0, s, L);
+  else if (vec)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kFullVec, BATCH, false>), g, b, 0, s, L);
   else
-    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, true>), dim3(a.grid), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kScalar, BATCH, false>), g, b, 0, s, L);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
-template <int LOG_T>
-int launch_tiled_spt(int spt, const TiledArgs& a, bool guard, hipStream_t s) {
+template <int LOG_T, bool BATCH>
+int launch_tiled_spt(int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
   switch (spt) {
-    case 1: return launch_tiled_t<LOG_T, 1>(a, guard, s);
-    case 2: return launch_tiled_t<LOG_T, 2>(a, guard, s);
-    case 4: return launch_tiled_t<LOG_T, 4>(a, guard, s);
-    case 8: return launch_tiled_t<LOG_T, 8>(a, guard, s);
-    case 16: return launch_tiled_t<LOG_T, 16>(a, guard, s);
-    case 32: return launch_tiled_t<LOG_T, 32>(a, guard, s);
+    case 1: return launch_tiled_t<LOG_T, 1, BATCH>(L, vec, rag, s);
+    case 2: return launch_tiled_t<LOG_T, 2, BATCH>(L, vec, rag, s);
+    case 4: return launch_tiled_t<LOG_T, 4, BATCH>(L, vec, rag, s);
+    case 8: return launch_tiled_t<LOG_T, 8, BATCH>(L, vec, rag, s);
+    case 16: return launch_tiled_t<LOG_T, 16, BATCH>(L, vec, rag, s);
+    case 32: return launch_tiled_t<LOG_T, 32, BATCH>(L, vec, rag, s);
     default: return RNNLS_E_UNSUPPORTED;
   }
 }
 
-int launch_tiled(int log_t, int spt, const TiledArgs& a, bool guard, hipStream_t s) {
+template <bool BATCH>
+int launch_tiled(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
   switch (log_t) {
-    case 12: return launch_tiled_spt<12>(spt, a, guard, s);
-    case 13: return launch_tiled_spt<13>(spt, a, guard, s);
-    case 14: return launch_tiled_spt<14>(spt, a, guard, s);
-    case 15: return launch_tiled_spt<15>(spt, a, guard, s);
+    case 12: return launch_tiled_spt<12, BATCH>(spt, L, vec, rag, s);
+    case 13: return launch_tiled_spt<13, BATCH>(spt, L, vec, rag, s);
+    case 14: return launch_tiled_spt<14, BATCH>(spt, L, vec, rag, s);
+    case 15: return launch_tiled_spt<15, BATCH>(spt, L, vec, rag, s);
     default: return RNNLS_E_UNSUPPORTED;
-  }
-}
-
-int wgs_per_cu(int log_t) {
-  switch (log_t) {
-    case 15: return 1;
-    case 14: return 2;
-    case 13: return 4;
-    default: return 8;
   }
 }
 
@@ -317,6 +385,17 @@ rnnls_tuning current_tuning() {
 }
 
 }  // namespace
+
+int srht_wgs_per_cu(int log_t) {
+  const int t = g_wgs_per_cu.load();
+  if (t > 0) return t;
+  switch (log_t) {
+    case 15: return 1;
+    case 14: return 2;
+    case 13: return 4;
+    default: return 8;
+  }
+}
 
 int set_tuning(const rnnls_tuning* t) {
   if (!t) {
@@ -337,6 +416,36 @@ int get_tuning(rnnls_tuning* t) {
   return RNNLS_OK;
 }
 
+// Tile size for one problem: log_t_cap (0: the tuned or default 2^15), at most
+// n', widened while 32 kept rows per thread cannot hold r_cap; 0 = direct.
+int srht_pref_log_t(int m, int r_cap, int log_t_cap) {
+  if (m <= 11) return 0;
+  int cap = log_t_cap > 0 ? log_t_cap : g_log_tile.load();
+  int lt = cap > 0 ? cap : 15;
+  if (lt > m) lt = m;
+  while (((1 << lt) / kRegs) * 32 < r_cap && lt < 15 && lt < m) ++lt;
+  return lt;
+}
+
+int srht_spt(int log_t, int r_cap) {
+  const int nt = (1 << log_t) / kRegs;
+  int spt = 1;
+  while (spt * nt < r_cap) spt <<= 1;
+  return spt;
+}
+
+int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, int64_t grid) {
+  int pieces = 0;
+  for (int c = 0; c < ncols && tiles > 0; ++c) {
+    const int64_t first = item0 + (int64_t)c * tiles;
+    const int64_t w0 = owner_of(first, items, grid);
+    const int64_t w1 = owner_of(first + tiles - 1, items, grid);
+    const int k = (int)(w1 - w0 + 1);
+    if (k > pieces) pieces = k;
+  }
+  return pieces;
+}
+
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   SrhtPlan p{};
   p.n = n;
@@ -344,34 +453,15 @@ SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   p.ncols = ncols;
   p.r_cap = r_cap;
   const int m = ilog2_exact((uint64_t)p.n_pad);
-  if (m <= 11) {  // direct kernel
-    p.log_t = 0;
-    return p;
-  }
-  const rnnls_tuning tune = current_tuning();
-  p.log_t = tune.srht_log_tile > 0 ? tune.srht_log_tile : 15;
-  if (p.log_t > m) p.log_t = m;
-  int spt = 1;
-  // at most 32 kept rows per thread: widen the tile when r needs it
-  while (((1 << p.log_t) / kRegs) * 32 < r_cap && p.log_t < 15 && p.log_t < m) ++p.log_t;
-  const int nt = (1 << p.log_t) / kRegs;
-  while (spt * nt < r_cap) spt <<= 1;
-  p.spt = spt;
+  p.log_t = srht_pref_log_t(m, r_cap, 0);
+  if (p.log_t == 0) return p;  // direct kernel
+  p.spt = srht_spt(p.log_t, r_cap);
   p.tiles = n >> p.log_t;                       // full tiles per column
   p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;  // one straddling tile
   const int64_t items = (int64_t)ncols * p.tiles;
-  const int per_cu = tune.srht_wgs_per_cu > 0 ? tune.srht_wgs_per_cu : wgs_per_cu(p.log_t);
-  const int64_t cap = (int64_t)cus * per_cu;
+  const int64_t cap = (int64_t)cus * srht_wgs_per_cu(p.log_t);
   p.grid = (int)(items < cap ? items : cap);
-  // most workgroups of the main launch touching one column
-  int pieces = 0;
-  for (int c = 0; c < ncols && items > 0; ++c) {
-    const int64_t w0 = owner_of((int64_t)c * p.tiles, items, p.grid);
-    const int64_t w1 = owner_of((int64_t)c * p.tiles + p.tiles - 1, items, p.grid);
-    const int k = (int)(w1 - w0 + 1);
-    if (k > pieces) pieces = k;
-  }
-  p.pieces = pieces + p.rag;
+  p.pieces = srht_owner_pieces(0, p.tiles, ncols, items, p.grid) + p.rag;
   return p;
 }
 
@@ -380,58 +470,83 @@ size_t srht_partials_bytes(const SrhtPlan& p) {
   return (size_t)p.ncols * p.pieces * p.r_cap * sizeof(float);
 }
 
-int launch_srht(const SrhtPlan& p, const float* A, int64_t lda, const float* b,
-                const uint32_t* sign_words, const int32_t* rows, const int32_t* count,
-                float /*unused*/, float* partials, float* SA, int64_t ldsa, float* Sb, int d,
-                double inv_sqrt_r, hipStream_t s) {
+static bool aligned16(const void* ptr) { return ((uintptr_t)ptr % 16) == 0; }
+
+int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   const int threads = 256;
   const dim3 rgrid((p.r_cap + threads - 1) / threads, p.ncols);
+  j.n = p.n;
+  j.ncols = p.ncols;
+  j.r_cap = p.r_cap;
+  j.log_t = p.log_t;
+  j.tiles = p.tiles;
+  j.rag = p.rag;
+  j.pieces = p.pieces;
+  j.item0 = j.item0_rag = j.col0 = 0;
   void* tok = nullptr;
   if (p.log_t == 0) {
     timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
-    hipLaunchKernelGGL(srht_direct_kernel, rgrid, dim3(threads), 0, s, A, lda, b, d, p.n,
-                       sign_words, rows, count, inv_sqrt_r, SA, ldsa, Sb);
+    hipLaunchKernelGGL(srht_direct_kernel<false>, rgrid, dim3(threads), 0, s, j,
+                       (const SketchJob*)nullptr, 1);
     timer_end(RNNLS_TIMER_SKETCH, s, tok);
     return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
   }
-  TiledArgs a;
-  a.A = A;
-  a.lda = lda;
-  a.b = b;
-  a.d = d;
-  a.n = p.n;
-  a.pieces = p.pieces;
-  a.r_cap = p.r_cap;
-  a.sign_words = sign_words;
-  a.rows = rows;
-  a.count = count;
-  a.partials = partials;
-  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
-                   (b == nullptr || (uintptr_t)b % 16 == 0);
+  TiledLaunch L{};
+  L.one = j;
+  L.njobs = 1;
+  const bool vec = aligned16(j.A) && (j.lda % 4 == 0) &&
+                   (p.ncols == j.d || (aligned16(j.B) && (p.ncols - j.d == 1 || j.ldb % 4 == 0)));
   int rc = RNNLS_OK;
+  const int64_t main_items = (int64_t)p.ncols * p.tiles;
   timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
   if (p.tiles > 0) {  // tiles fully inside A
-    a.tiles = p.tiles;
-    a.tile0 = 0;
-    a.items = (int64_t)p.ncols * p.tiles;
-    a.grid = p.grid;
-    a.piece0 = 0;
-    rc = launch_tiled(p.log_t, p.spt, a, !vec, s);
+    L.items = main_items;
+    L.grid = p.grid;
+    rc = launch_tiled<false>(p.log_t, p.spt, L, vec, false, s);
   }
   if (rc == RNNLS_OK && p.rag) {  // the tile straddling row n, one per column
-    a.tiles = 1;
-    a.tile0 = p.tiles;
-    a.items = p.ncols;
-    a.grid = p.ncols;
-    a.piece0 = p.pieces - 1;
-    rc = launch_tiled(p.log_t, p.spt, a, true, s);
+    L.items = p.ncols;
+    L.grid = p.ncols;
+    rc = launch_tiled<false>(p.log_t, p.spt, L, vec, true, s);
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
-  const int64_t main_items = (int64_t)p.ncols * p.tiles;
-  hipLaunchKernelGGL(srht_reduce_kernel, rgrid, dim3(threads), 0, s, partials, p.pieces,
-                     p.r_cap, p.tiles, main_items, (int64_t)p.grid, p.rag ? p.pieces - 1 : -1,
-                     count, d, inv_sqrt_r, SA, ldsa, Sb);
+  hipLaunchKernelGGL(srht_reduce_kernel<false>, rgrid, dim3(threads), 0, s, j,
+                     (const SketchJob*)nullptr, 1, main_items, (int64_t)(p.grid > 0 ? p.grid : 1));
+  return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipStream_t s) {
+  if (njobs < 1 || g.cols < 1) return RNNLS_OK;
+  const int threads = 256;
+  const dim3 rgrid((unsigned)((g.max_r_cap + threads - 1) / threads), (unsigned)g.cols);
+  SketchJob none{};
+  void* tok = nullptr;
+  if (g.log_t == 0) {
+    timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
+    hipLaunchKernelGGL(srht_direct_kernel<true>, rgrid, dim3(threads), 0, s, none, dev, njobs);
+    timer_end(RNNLS_TIMER_SKETCH, s, tok);
+    return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+  }
+  TiledLaunch L{};
+  L.jobs = dev;
+  L.njobs = njobs;
+  int rc = RNNLS_OK;
+  timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
+  if (g.items > 0) {
+    L.items = g.items;
+    L.grid = g.grid;
+    rc = launch_tiled<true>(g.log_t, g.spt, L, g.vec, false, s);
+  }
+  if (rc == RNNLS_OK && g.items_rag > 0) {
+    L.items = g.items_rag;
+    L.grid = g.items_rag;
+    rc = launch_tiled<true>(g.log_t, g.spt, L, g.vec, true, s);
+  }
+  timer_end(RNNLS_TIMER_SKETCH, s, tok);
+  if (rc != RNNLS_OK) return rc;
+  hipLaunchKernelGGL(srht_reduce_kernel<true>, rgrid, dim3(threads), 0, s, none, dev, njobs,
+                     g.items, (int64_t)(g.grid > 0 ? g.grid : 1));
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

@@ -27,6 +27,26 @@ struct KeepRule {
   uint64_t threshold;
 };
 
+__device__ __forceinline__ KeepRule make_rule(const StreamJob& j) {
+  KeepRule k{};
+  k.mode = j.mode;
+  k.r = (uint32_t)j.r;
+  if (j.mode == RNNLS_SAMPLE_EXACT) {
+    const PermKeys p = make_perm_keys(j.seed, j.m);
+    k.mask = p.mask;
+    k.shift = p.shift;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      k.ka[t] = p.ka[t];
+      k.kbinv[t] = inverse_odd(p.kb[t]) & p.mask;
+    }
+  } else {
+    k.sample_key = stream_key(j.seed, kStreamSample);
+    k.threshold = (uint64_t)j.r << (64 - j.m);
+  }
+  return k;
+}
+
 __device__ __forceinline__ bool kept(const KeepRule& k, uint32_t j) {
   if (k.mode == RNNLS_SAMPLE_EXACT) {
     uint32_t x = j;
@@ -39,6 +59,33 @@ __device__ __forceinline__ bool kept(const KeepRule& k, uint32_t j) {
     return x < k.r;
   }
   return mix64(k.sample_key + (uint64_t)j) < k.threshold;
+}
+
+// Largest job index whose first block is <= blk (jobs sorted by blk0).
+__device__ __forceinline__ int find_job(const StreamJob* jobs, int njobs, int64_t blk) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ StreamJob job_of_block(const StreamJob& one, const StreamJob* jobs,
+                                                  int njobs, int64_t* local_blk) {
+  if (!BATCH) {
+    *local_blk = blockIdx.x;
+    return one;
+  }
+  const int i = find_job(jobs, njobs, blockIdx.x);
+  const StreamJob j = jobs[i];
+  *local_blk = (int64_t)blockIdx.x - j.blk0;
+  return j;
+}
+
+__device__ __forceinline__ int64_t nblocks_of(int m) {
+  return ((1ll << m) + kRowsPerBlock - 1) / kRowsPerBlock;
 }
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
@@ -63,13 +110,21 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
   return before + incl - v;
 }
 
-// signs + kept mask + per-block kept counts
-__global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(
-    KeepRule rule, uint64_t sign_key, int64_t n_pad, int sign_log_t,
-    uint32_t* __restrict__ sign_words,
-    uint32_t* __restrict__ kept_words, uint32_t* __restrict__ block_counts) {
-  const int64_t w = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+// signs + kept mask + per-block kept counts.  Scratch of a job: kept words
+// [n'/32], block counts [blocks], block offsets [blocks].
+template <bool BATCH>
+__global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(StreamJob one,
+                                                                     const StreamJob* jobs,
+                                                                     int njobs) {
+  int64_t lb;
+  const StreamJob J = job_of_block<BATCH>(one, jobs, njobs, &lb);
+  const KeepRule rule = make_rule(J);
+  const uint64_t sign_key = stream_key(J.seed, kStreamSign);
+  const int64_t n_pad = 1ll << J.m;
   const int64_t nwords = (n_pad + 31) / 32;
+  uint32_t* kept_words = J.scratch;
+  uint32_t* counts = J.scratch + nwords;
+  const int64_t w = lb * kThreads + threadIdx.x;
   uint32_t sbits = 0, kbits = 0;
   if (w < nwords) {
     const uint64_t base = (uint64_t)w * 32ull;
@@ -83,33 +138,50 @@ __global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(
     // row tile*T + k*(T/8) + 4*tid + e
     uint64_t first = base;
     int kstride = 4;
-    if (sign_log_t > 0) {
-      const int64_t nt = (1ll << sign_log_t) >> 5;
-      first = ((uint64_t)(w / nt) << sign_log_t) + 4ull * (uint64_t)(w % nt);
-      kstride = (int)((1ll << sign_log_t) >> 3);
+    if (J.sign_log_t > 0) {
+      const int64_t nt = (1ll << J.sign_log_t) >> 5;
+      first = ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt);
+      kstride = (int)((1ll << J.sign_log_t) >> 3);
     }
 #pragma unroll 4
     for (int b = 0; b < 32; ++b) {
       const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
       if ((int64_t)j < n_pad) sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
     }
-    sign_words[w] = sbits;
+    J.sign_words[w] = sbits;
     kept_words[w] = kbits;
+    if (J.sign_export && J.sign_export != J.sign_words) {
+      uint32_t nat = 0;
+      if (J.sign_log_t > 0) {
+#pragma unroll 4
+        for (int k = 0; k < 32; ++k)
+          nat |= (uint32_t)(mix64(sign_key + base + (uint64_t)k) >> 63) << k;
+      } else {
+        nat = sbits;
+      }
+      J.sign_export[w] = nat;
+    }
   }
   int total;
   (void)block_exclusive_scan(__popc(kbits), &total);
-  if (threadIdx.x == 0) block_counts[blockIdx.x] = (uint32_t)total;
+  if (threadIdx.x == 0) counts[lb] = (uint32_t)total;
 }
 
-__global__ __launch_bounds__(kThreads) void streams_offsets_kernel(
-    int64_t nblocks, const uint32_t* __restrict__ block_counts, uint32_t* __restrict__ offsets,
-    int32_t r_cap, int32_t* __restrict__ count, int32_t* __restrict__ status) {
+// One workgroup per job: block counts -> block offsets, kept count, status.
+template <bool BATCH>
+__global__ __launch_bounds__(kThreads) void streams_offsets_kernel(StreamJob one,
+                                                                   const StreamJob* jobs) {
+  const StreamJob J = BATCH ? jobs[blockIdx.x] : one;
+  const int64_t nwords = ((1ll << J.m) + 31) / 32;
+  const int64_t nblocks = nblocks_of(J.m);
+  const uint32_t* counts = J.scratch + nwords;
+  uint32_t* offsets = J.scratch + nwords + nblocks;
   __shared__ uint32_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int64_t base = 0; base < nblocks; base += kThreads) {
     const int64_t i = base + threadIdx.x;
-    const int v = (i < nblocks) ? (int)block_counts[i] : 0;
+    const int v = (i < nblocks) ? (int)counts[i] : 0;
     int total;
     const int ex = block_exclusive_scan(v, &total);
     if (i < nblocks) offsets[i] = carry + (uint32_t)ex;
@@ -119,47 +191,33 @@ __global__ __launch_bounds__(kThreads) void streams_offsets_kernel(
   }
   if (threadIdx.x == 0) {
     const uint32_t k = carry;
-    *count = (int32_t)(k > (uint32_t)r_cap ? (uint32_t)r_cap : k);
-    if (status)
-      *status = k == 0 ? RNNLS_SOLVE_NO_ROWS
-                       : (k > (uint32_t)r_cap ? RNNLS_SOLVE_OVERFLOW : RNNLS_SOLVE_OK);
+    const uint32_t cap = (uint32_t)J.r_cap;
+    *J.count = (int32_t)(k > cap ? cap : k);
+    if (J.status)
+      *J.status = k == 0 ? RNNLS_SOLVE_NO_ROWS : (k > cap ? RNNLS_SOLVE_OVERFLOW : RNNLS_SOLVE_OK);
   }
 }
 
-__global__ __launch_bounds__(kThreads) void streams_write_rows_kernel(
-    int64_t n_pad, const uint32_t* __restrict__ kept_words, const uint32_t* __restrict__ offsets,
-    int32_t r_cap, int32_t* __restrict__ rows) {
-  const int64_t w = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t nwords = (n_pad + 31) / 32;
+template <bool BATCH>
+__global__ __launch_bounds__(kThreads) void streams_write_rows_kernel(StreamJob one,
+                                                                      const StreamJob* jobs,
+                                                                      int njobs) {
+  int64_t lb;
+  const StreamJob J = job_of_block<BATCH>(one, jobs, njobs, &lb);
+  const int64_t nwords = ((1ll << J.m) + 31) / 32;
+  const int64_t nblocks = nblocks_of(J.m);
+  const uint32_t* kept_words = J.scratch;
+  const uint32_t* offsets = J.scratch + nwords + nblocks;
+  const int64_t w = lb * kThreads + threadIdx.x;
   uint32_t bits = (w < nwords) ? kept_words[w] : 0u;
   int total;
-  int pos = (int)offsets[blockIdx.x] + block_exclusive_scan(__popc(bits), &total);
+  int pos = (int)offsets[lb] + block_exclusive_scan(__popc(bits), &total);
   while (bits) {
     const int k = __ffs(bits) - 1;
     bits &= bits - 1;
-    if (pos < r_cap) rows[pos] = (int32_t)(w * 32 + k);
+    if (pos < J.r_cap) J.rows[pos] = (int32_t)(w * 32 + k);
     ++pos;
   }
-}
-
-// Natural-layout sign words (bit j % 32 of word j / 32), for export.
-__global__ __launch_bounds__(kThreads) void sign_words_natural_kernel(
-    uint64_t sign_key, int64_t n_pad, uint32_t* __restrict__ words) {
-  const int64_t w = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (w >= (n_pad + 31) / 32) return;
-  uint32_t bits = 0;
-#pragma unroll 4
-  for (int k = 0; k < 32; ++k) {
-    const int64_t j = w * 32 + k;
-    if (j < n_pad) bits |= (uint32_t)(mix64(sign_key + (uint64_t)j) >> 63) << k;
-  }
-  words[w] = bits;
-}
-
-uint32_t inverse_odd(uint32_t a) {
-  uint32_t x = a;  // Newton iteration for a^{-1} mod 2^32 (a odd)
-  for (int i = 0; i < 5; ++i) x *= 2u - a * x;
-  return x;
 }
 
 }  // namespace
@@ -170,40 +228,29 @@ size_t streams_scratch_words(int64_t n_pad) {
   return (size_t)(nwords + 2 * nblocks + 2);
 }
 
-int launch_streams(uint64_t seed, int m, int32_t r, int32_t r_cap, int mode, int sign_log_t,
-                   uint32_t* sign_words, uint32_t* sign_export, int32_t* rows, int32_t* count,
-                   int32_t* status, uint32_t* scratch, hipStream_t s) {
-  const int64_t n_pad = 1ll << m;
-  const int64_t nwords = (n_pad + 31) / 32;
-  const int64_t nblocks = (n_pad + kRowsPerBlock - 1) / kRowsPerBlock;
-  KeepRule rule{};
-  rule.mode = mode;
-  rule.r = (uint32_t)r;
-  if (mode == RNNLS_SAMPLE_EXACT) {
-    const PermKeys k = make_perm_keys(seed, m);
-    rule.mask = k.mask;
-    rule.shift = k.shift;
-    for (int t = 0; t < 4; ++t) {
-      rule.ka[t] = k.ka[t];
-      rule.kbinv[t] = inverse_odd(k.kb[t]) & k.mask;
-    }
-  } else {
-    rule.sample_key = stream_key(seed, kStreamSample);
-    rule.threshold = (uint64_t)r << (64 - m);
-  }
-  uint32_t* kept_words = scratch;
-  uint32_t* counts = scratch + nwords;
-  uint32_t* offsets = counts + nblocks;
-  hipLaunchKernelGGL(streams_scan_rows_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, s,
-                     rule, stream_key(seed, kStreamSign), n_pad, sign_log_t, sign_words, kept_words,
-                     counts);
-  if (sign_export && sign_export != sign_words)
-    hipLaunchKernelGGL(sign_words_natural_kernel, dim3((unsigned)((nwords + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, s, stream_key(seed, kStreamSign), n_pad, sign_export);
-  hipLaunchKernelGGL(streams_offsets_kernel, dim3(1), dim3(kThreads), 0, s, nblocks, counts,
-                     offsets, r_cap, count, status);
-  hipLaunchKernelGGL(streams_write_rows_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, s,
-                     n_pad, kept_words, offsets, r_cap, rows);
+int64_t streams_blocks(int m) { return ((1ll << m) + kRowsPerBlock - 1) / kRowsPerBlock; }
+
+int launch_streams(const StreamJob& j, hipStream_t s) {
+  const unsigned nb = (unsigned)streams_blocks(j.m);
+  hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
+                     (const StreamJob*)nullptr, 1);
+  hipLaunchKernelGGL(streams_offsets_kernel<false>, dim3(1), dim3(kThreads), 0, s, j,
+                     (const StreamJob*)nullptr);
+  hipLaunchKernelGGL(streams_write_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
+                     (const StreamJob*)nullptr, 1);
+  return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs, hipStream_t s) {
+  if (njobs < 1) return RNNLS_OK;
+  const StreamJob& last = host[njobs - 1];
+  const unsigned nb = (unsigned)(last.blk0 + streams_blocks(last.m));
+  StreamJob none{};
+  hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
+                     njobs);
+  hipLaunchKernelGGL(streams_offsets_kernel<true>, dim3(njobs), dim3(kThreads), 0, s, none, dev);
+  hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
+                     njobs);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

@@ -33,6 +33,8 @@ void timer_begin(int which, hipStream_t s, void** token) {
   Registry& R = reg();
   std::lock_guard<std::mutex> lock(R.mu);
   if (!R.on) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   Pair p;
   if (!R.pool.empty()) {
     p = R.pool.back();

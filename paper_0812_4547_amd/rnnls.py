@@ -22,11 +22,14 @@ SOLVE_OK, SOLVE_MAX_ITER, SOLVE_KKT_FAIL, SOLVE_NO_ROWS, SOLVE_OVERFLOW = 0, 1, 
 SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
-MAX_D, MAX_R = 128, 32768
+MAX_D, MAX_R, MAX_K = 128, 32768, 4096
 
 EXPORTS = (
     "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
-    "rnnls_nnls_solve", "rnnls_rand_nnls", "rnnls_timing_enable", "rnnls_timing_read",
+    "rnnls_nnls_solve", "rnnls_rand_nnls", "rnnls_multi_workspace_bytes",
+    "rnnls_rand_nnls_multi", "rnnls_batch_workspace_bytes", "rnnls_batch_create",
+    "rnnls_batch_run", "rnnls_batch_autotune", "rnnls_batch_capture", "rnnls_batch_launch",
+    "rnnls_batch_destroy", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning",
 )
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE = 0, 1, 2
@@ -40,6 +43,14 @@ class Opts(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("srht_log_tile", ctypes.c_int32), ("srht_wgs_per_cu", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    """rnnls_problem: one problem of a batch (device pointers)."""
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("r", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("rnorm", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class RnnlsError(RuntimeError):
@@ -60,6 +71,16 @@ _SIGS = {
                          ctypes.c_int),
     "rnnls_rand_nnls": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
                          _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_multi_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
+    "rnnls_rand_nnls_multi": ([_i64, _i32, _i32, _i32, _u64, _p, _i64, _p, _i64, _p, _i64, _p,
+                               _p, _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_batch_workspace_bytes": ([_i32, _p, _p], _sz),
+    "rnnls_batch_create": ([_p, _i32, _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_batch_run": ([_p, _p], ctypes.c_int),
+    "rnnls_batch_autotune": ([_p, _p, _p], ctypes.c_int),
+    "rnnls_batch_capture": ([_p], ctypes.c_int),
+    "rnnls_batch_launch": ([_p, _p], ctypes.c_int),
+    "rnnls_batch_destroy": ([_p], ctypes.c_int),
     "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
     "rnnls_set_tuning": ([_p], ctypes.c_int),
@@ -235,6 +256,110 @@ def rand_nnls(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, opts: Opts | 
     _check(rc, "rnnls_rand_nnls")
     out.sketch = sk
     return out
+
+
+@dataclass
+class MultiSolution:
+    X: torch.Tensor       # float64 (d, k) column-major
+    rnorm: torch.Tensor   # float64 (k,)
+    iters: torch.Tensor   # int32 (k,)
+    status: torch.Tensor  # int32 (k,)
+
+
+def multi_workspace(n: int, d: int, k: int, r: int, opts: Opts | None = None, device="cuda"):
+    nbytes = int(load().rnnls_multi_workspace_bytes(n, d, k, r, ctypes.byref(opts or Opts())))
+    if nbytes == 0:
+        raise RnnlsError("invalid sizes for the workspace query")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def rand_nnls_multi(A: torch.Tensor, B: torch.Tensor, r: int, seed: int,
+                    opts: Opts | None = None, ws=None, out: MultiSolution | None = None,
+                    stream=None) -> MultiSolution:
+    """Algorithm 1 for k right-hand sides sharing A (rnnls_rand_nnls_multi)."""
+    opts = opts or Opts()
+    n, d = A.shape
+    k = B.shape[1]
+    lda = _check_colmajor(A, "A")
+    ldb = _check_colmajor(B, "B")
+    dev = A.device
+    if out is None:
+        out = MultiSolution(torch.empty((k, d), dtype=torch.float64, device=dev).t(),
+                            torch.empty(k, dtype=torch.float64, device=dev),
+                            torch.empty(k, dtype=torch.int32, device=dev),
+                            torch.empty(k, dtype=torch.int32, device=dev))
+    if ws is None:
+        ws = multi_workspace(n, d, k, r, opts, dev)
+    ldx = out.X.stride(1) if k > 1 else d
+    rc = load().rnnls_rand_nnls_multi(n, d, k, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(B), ldb,
+                                      _ptr(out.X), ldx, _ptr(out.rnorm), _ptr(out.iters),
+                                      _ptr(out.status), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                      _stream(stream))
+    _check(rc, "rnnls_rand_nnls_multi")
+    return out
+
+
+class Batch:
+    """A batch plan (rnnls_batch_*) over problems given as (A, b, r, seed)
+    with A column-major (n, d) and b (n,) on the device.  Owns the outputs
+    x[i] (float64 (d_i,)), rnorm, iters, status (one entry per problem) and
+    the workspace; keeps references to A and b for the plan's life."""
+
+    def __init__(self, problems, opts: Opts | None = None, device="cuda"):
+        self.opts = opts or Opts()
+        self._keep = []
+        count = len(problems)
+        self.x = []
+        self.rnorm = torch.empty(count, dtype=torch.float64, device=device)
+        self.iters = torch.empty(count, dtype=torch.int32, device=device)
+        self.status = torch.empty(count, dtype=torch.int32, device=device)
+        arr = (Problem * count)()
+        for i, (A, b, r, seed) in enumerate(problems):
+            n, d = A.shape
+            lda = _check_colmajor(A, "A")
+            x = torch.empty(d, dtype=torch.float64, device=device)
+            self.x.append(x)
+            self._keep.append((A, b))
+            arr[i] = Problem(n, d, r, seed & (2**64 - 1), A.data_ptr(), lda, b.data_ptr(),
+                             x.data_ptr(), self.rnorm[i:].data_ptr(), self.iters[i:].data_ptr(),
+                             self.status[i:].data_ptr())
+        self._arr = arr
+        lib = load()
+        nbytes = int(lib.rnnls_batch_workspace_bytes(count, arr, ctypes.byref(self.opts)))
+        if nbytes == 0:
+            raise RnnlsError("invalid batch for the workspace query")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._plan = ctypes.c_void_p()
+        bad = ctypes.c_int32(-1)
+        rc = lib.rnnls_batch_create(ctypes.byref(self._plan), count, arr, ctypes.byref(self.opts),
+                                    _ptr(self.ws), self.ws.numel(), ctypes.byref(bad))
+        _check(rc, f"rnnls_batch_create (problem {bad.value})")
+
+    def run(self, stream=None):
+        _check(load().rnnls_batch_run(self._plan, _stream(stream)), "rnnls_batch_run")
+
+    def autotune(self, stream=None) -> tuple[int, int]:
+        t = Tuning()
+        _check(load().rnnls_batch_autotune(self._plan, _stream(stream), ctypes.byref(t)),
+               "rnnls_batch_autotune")
+        return t.srht_log_tile, t.srht_wgs_per_cu
+
+    def capture(self):
+        _check(load().rnnls_batch_capture(self._plan), "rnnls_batch_capture")
+
+    def launch(self, stream=None):
+        _check(load().rnnls_batch_launch(self._plan, _stream(stream)), "rnnls_batch_launch")
+
+    def close(self):
+        if self._plan:
+            load().rnnls_batch_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True) -> None:
