@@ -262,6 +262,71 @@ int rnnls_batch_capture(rnnls_batch* plan);
 int rnnls_batch_launch(rnnls_batch* plan, void* stream);
 int rnnls_batch_destroy(rnnls_batch* plan);
 
+/* ---- learned passive-set proposals --------------------------------------
+ * A 3-layer perceptron maps per-column features of a sketched problem to the
+ * probability that the column is passive (x_j > 0) at the optimum; the
+ * proposal warm-starts Lawson-Hanson (the paper always starts from x = 0,
+ * Section 4.1), whose KKT certificate judges the result: a rejected warm
+ * start is replaced by a cold start from x = 0.
+ *
+ * Features of column j from the Gram form (G, q, c) of the sketched problem,
+ * C_jk = G_jk / sqrt(G_jj G_kk) (0 for a zero column):
+ *   f0 = q_j / sqrt(G_jj c); f1 = q_j / max|q|; f2 = (q_j - mean q) / std q;
+ *   f3 = mean_{k!=j} C_jk; f4 = max_{k!=j} C_jk; f5 = mean_{k!=j} C_jk f0_k;
+ *   f6 = log(G_jj / mean_k G_kk) clamped to [-30, 30]; f7 = d / 128.
+ * Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), p = sigmoid(w3.h2 + b3)
+ * with BF16 weights W1 (128x8), W2 (128x128), w3 (128), FP32 biases and FP32
+ * accumulation.  FP32 master parameters theta[RNNLS_MLP_PARAMS] in the order
+ * W1 (row-major), b1, W2 (row-major), b2, w3, b3; the BF16 copy
+ * wb[RNNLS_MLP_BF16_WEIGHTS] holds W1, W2, w3 rounded to nearest even.
+ * Training loss: mean binary cross-entropy with logits over the rows.
+ */
+#define RNNLS_MLP_FEATURES 8
+#define RNNLS_MLP_WIDTH 128
+#define RNNLS_MLP_PARAMS 17793
+#define RNNLS_MLP_BF16_WEIGHTS 17536
+#define RNNLS_MLP_MAX_ROWS (1 << 24)
+
+/* Features of one problem from its device Gram form: G (d x d, row-major
+ * FP64), q (d), c (1) -> X (d x 8 FP32, row-major). */
+int rnnls_features(int32_t d, const double* G, const double* q, const double* c, float* X,
+                   void* stream);
+/* wb <- bf16(theta's weights). */
+int rnnls_mlp_sync_bf16(const float* theta, uint16_t* wb, void* stream);
+/* prob[i] = p(X[i]) (nullable), flags[i] = prob > threshold (nullable). */
+int rnnls_mlp_forward(int64_t rows, const float* X, const float* theta, const uint16_t* wb,
+                      float* prob, uint8_t* flags, float threshold, void* stream);
+/* Workspace of rnnls_mlp_gradient / rnnls_mlp_train_step for `rows` rows. */
+size_t rnnls_mlp_workspace_bytes(int64_t rows);
+/* grad[RNNLS_MLP_PARAMS] = d loss / d theta (the BF16 weights are used in the
+ * forward pass; their gradient is applied to the FP32 master copy); loss[1]
+ * (nullable) = mean loss.  Deterministic (fixed-order reductions). */
+int rnnls_mlp_gradient(int64_t rows, const float* X, const uint8_t* y, const float* theta,
+                       const uint16_t* wb, float* grad, float* loss, void* ws,
+                       size_t ws_bytes, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on theta, refreshing wb. */
+int rnnls_mlp_adam(float* theta, uint16_t* wb, const float* grad, float* m, float* v,
+                   int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+/* Gradient + Adam (beta 0.9 / 0.999, eps 1e-8) on one mini-batch. */
+int rnnls_mlp_train_step(int64_t rows, const float* X, const uint8_t* y, float* theta,
+                         uint16_t* wb, float* m, float* v, int32_t step, float lr, float* loss,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Batch plans and the learned proposal:
+ * rnnls_batch_columns    total columns (sum of d) of the plan's problems
+ * rnnls_batch_features   X (columns x 8, problems in order) of the last pass
+ *                        and, if passive != NULL, its solutions' flags x_j > 0
+ * rnnls_batch_set_model  theta/wb (device, kept by the caller) warm-start
+ *                        every later pass from flags prob > threshold; NULL
+ *                        theta turns the warm start off
+ * rnnls_batch_warm_used  int32[count]: 1 where the last pass kept the warm start
+ */
+int rnnls_batch_columns(const rnnls_batch* plan, int64_t* columns);
+int rnnls_batch_features(rnnls_batch* plan, float* X, uint8_t* passive, void* stream);
+int rnnls_batch_set_model(rnnls_batch* plan, const float* theta, const uint16_t* wb,
+                          float threshold);
+int rnnls_batch_warm_used(rnnls_batch* plan, int32_t* out, void* stream);
+
 /* ---- launch tuning ------------------------------------------------------
  * Process-wide launch shape of the sketch kernel (all fields 0 = automatic).
  *  srht_log_tile   log2 of the rows one workgroup transforms at a time:

@@ -23,4 +23,6 @@ nnls         Lawson-Hanson active-set NNLS (Definition 1), KKT certificate,
 rand_nnls    Algorithm 1 end to end.
 diagnostics  realised subspace-embedding distortion (Lemma 1) and the
              row-norm flattening of Lemma 2, plus the proof chain of Theorem 1.
+learned      per-column features, the passive-set perceptron (forward, loss,
+             gradient, Adam step) of the learned warm start, in FP64.
 """

@@ -86,6 +86,16 @@ struct rnnls_batch {
   int l_max_d[2] = {0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // learned proposal
+  int64_t columns = 0;
+  std::vector<char> fjobs;  // FeatJob records
+  void* fdev = nullptr;
+  float* X = nullptr;
+  uint8_t* flags = nullptr;
+  int32_t* warm_used = nullptr;
+  const float* theta = nullptr;
+  const uint16_t* wb = nullptr;
+  float threshold = 0.5f;
 };
 
 namespace {
@@ -200,7 +210,11 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
-    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus);
+    {  // about 4 workgroups per CU over the whole batch
+      const MomentsPlan one = moments_plan(rcap[i], p.d, 1, B.cus);
+      const int64_t per = (4ll * B.cus + (int64_t)np * one.pairs - 1) / ((int64_t)np * one.pairs);
+      mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, (int)std::max<int64_t>(1, per));
+    }
     o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
     o_cnt[i] = put(off, sizeof(int32_t));
     o_st[i] = put(off, sizeof(int32_t));
@@ -228,11 +242,21 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
                   ? put(off, sizeof(double) * (size_t)(B.probs[i].d + 1) * (B.probs[i].d | 1))
                   : (size_t)-1;
   }
+  int64_t columns = 0;
+  for (int i = 0; i < np; ++i) columns += B.probs[i].d;
+  const size_t o_X = put(off, sizeof(float) * (size_t)columns * RNNLS_MLP_FEATURES);
+  const size_t o_fl = put(off, (size_t)columns);
+  const size_t o_wu = put(off, sizeof(int32_t) * (size_t)np);
   const size_t total = off;
   if (!ws) return total;
+  B.columns = columns;
+  B.X = at<float>(ws, o_X);
+  B.flags = at<uint8_t>(ws, o_fl);
+  B.warm_used = at<int32_t>(ws, o_wu);
+  B.fjobs.assign((size_t)np * feat_job_bytes(), 0);
 
   // fill pointers
-  int64_t blk0 = 0, chunk0 = 0, ent0 = 0;
+  int64_t blk0 = 0, chunk0 = 0, ent0 = 0, row0 = 0;
   int max_pairs = 0;
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
@@ -296,6 +320,11 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     lj.iters = p.iters;
     lj.status = p.status;
     lj.qp_global = o_qp[i] == (size_t)-1 ? nullptr : at<double>(ws, o_qp[i]);
+    lj.p0 = B.theta ? B.flags + row0 : nullptr;
+    lj.warm_used = B.warm_used + i;
+    make_feat_job(B.fjobs.data() + (size_t)i * feat_job_bytes(), mj.G, mj.Q, mj.c, p.x, p.d,
+                  row0);
+    row0 += p.d;
     const int h = p.d > 64;
     B.ljobs[h].push_back(lj);
     B.l_max_d[h] = std::max(B.l_max_d[h], p.d);
@@ -356,6 +385,8 @@ int plan(rnnls_batch& B, const Candidate& c) {
     o_l[h] = bytes;
     bytes += align256(sizeof(LhJob) * B.ljobs[h].size());
   }
+  const size_t o_f = bytes;
+  bytes += align256(B.fjobs.size());
   if (hipMalloc(&B.dev_tables, bytes) != hipSuccess) {
     B.dev_tables = nullptr;
     return RNNLS_E_HIP;
@@ -369,6 +400,7 @@ int plan(rnnls_batch& B, const Candidate& c) {
     copy(o_g[g], B.groups[g].jobs.data(), sizeof(SketchJob) * B.groups[g].jobs.size());
   copy(o_m, B.mjobs.data(), sizeof(MomentJob) * B.mjobs.size());
   for (int h = 0; h < 2; ++h) copy(o_l[h], B.ljobs[h].data(), sizeof(LhJob) * B.ljobs[h].size());
+  copy(o_f, B.fjobs.data(), B.fjobs.size());
   if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
     return RNNLS_E_HIP;
   char* base = static_cast<char*>(B.dev_tables);
@@ -377,6 +409,7 @@ int plan(rnnls_batch& B, const Candidate& c) {
     B.groups[g].dev = reinterpret_cast<SketchJob*>(base + o_g[g]);
   B.mdev = reinterpret_cast<MomentJob*>(base + o_m);
   for (int h = 0; h < 2; ++h) B.ldev[h] = reinterpret_cast<LhJob*>(base + o_l[h]);
+  B.fdev = base + o_f;
   B.tune = c;
   return RNNLS_OK;
 }
@@ -396,6 +429,12 @@ int run_all(rnnls_batch& B, hipStream_t s) {
   if (rc) return rc;
   rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.m_entries, s);
   if (rc) return rc;
+  if (B.theta) {  // learned proposal -> warm-start flags
+    rc = launch_features_batch(B.fdev, B.count, B.X, s);
+    if (rc) return rc;
+    rc = launch_mlp_forward(B.columns, B.X, B.theta, B.wb, nullptr, B.flags, B.threshold, s);
+    if (rc) return rc;
+  }
   for (int h = 0; h < 2; ++h) {
     rc = launch_lawson_hanson_batch(B.ldev[h], (int)B.ljobs[h].size(), B.l_max_d[h], s);
     if (rc) return rc;
@@ -564,6 +603,42 @@ int rnnls_batch_launch(rnnls_batch* B, void* stream) {
   if (!B) return -1;
   if (!B->exec) return RNNLS_E_UNSUPPORTED;
   return hipGraphLaunch(B->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? RNNLS_OK
+             : RNNLS_E_HIP;
+}
+
+int rnnls_batch_columns(const rnnls_batch* B, int64_t* columns) {
+  if (!B) return -1;
+  if (!columns) return -2;
+  *columns = B->columns;
+  return RNNLS_OK;
+}
+
+int rnnls_batch_features(rnnls_batch* B, float* X, uint8_t* passive, void* stream) {
+  if (!B) return -1;
+  if (!X) return -2;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = launch_features_batch(B->fdev, B->count, X, s);
+  if (rc == RNNLS_OK && passive) rc = launch_passive_flags(B->fdev, B->count, passive, s);
+  return rc;
+}
+
+int rnnls_batch_set_model(rnnls_batch* B, const float* theta, const uint16_t* wb,
+                          float threshold) {
+  if (!B) return -1;
+  if (theta && !wb) return -3;
+  if (!(threshold > 0.0f && threshold < 1.0f)) return -4;
+  B->theta = theta;
+  B->wb = wb;
+  B->threshold = threshold;
+  return plan(*B, B->tune);  // the Lawson-Hanson descriptors gain or lose p0
+}
+
+int rnnls_batch_warm_used(rnnls_batch* B, int32_t* out, void* stream) {
+  if (!B) return -1;
+  if (!out) return -2;
+  return hipMemcpyAsync(out, B->warm_used, sizeof(int32_t) * B->count, hipMemcpyDeviceToDevice,
+                        reinterpret_cast<hipStream_t>(stream)) == hipSuccess
              ? RNNLS_OK
              : RNNLS_E_HIP;
 }

@@ -177,6 +177,9 @@ struct LhJob {
   int32_t* iters;   // nullable, stride 1
   int32_t* status;  // nullable, stride 1
   double* qp_global;  // lh_matrix_words per problem when Q[:,P] is not in LDS
+  const uint8_t* p0;  // nullable: proposed passive set (d flags) for a warm start
+  int64_t p0_stride;
+  int32_t* warm_used;  // nullable, stride 1: 1 if the warm start was kept
 };
 
 // ---------------------------------------------------------------- launchers
@@ -226,7 +229,8 @@ struct MomentsPlan {
   int d, k;
   int chunks, nbA, nb, pairs;
 };
-MomentsPlan moments_plan(int64_t m, int d, int k, int cus);
+// max_chunks > 0 caps the row chunks (batches spread over problems instead)
+MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);
 size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
 int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
@@ -238,6 +242,16 @@ bool lh_qp_in_lds(int d);
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);
 // every job of a batch has d <= max_d, one problem each
 int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s);
+
+// Learned proposals (learned.hip).  Feature jobs are opaque records of
+// feat_job_bytes() bytes built by make_feat_job.
+size_t feat_job_bytes();
+void make_feat_job(void* out, const double* G, const double* q, const double* c,
+                   const double* x, int d, int64_t row0);
+int launch_features_batch(const void* jobs, int njobs, float* X, hipStream_t s);
+int launch_passive_flags(const void* jobs, int njobs, uint8_t* flags, hipStream_t s);
+int launch_mlp_forward(int64_t rows, const float* X, const float* theta, const uint16_t* wb,
+                       float* prob, uint8_t* flags, float threshold, hipStream_t s);
 
 int device_cus();
 

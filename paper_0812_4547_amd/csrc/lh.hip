@@ -342,241 +342,314 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
   double z[H];
   // column-distributed state
   int cslot[H];    // slot of a column, -1 if not passive
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    scol[h] = -1;
-    xs[h] = 0.0;
-    z[h] = 0.0;
-    cslot[h] = -1;
-  }
   int hwm = 0, np = 0, iters = 0;
   int status = RNNLS_SOLVE_OK;
 
-  for (;;) {
-    // ---- outer step: w = q - QP x_P
-    double w[H];
-    stage(vb, xs);
-    mv(qrow, vb, hwm, w);
-#pragma unroll
-    for (int h = 0; h < H; ++h) w[h] = (valid[h] ? qs[lane + h * kW] : 0.0) - w[h];
-    bool refused[H];
-#pragma unroll
-    for (int h = 0; h < H; ++h) refused[h] = false;
-    int t = -1;
-    double u[H], g[H], qnew[H], zt = 0.0, sval = 0.0, sinv = 0.0;
-    for (;;) {
-      bool cand[H];
-#pragma unroll
-      for (int h = 0; h < H; ++h) cand[h] = valid[h] && cslot[h] < 0 && !refused[h];
-      double best;
-      const int bidx = uni(wave_arg<true>(w, cand, best));
-      if (bidx == kNone || !(best > tau)) break;
-      // the entering column of Q (read from global memory now, used when
-      // QP gains it, so its latency overlaps the candidate test)
-#pragma unroll
-      for (int h = 0; h < H; ++h) qnew[h] = valid[h] ? Qg[(int64_t)bidx * d + lane + h * kW] : 0.0;
-      // candidate: g = Q[P, t] = QP[t][slot], u = B g, Schur complement s,
-      // coefficient z_t
-#pragma unroll
-      for (int h = 0; h < H; ++h) g[h] = valid[h] ? QP[bidx * ld + lane + h * kW] : 0.0;
-      stage(vb, g);
-      const double qtt = uni(dq[bidx]);
-      const double qt = uni(qs[bidx]);
-      mv(brow, vb, hwm, u);
-      double gu = 0.0, gx = 0.0;
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        gu += g[h] * u[h];
-        gx += g[h] * xs[h];
-      }
-      wave_sum2(gu, gx);
-      sval = uni(qtt - gu);
-      sinv = uni(1.0 / sval);
-      zt = uni((qt - gx) * sinv);
-      if (!((sval > kDependence * qtt) && (zt > 0.0))) {
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (lane + h * kW == bidx) refused[h] = true;
-        continue;
-      }
-      t = bidx;
-      break;
-    }
-    if (t < 0) break;
-    if (iters >= max_iter) {
-      status = RNNLS_SOLVE_MAX_ITER;
-      break;
-    }
-    ++iters;
-    // ---- border B with t in the lowest free slot j; QP gains column t
+  // Border B with column t (u = B g, g = Q[P, t], sinv = 1 / Schur
+  // complement) in the lowest free slot; QP gains column t (qnew = Q[:, t]).
+  auto border = [&](int t, const double (&u)[H], const double (&qnew)[H], double sinv) {
     const uint64_t free0 = __ballot(scol[0] < 0 && valid[0]);
     const uint64_t free1 = H == 2 ? __ballot(scol[H - 1] < 0 && valid[H - 1]) : 0ull;
     const int j = uni(free0 ? __ffsll((unsigned long long)free0) - 1
                             : kW + __ffsll((unsigned long long)free1) - 1);
-    {
-      const double inv = sinv;
-      double ua[H];
+    double ua[H];
 #pragma unroll
-      for (int h = 0; h < H; ++h) ua[h] = u[h] * inv;
-      stage(vb, u);  // u is zero on free slots and on slot j
-      rank1(brow, ua, vb, hwm);
-      lh_sync<QPG>();
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int s = lane + h * kW;
-        if (valid[h] && s != j) {
-          Bs[s * ld + j] = -ua[h];
-          Bs[j * ld + s] = -ua[h];
-        }
-        if (valid[h]) QP[s * ld + j] = qnew[h];
-      }
-      if (lane == 0) Bs[j * ld + j] = inv;
-    }
+    for (int h = 0; h < H; ++h) ua[h] = u[h] * sinv;
+    stage(vb, u);  // u is zero on free slots and on slot j
+    rank1(brow, ua, vb, hwm);
+    lh_sync<QPG>();
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const int s = lane + h * kW;
-      z[h] = (scol[h] >= 0) ? xs[h] - u[h] * zt : 0.0;
-      if (s == j) {
-        z[h] = zt;
-        scol[h] = t;
+      if (valid[h] && s != j) {
+        Bs[s * ld + j] = -ua[h];
+        Bs[j * ld + s] = -ua[h];
       }
+      if (valid[h]) QP[s * ld + j] = qnew[h];
+    }
+    if (lane == 0) Bs[j * ld + j] = sinv;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int s = lane + h * kW;
+      if (s == j) scol[h] = t;
       if (s == t) cslot[h] = j;
     }
     hwm = uni(j + 1 > hwm ? j + 1 : hwm);
     ++np;
     lh_sync<QPG>();
-    // ---- inner loop
-    for (;;) {
-      bool allpos = true;
-#pragma unroll
-      for (int h = 0; h < H; ++h)
-        if (scol[h] >= 0 && !(z[h] > 0.0)) allpos = false;
-      if (wave_all(allpos)) {
-#pragma unroll
-        for (int h = 0; h < H; ++h) xs[h] = z[h];
-        break;
-      }
-      double rat[H];
-      bool neg[H];
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        neg[h] = scol[h] >= 0 && !(z[h] > 0.0);
-        const double den = xs[h] - z[h];
-        rat[h] = den > 0.0 ? xs[h] / den : 0.0;
-      }
-      double ratio;
-      const int ridx = uni(wave_arg<false>(rat, neg, ratio));
-      // non-finite data can leave no valid ratio: then stay put and drop every
-      // nonpositive coefficient, so each pass removes at least one index
-      const bool stuck = (ridx == kNone);
-      const double alpha = stuck ? 0.0 : ratio;
-      bool drop[H];
+    return j;
+  };
+
+  // Remove the slots flagged in (m0, m1): B <- B - b b^T / b_jj with
+  // b = B[:, jd], then clear row and column jd of B and column jd of QP.
+  auto drop_slots = [&](uint64_t m0, uint64_t m1) {
+    while (m0 | m1) {
+      const int jd = uni(m0 ? __ffsll((unsigned long long)m0) - 1
+                            : kW + __ffsll((unsigned long long)m1) - 1);
+      if (jd < kW) m0 &= m0 - 1; else m1 &= m1 - 1;
+      const double bjj = uni(Bs[jd * ld + jd]);
+      double bvec[H], ba[H];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int s = lane + h * kW;
-        drop[h] = false;
-        if (scol[h] >= 0) {
-          const double xn = xs[h] + alpha * (z[h] - xs[h]);
-          drop[h] = (s == ridx) || !(xn > tau) || (stuck && !(z[h] > 0.0));
-          xs[h] = drop[h] ? 0.0 : xn;
-        }
+        bvec[h] = (valid[h] && s != jd) ? brow[h][jd] : 0.0;
+        ba[h] = -bvec[h] / bjj;
       }
-      uint64_t m0 = __ballot(drop[0]);
-      uint64_t m1 = H == 2 ? __ballot(drop[H - 1]) : 0ull;
-      while (m0 | m1) {
-        const int jd = uni(m0 ? __ffsll((unsigned long long)m0) - 1
-                              : kW + __ffsll((unsigned long long)m1) - 1);
-        if (jd < kW) m0 &= m0 - 1; else m1 &= m1 - 1;
-        // downdate: B <- B - b b^T / b_jj with b = B[:, jd], then clear jd
-        const double bjj = uni(Bs[jd * ld + jd]);
-        double bvec[H], ba[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const int s = lane + h * kW;
-          bvec[h] = (valid[h] && s != jd) ? brow[h][jd] : 0.0;
-          ba[h] = -bvec[h] / bjj;
-        }
-        stage(vb, bvec);
-        rank1(brow, ba, vb, hwm);
-        lh_sync<QPG>();
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const int s = lane + h * kW;
-          if (valid[h]) {
-            Bs[s * ld + jd] = 0.0;
-            Bs[jd * ld + s] = 0.0;
-            QP[s * ld + jd] = 0.0;
-          }
-        }
-        const int col = uni(bcast(scol, jd));
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          if (lane + h * kW == jd) {
-            scol[h] = -1;
-            xs[h] = 0.0;
-          }
-          if (lane + h * kW == col) cslot[h] = -1;
-        }
-        --np;
-        lh_sync<QPG>();
-      }
-      while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
-      hwm = uni(hwm);
-      if (np == 0) break;
-      // z = B q_P, then z += B (q_P - Q[P,P] z)
-      double qp[H], r[H], dz[H];
-      const double* prow[H];
+      stage(vb, bvec);
+      rank1(brow, ba, vb, hwm);
+      lh_sync<QPG>();
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        qp[h] = scol[h] >= 0 ? qs[scol[h]] : 0.0;
-        prow[h] = QP + (scol[h] >= 0 ? scol[h] : d) * ld;
+        const int s = lane + h * kW;
+        if (valid[h]) {
+          Bs[s * ld + jd] = 0.0;
+          Bs[jd * ld + s] = 0.0;
+          QP[s * ld + jd] = 0.0;
+        }
       }
-      stage(vb, qp);
-      mv(brow, vb, hwm, z);
+      const int col = uni(bcast(scol, jd));
 #pragma unroll
-      for (int h = 0; h < H; ++h)
-        if (scol[h] < 0) z[h] = 0.0;
-      stage(vb, z);
-      mv(prow, vb, hwm, r);
-#pragma unroll
-      for (int h = 0; h < H; ++h) r[h] = scol[h] >= 0 ? qp[h] - r[h] : 0.0;
-      stage(vb, r);
-      mv(brow, vb, hwm, dz);
-#pragma unroll
-      for (int h = 0; h < H; ++h) z[h] += dz[h];
+      for (int h = 0; h < H; ++h) {
+        if (lane + h * kW == jd) {
+          scol[h] = -1;
+          xs[h] = 0.0;
+        }
+        if (lane + h * kW == col) cslot[h] = -1;
+      }
+      --np;
+      lh_sync<QPG>();
     }
-  }
+    while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
+    hwm = uni(hwm);
+  };
 
-  // ---- certificate and outputs: x by column through LDS
+  // z = B q_P, then one refinement step z += B (q_P - Q[P,P] z)
+  auto solve_z = [&]() {
+    double qp[H], r[H], dz[H];
+    const double* prow[H];
 #pragma unroll
-  for (int h = 0; h < H; ++h)
-    if (scol[h] >= 0) xcol[scol[h]] = xs[h];
-  double wf[H];
-  stage(vb, xs);
-  mv(qrow, vb, hwm, wf);
+    for (int h = 0; h < H; ++h) {
+      qp[h] = scol[h] >= 0 ? qs[scol[h]] : 0.0;
+      prow[h] = QP + (scol[h] >= 0 ? scol[h] : d) * ld;
+    }
+    stage(vb, qp);
+    mv(brow, vb, hwm, z);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if (scol[h] < 0) z[h] = 0.0;
+    stage(vb, z);
+    mv(prow, vb, hwm, r);
+#pragma unroll
+    for (int h = 0; h < H; ++h) r[h] = scol[h] >= 0 ? qp[h] - r[h] : 0.0;
+    stage(vb, r);
+    mv(brow, vb, hwm, dz);
+#pragma unroll
+    for (int h = 0; h < H; ++h) z[h] += dz[h];
+  };
+
+  // A proposed passive set (warm start) is tried first; its result must pass
+  // the KKT certificate, else a cold start from x = 0 replaces it.
+  const uint8_t* p0 = J.p0 ? J.p0 + sub * J.p0_stride : nullptr;
+  int warm = p0 ? 1 : 0;
+  int total_iters = 0;
   bool ok = true;
   double xq = 0.0, xw = 0.0;
+  for (;;) {
 #pragma unroll
-  for (int h = 0; h < H; ++h) {
-    const int col = lane + h * kW;
-    if (valid[h]) {
-      const double acc = qs[col] - wf[h];
-      const double xj = xcol[col];
-      if (xj < 0.0) ok = false;
-      if (xj > 0.0) {
-        if (!(fabs(acc) <= 1e3 * tau)) ok = false;
-      } else if (!(acc <= tau)) {
-        ok = false;
-      }
-      xq += xj * qs[col];
-      xw += xj * acc;
-      x_out[col] = xj;
-      if (w_out) w_out[col] = acc;
+    for (int h = 0; h < H; ++h) {
+      scol[h] = -1;
+      xs[h] = 0.0;
+      z[h] = 0.0;
+      cslot[h] = -1;
     }
+    hwm = np = iters = 0;
+    status = RNNLS_SOLVE_OK;
+
+    if (warm) {
+      // ---- warm start: border every proposed column (skipping dependent
+      // ones), then drop nonpositive coefficients until z > 0 on P
+      for (int t = 0; t < d; ++t) {
+        if (!p0[t]) continue;
+        double g[H], u[H], qnew[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          g[h] = valid[h] ? QP[t * ld + lane + h * kW] : 0.0;
+          qnew[h] = valid[h] ? Qg[(int64_t)t * d + lane + h * kW] : 0.0;
+        }
+        stage(vb, g);
+        mv(brow, vb, hwm, u);
+        double gu = 0.0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) gu += g[h] * u[h];
+        const double qtt = uni(dq[t]);
+        const double sval = uni(qtt - wave_sum(gu));
+        if (!(sval > kDependence * qtt)) continue;
+        border(t, u, qnew, uni(1.0 / sval));
+      }
+      while (np > 0) {
+        solve_z();
+        bool drop[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) drop[h] = scol[h] >= 0 && !(z[h] > 0.0);
+        const uint64_t m0 = __ballot(drop[0]);
+        const uint64_t m1 = H == 2 ? __ballot(drop[H - 1]) : 0ull;
+        if (!(m0 | m1)) break;
+        drop_slots(m0, m1);
+      }
+#pragma unroll
+      for (int h = 0; h < H; ++h) xs[h] = scol[h] >= 0 ? z[h] : 0.0;
+    }
+
+    for (;;) {
+      // ---- outer step: w = q - QP x_P
+      double w[H];
+      stage(vb, xs);
+      mv(qrow, vb, hwm, w);
+#pragma unroll
+      for (int h = 0; h < H; ++h) w[h] = (valid[h] ? qs[lane + h * kW] : 0.0) - w[h];
+      bool refused[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) refused[h] = false;
+      int t = -1;
+      double u[H], g[H], qnew[H], zt = 0.0, sval = 0.0, sinv = 0.0;
+      for (;;) {
+        bool cand[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) cand[h] = valid[h] && cslot[h] < 0 && !refused[h];
+        double best;
+        const int bidx = uni(wave_arg<true>(w, cand, best));
+        if (bidx == kNone || !(best > tau)) break;
+        // the entering column of Q (read from global memory now, used when
+        // QP gains it, so its latency overlaps the candidate test)
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          qnew[h] = valid[h] ? Qg[(int64_t)bidx * d + lane + h * kW] : 0.0;
+        // candidate: g = Q[P, t] = QP[t][slot], u = B g, Schur complement s,
+        // coefficient z_t
+#pragma unroll
+        for (int h = 0; h < H; ++h) g[h] = valid[h] ? QP[bidx * ld + lane + h * kW] : 0.0;
+        stage(vb, g);
+        const double qtt = uni(dq[bidx]);
+        const double qt = uni(qs[bidx]);
+        mv(brow, vb, hwm, u);
+        double gu = 0.0, gx = 0.0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          gu += g[h] * u[h];
+          gx += g[h] * xs[h];
+        }
+        wave_sum2(gu, gx);
+        sval = uni(qtt - gu);
+        sinv = uni(1.0 / sval);
+        zt = uni((qt - gx) * sinv);
+        if (!((sval > kDependence * qtt) && (zt > 0.0))) {
+#pragma unroll
+          for (int h = 0; h < H; ++h)
+            if (lane + h * kW == bidx) refused[h] = true;
+          continue;
+        }
+        t = bidx;
+        break;
+      }
+      if (t < 0) break;
+      if (iters >= max_iter) {
+        status = RNNLS_SOLVE_MAX_ITER;
+        break;
+      }
+      ++iters;
+      // ---- border B with t; z = (x_P - u z_t, z_t)
+#pragma unroll
+      for (int h = 0; h < H; ++h) z[h] = (scol[h] >= 0) ? xs[h] - u[h] * zt : 0.0;
+      const int j = border(t, u, qnew, sinv);
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        if (lane + h * kW == j) z[h] = zt;
+      // ---- inner loop
+      for (;;) {
+        bool allpos = true;
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          if (scol[h] >= 0 && !(z[h] > 0.0)) allpos = false;
+        if (wave_all(allpos)) {
+#pragma unroll
+          for (int h = 0; h < H; ++h) xs[h] = z[h];
+          break;
+        }
+        double rat[H];
+        bool neg[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          neg[h] = scol[h] >= 0 && !(z[h] > 0.0);
+          const double den = xs[h] - z[h];
+          rat[h] = den > 0.0 ? xs[h] / den : 0.0;
+        }
+        double ratio;
+        const int ridx = uni(wave_arg<false>(rat, neg, ratio));
+        // non-finite data can leave no valid ratio: then stay put and drop
+        // every nonpositive coefficient, so each pass removes at least one index
+        const bool stuck = (ridx == kNone);
+        const double alpha = stuck ? 0.0 : ratio;
+        bool drop[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const int s = lane + h * kW;
+          drop[h] = false;
+          if (scol[h] >= 0) {
+            const double xn = xs[h] + alpha * (z[h] - xs[h]);
+            drop[h] = (s == ridx) || !(xn > tau) || (stuck && !(z[h] > 0.0));
+            xs[h] = drop[h] ? 0.0 : xn;
+          }
+        }
+        drop_slots(__ballot(drop[0]), H == 2 ? __ballot(drop[H - 1]) : 0ull);
+        if (np == 0) break;
+        solve_z();
+      }
+    }
+
+    // ---- certificate: x by column through LDS, w = q - Q x
+    for (int j = lane; j < d; j += kW) xcol[j] = 0.0;
+    lh_sync<false>();
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if (scol[h] >= 0) xcol[scol[h]] = xs[h];
+    double wf[H];
+    stage(vb, xs);
+    mv(qrow, vb, hwm, wf);
+    ok = true;
+    xq = 0.0;
+    xw = 0.0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int col = lane + h * kW;
+      if (valid[h]) {
+        const double acc = qs[col] - wf[h];
+        const double xj = xcol[col];
+        if (xj < 0.0) ok = false;
+        if (xj > 0.0) {
+          if (!(fabs(acc) <= 1e3 * tau)) ok = false;
+        } else if (!(acc <= tau)) {
+          ok = false;
+        }
+        xq += xj * qs[col];
+        xw += xj * acc;
+        x_out[col] = xj;
+        if (w_out) w_out[col] = acc;
+      }
+    }
+    ok = wave_all(ok);
+    xq = wave_sum(xq);
+    xw = wave_sum(xw);
+    total_iters += iters;
+    if (!warm || (ok && status == RNNLS_SOLVE_OK)) break;
+    // the warm start failed its certificate: clear B and QP, start cold
+    warm = 0;
+    lh_sync<QPG>();
+    for (int e = lane; e < mw; e += kW) {
+      Bs[e] = 0.0;
+      QP[e] = 0.0;
+    }
+    lh_sync<QPG>();
   }
-  ok = wave_all(ok);
-  xq = wave_sum(xq);
-  xw = wave_sum(xw);
   if (lane == 0) {
     if (status == RNNLS_SOLVE_OK && !ok) status = RNNLS_SOLVE_KKT_FAIL;
     if (J.pre_status) {
@@ -585,8 +658,9 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
     }
     const double r2 = c - xq - xw;
     if (J.rnorm) J.rnorm[sub] = sqrt(r2 > 0.0 ? r2 : 0.0);
-    if (J.iters) J.iters[sub] = iters;
+    if (J.iters) J.iters[sub] = total_iters;
     if (J.status) J.status[sub] = status;
+    if (J.warm_used) J.warm_used[sub] = warm;
   }
 }
 

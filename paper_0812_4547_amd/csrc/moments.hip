@@ -11,8 +11,7 @@
 // of 256 threads (2 x 2 register tile each) computes one such block over one
 // chunk of rows staged in LDS 64 at a time, so even a 4096-row sketch spreads
 // over hundreds of workgroups.  The per-chunk partials are then summed in a
-// fixed order (one wavefront per entry, fixed lane assignment and shuffle
-// tree: deterministic).
+// fixed order (one thread per entry: deterministic).
 //
 // One problem travels by value in the kernel arguments; a batch of problems
 // (different m, d) reads its descriptors from a device table.
@@ -122,16 +121,16 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const 
   }
 }
 
-// One wavefront per output entry: lanes take chunks lane, lane+64, ... in
-// order, then a fixed shuffle tree.  Entry e < pairs*1024 is element
-// (e/32 % 32, e % 32) of block pair e/1024; the next d are column 1-norms.
+// One thread per output entry, summing the chunks in order (deterministic;
+// consecutive threads read consecutive entries of each chunk).  Entry
+// e < pairs*1024 is element (e/32 % 32, e % 32) of block pair e/1024; the
+// next d are column 1-norms.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const MomentJob* jobs,
                                                           int njobs) {
-  const int64_t eg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t eg = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t e64;
   const MomentJob& J = mjob<BATCH>(one, jobs, njobs, eg, &MomentJob::ent0, e64);
-  const int lane = threadIdx.x & 63;
   const int nblk = J.pairs * kBlk * kBlk;
   if (e64 >= nblk + J.d) return;
   const int e = (int)e64;
@@ -142,22 +141,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const M
     pair_blocks(e / (kBlk * kBlk), J.nbA, J.nb, bi, bj);
     i = bi * kBlk + (e / kBlk) % kBlk;
     j = bj * kBlk + e % kBlk;
-    if (i > j || j >= D1) return;  // the whole wavefront leaves together
+    if (i > j || j >= D1) return;
     if (j < J.d) kind = 0;
     else if (i < J.d) kind = 1;
     else if (i == j) kind = 2;
     else return;
   }
+  const double* src = kind != 3 ? J.part + e : J.part_abs + (e - nblk);
+  const int64_t stride = kind != 3 ? nblk : J.d;
   double s = 0.0;
-  if (kind != 3) {
-    for (int c = lane; c < J.chunks; c += 64) s += J.part[(int64_t)c * nblk + e];
-  } else {
-    const int col = e - nblk;
-    for (int c = lane; c < J.chunks; c += 64) s += J.part_abs[(int64_t)c * J.d + col];
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane != 0) return;
+#pragma unroll 8
+  for (int c = 0; c < J.chunks; ++c) s += src[(int64_t)c * stride];
   switch (kind) {
     case 0:
       J.G[(int64_t)i * J.d + j] = s;
@@ -171,7 +165,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const M
 
 }  // namespace
 
-MomentsPlan moments_plan(int64_t m, int d, int k, int cus) {
+MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   MomentsPlan p;
   p.m = m;
   p.d = d;
@@ -180,7 +174,8 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus) {
   p.nb = (d + k + kBlk - 1) / kBlk;
   p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
   const int64_t want = (m + kRows - 1) / kRows;
-  const int64_t cap = 2 * (int64_t)cus;
+  int64_t cap = 2 * (int64_t)cus;
+  if (max_chunks > 0 && max_chunks < cap) cap = max_chunks;
   p.chunks = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
   return p;
 }
@@ -204,7 +199,7 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   hipLaunchKernelGGL(gram_partial_kernel<false>, dim3(p.chunks, p.pairs), dim3(256), 0, s, j,
                      (const MomentJob*)nullptr, 1);
   const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
-  hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 3) / 4)), dim3(256), 0, s,
+  hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s,
                      j, (const MomentJob*)nullptr, 1);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
@@ -218,7 +213,7 @@ int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int ma
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)chunks, (unsigned)max_pairs),
                      dim3(256), 0, s, none, dev, njobs);
-  hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)((entries + 3) / 4)), dim3(256), 0,
+  hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0,
                      s, none, dev, njobs);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;

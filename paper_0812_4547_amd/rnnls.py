@@ -29,9 +29,13 @@ EXPORTS = (
     "rnnls_nnls_solve", "rnnls_rand_nnls", "rnnls_multi_workspace_bytes",
     "rnnls_rand_nnls_multi", "rnnls_batch_workspace_bytes", "rnnls_batch_create",
     "rnnls_batch_run", "rnnls_batch_autotune", "rnnls_batch_capture", "rnnls_batch_launch",
-    "rnnls_batch_destroy", "rnnls_timing_enable", "rnnls_timing_read",
+    "rnnls_batch_destroy", "rnnls_features", "rnnls_mlp_sync_bf16", "rnnls_mlp_forward",
+    "rnnls_mlp_workspace_bytes", "rnnls_mlp_gradient", "rnnls_mlp_adam", "rnnls_mlp_train_step",
+    "rnnls_batch_columns", "rnnls_batch_features", "rnnls_batch_set_model",
+    "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning",
 )
+MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE = 0, 1, 2
 
 
@@ -81,6 +85,19 @@ _SIGS = {
     "rnnls_batch_capture": ([_p], ctypes.c_int),
     "rnnls_batch_launch": ([_p, _p], ctypes.c_int),
     "rnnls_batch_destroy": ([_p], ctypes.c_int),
+    "rnnls_features": ([_i32, _p, _p, _p, _p, _p], ctypes.c_int),
+    "rnnls_mlp_sync_bf16": ([_p, _p, _p], ctypes.c_int),
+    "rnnls_mlp_forward": ([_i64, _p, _p, _p, _p, _p, ctypes.c_float, _p], ctypes.c_int),
+    "rnnls_mlp_workspace_bytes": ([_i64], _sz),
+    "rnnls_mlp_gradient": ([_i64, _p, _p, _p, _p, _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_mlp_adam": ([_p, _p, _p, _p, _p, _i32, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, ctypes.c_float, _p], ctypes.c_int),
+    "rnnls_mlp_train_step": ([_i64, _p, _p, _p, _p, _p, _p, _i32, ctypes.c_float, _p, _p, _sz,
+                              _p], ctypes.c_int),
+    "rnnls_batch_columns": ([_p, _p], ctypes.c_int),
+    "rnnls_batch_features": ([_p, _p, _p, _p], ctypes.c_int),
+    "rnnls_batch_set_model": ([_p, _p, _p, ctypes.c_float], ctypes.c_int),
+    "rnnls_batch_warm_used": ([_p, _p, _p], ctypes.c_int),
     "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
     "rnnls_set_tuning": ([_p], ctypes.c_int),
@@ -325,12 +342,14 @@ class Batch:
                              self.status[i:].data_ptr())
         self._arr = arr
         lib = load()
-        nbytes = int(lib.rnnls_batch_workspace_bytes(count, arr, ctypes.byref(self.opts)))
-        if nbytes == 0:
-            raise RnnlsError("invalid batch for the workspace query")
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self._plan = ctypes.c_void_p()
         bad = ctypes.c_int32(-1)
+        nbytes = int(lib.rnnls_batch_workspace_bytes(count, arr, ctypes.byref(self.opts)))
+        if nbytes == 0:  # let the library name the invalid argument / problem
+            rc = lib.rnnls_batch_create(ctypes.byref(self._plan), count, arr,
+                                        ctypes.byref(self.opts), None, 0, ctypes.byref(bad))
+            raise RnnlsError(f"rnnls_batch_create (problem {bad.value}) returned {rc}")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         rc = lib.rnnls_batch_create(ctypes.byref(self._plan), count, arr, ctypes.byref(self.opts),
                                     _ptr(self.ws), self.ws.numel(), ctypes.byref(bad))
         _check(rc, f"rnnls_batch_create (problem {bad.value})")
@@ -350,6 +369,36 @@ class Batch:
     def launch(self, stream=None):
         _check(load().rnnls_batch_launch(self._plan, _stream(stream)), "rnnls_batch_launch")
 
+    def columns(self) -> int:
+        n = ctypes.c_int64(0)
+        _check(load().rnnls_batch_columns(self._plan, ctypes.byref(n)), "rnnls_batch_columns")
+        return int(n.value)
+
+    def features(self, with_passive: bool = True, stream=None):
+        """(X (columns, 8) float32, passive flags (columns,) uint8 or None) of
+        the last pass, problems in order."""
+        cols = self.columns()
+        dev = self.rnorm.device
+        X = torch.empty((cols, MLP_FEATURES), dtype=torch.float32, device=dev)
+        y = torch.empty(cols, dtype=torch.uint8, device=dev) if with_passive else None
+        _check(load().rnnls_batch_features(self._plan, _ptr(X), _ptr(y), _stream(stream)),
+               "rnnls_batch_features")
+        return X, y
+
+    def set_model(self, mlp, threshold: float = 0.5):
+        """Warm-start later passes from the perceptron `mlp` (None: cold)."""
+        self._mlp = mlp
+        theta = _ptr(mlp.theta) if mlp is not None else None
+        wb = _ptr(mlp.wb) if mlp is not None else None
+        _check(load().rnnls_batch_set_model(self._plan, theta, wb, float(threshold)),
+               "rnnls_batch_set_model")
+
+    def warm_used(self, stream=None) -> torch.Tensor:
+        out = torch.empty(len(self.x), dtype=torch.int32, device=self.rnorm.device)
+        _check(load().rnnls_batch_warm_used(self._plan, _ptr(out), _stream(stream)),
+               "rnnls_batch_warm_used")
+        return out
+
     def close(self):
         if self._plan:
             load().rnnls_batch_destroy(self._plan)
@@ -360,6 +409,74 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def features(G: torch.Tensor, q: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:
+    """Per-column features (d, 8) of one problem from its device Gram form."""
+    d = q.numel()
+    X = torch.empty((d, MLP_FEATURES), dtype=torch.float32, device=q.device)
+    _check(load().rnnls_features(d, _ptr(G.contiguous()), _ptr(q), _ptr(c), _ptr(X),
+                                 _stream(stream)), "rnnls_features")
+    return X
+
+
+class Mlp:
+    """Device parameters of the passive-set perceptron: FP32 master theta,
+    BF16 copy wb of the weights, Adam moments m, v."""
+
+    def __init__(self, theta: torch.Tensor):
+        assert theta.numel() == MLP_PARAMS and theta.dtype == torch.float32 and theta.is_cuda
+        self.theta = theta.contiguous()
+        self.wb = torch.empty(MLP_BF16_WEIGHTS, dtype=torch.int16, device=theta.device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.step = 0
+        self._ws = None
+        _check(load().rnnls_mlp_sync_bf16(_ptr(self.theta), _ptr(self.wb),
+                                          _stream(None)), "rnnls_mlp_sync_bf16")
+
+    def _workspace(self, rows):
+        need = int(load().rnnls_mlp_workspace_bytes(rows))
+        if need == 0:
+            raise RnnlsError("invalid row count")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.theta.device)
+        return self._ws
+
+    def forward(self, X: torch.Tensor, threshold: float = 0.5, stream=None):
+        rows = X.shape[0]
+        prob = torch.empty(rows, dtype=torch.float32, device=X.device)
+        flags = torch.empty(rows, dtype=torch.uint8, device=X.device)
+        _check(load().rnnls_mlp_forward(rows, _ptr(X.contiguous()), _ptr(self.theta),
+                                        _ptr(self.wb), _ptr(prob), _ptr(flags),
+                                        float(threshold), _stream(stream)), "rnnls_mlp_forward")
+        return prob, flags
+
+    def gradient(self, X: torch.Tensor, y: torch.Tensor, stream=None):
+        rows = X.shape[0]
+        ws = self._workspace(rows)
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(load().rnnls_mlp_gradient(rows, _ptr(X.contiguous()), _ptr(y.contiguous()),
+                                         _ptr(self.theta), _ptr(self.wb), _ptr(grad), _ptr(loss),
+                                         _ptr(ws), ws.numel(), _stream(stream)),
+               "rnnls_mlp_gradient")
+        return grad, loss
+
+    def adam(self, grad: torch.Tensor, lr: float, stream=None):
+        self.step += 1
+        _check(load().rnnls_mlp_adam(_ptr(self.theta), _ptr(self.wb), _ptr(grad), _ptr(self.m),
+                                     _ptr(self.v), self.step, float(lr), 0.9, 0.999, 1e-8,
+                                     _stream(stream)), "rnnls_mlp_adam")
+
+    def train_step(self, X: torch.Tensor, y: torch.Tensor, lr: float, loss=None, stream=None):
+        rows = X.shape[0]
+        ws = self._workspace(rows)
+        self.step += 1
+        _check(load().rnnls_mlp_train_step(rows, _ptr(X), _ptr(y), _ptr(self.theta),
+                                           _ptr(self.wb), _ptr(self.m), _ptr(self.v), self.step,
+                                           float(lr), _ptr(loss), _ptr(ws), ws.numel(),
+                                           _stream(stream)), "rnnls_mlp_train_step")
 
 
 def timing_enable(on: bool = True) -> None:

@@ -126,6 +126,40 @@ def batch_instance(i: int, n: int, d: int, batch_seed: int = 4) -> Problem:
     return tfidf_like(n, d, seed=batch_seed * 1_000_003 + i)
 
 
+def tfidf_like_device(n: int, d: int, seed: int, device="cuda", mean_density: float = 0.01,
+                      zipf_s: float = 1.1, zero_frac: float = 0.3, noise: float = 0.05):
+    """Device-side tf-idf-like instance for large training sets: the column
+    densities and x* are drawn on the host as in tfidf_like, the entries on
+    the device (each entry nonzero with its column's density, values
+    lognormal(0,1), columns L2-normalised; a column left empty gets one
+    entry), b = A x* + e with ||e|| = noise ||A x*||.  Returns (A, b, x*) with
+    A an (n, d) column-major float32 tensor and b float32 (n,)."""
+    import torch
+    g = np.random.default_rng(seed)
+    rho = zipf_densities(d, mean_density, zipf_s, g)
+    x = g.uniform(0.0, 2.0, size=d)
+    x[g.choice(d, size=int(round(zero_frac * d)), replace=False)] = 0.0
+    fill_rows = g.integers(0, n, size=d)
+    tg = torch.Generator(device=device)
+    tg.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    M = torch.rand((d, n), generator=tg, device=device)
+    vals = torch.randn((d, n), generator=tg, device=device).exp_()
+    rho_t = torch.from_numpy(rho.astype(np.float32)).to(device).unsqueeze(1)
+    M = torch.where(M < rho_t, vals, torch.zeros((), device=device))
+    del vals
+    empty = (M.abs().sum(dim=1) == 0).nonzero().flatten()
+    if empty.numel():
+        fr = torch.from_numpy(fill_rows).to(device)
+        M[empty, fr[empty]] = 1.0
+    M /= M.norm(dim=1, keepdim=True)
+    xs = torch.from_numpy(x).to(device)
+    Ax = (M.t().double() @ xs)
+    e = torch.randn(n, generator=tg, device=device, dtype=torch.float64)
+    e *= noise * Ax.norm() / e.norm()
+    b = (Ax + e).float()
+    return M.t(), b, x
+
+
 def density_sweep(n: int, d: int, density: float, seed: int) -> Problem:
     """Random n x (d+1) matrix of the given density with U[0,1] nonzeros; one
     random column is b, the other d columns form A (Section 4.2)."""

@@ -1,0 +1,145 @@
+"""GPU parity and gain of the learned warm start: the feature, perceptron,
+gradient and Adam kernels against the FP64 oracle on the same seeded inputs,
+and the warm-started, KKT-judged solves against cold starts and the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hadamard, learned as olearned, nnls
+from paper_0812_4547_amd import learned, rnnls, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    rnnls.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _gram_case(n, d, seed, zero_col=False):
+    g = np.random.default_rng(seed)
+    A = np.abs(g.standard_normal((n, d))) * (g.random((n, d)) < 0.3)
+    if zero_col:
+        A[:, d // 2] = 0.0
+    b = A @ g.uniform(0, 2, d) + 0.05 * g.standard_normal(n)
+    return A.T @ A, A.T @ b, float(b @ b)
+
+
+@pytest.mark.parametrize("d,seed,zero", [(1, 1, False), (7, 2, False), (64, 3, True),
+                                         (65, 4, False), (128, 5, False)])
+def test_features_match_oracle(d, seed, zero):
+    G, q, c = _gram_case(400, d, seed, zero)
+    want = olearned.features(G, q, c)
+    got = rnnls.features(torch.from_numpy(G).cuda(), torch.from_numpy(q).cuda(),
+                         torch.tensor([c], dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
+
+
+def _net_case(rows, seed):
+    g = np.random.default_rng(seed)
+    theta = (g.standard_normal(olearned.N_PARAMS) * 0.15).astype(np.float32)
+    X = g.standard_normal((rows, 8)).astype(np.float32)
+    y = (g.random(rows) < 0.4).astype(np.uint8)
+    return theta, X, y
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 1000, 8192])
+def test_forward_matches_oracle(rows):
+    theta, X, y = _net_case(rows, rows)
+    mlp = rnnls.Mlp(torch.from_numpy(theta).cuda())
+    prob, flags = mlp.forward(torch.from_numpy(X).cuda(), threshold=0.5)
+    torch.cuda.synchronize()
+    want = olearned.forward(theta.astype(np.float64), X)["p"]
+    assert np.abs(prob.cpu().numpy() - want).max() <= 1e-5
+    agree = flags.cpu().numpy() == (want > 0.5)
+    assert agree.all() or np.all(np.abs(want[~agree] - 0.5) < 1e-5)
+    # the BF16 copy is the round-to-nearest-even of the master weights
+    P = olearned.unpack(theta)
+    wb = np.concatenate([olearned.bf16_round(P[k].astype(np.float32)).reshape(-1)
+                         for k in olearned.WEIGHTS])
+    got = (mlp.wb.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
+    assert np.array_equal(got.view(np.float32), wb)
+
+
+@pytest.mark.parametrize("rows", [5, 64, 777, 8192])
+def test_gradient_matches_oracle(rows):
+    theta, X, y = _net_case(rows, 100 + rows)
+    mlp = rnnls.Mlp(torch.from_numpy(theta).cuda())
+    grad, loss = mlp.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    want = olearned.gradient(theta.astype(np.float64), X, y)
+    wl = olearned.loss(theta.astype(np.float64), X, y)
+    assert abs(float(loss.item()) - wl) <= 1e-5 * max(1.0, abs(wl))
+    got = grad.cpu().numpy().astype(np.float64)
+    P_got, P_want = olearned.unpack(got), olearned.unpack(want)
+    for name in P_want:
+        num = np.linalg.norm(P_got[name] - P_want[name])
+        den = max(np.linalg.norm(P_want[name]), 1e-12)
+        assert num / den <= 1e-4, name
+
+
+def test_adam_matches_oracle():
+    """Three Adam steps on each side from the same start, each side with its
+    own gradients (device FP32 vs oracle FP64)."""
+    theta, X, y = _net_case(300, 9)
+    mlp = rnnls.Mlp(torch.from_numpy(theta).cuda())
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    lr = 1e-2
+    for step in range(1, 4):
+        grad, _ = mlp.gradient(Xd, yd)
+        mlp.adam(grad, lr=lr)
+        g64 = olearned.gradient(th, X, y)
+        th, m, v = olearned.adam_step(th, g64, m, v, step, lr=lr)
+        torch.cuda.synchronize()
+        assert np.abs(mlp.theta.cpu().numpy() - th).max() <= 2e-3 * lr, step
+
+
+def test_training_reduces_loss():
+    theta, X, y = _net_case(4096, 11)
+    # a learnable rule: passive when the first two features are positive
+    y = ((X[:, 0] > 0) & (X[:, 1] > -0.5)).astype(np.uint8)
+    mlp = rnnls.Mlp(learned.init_params(3))
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    hist = learned.train(mlp, Xd, yd, epochs=30, batch_rows=1024, lr=3e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    prob, _ = mlp.forward(Xd)
+    acc = ((prob.cpu().numpy() > 0.5) == y.astype(bool)).mean()
+    assert acc > 0.95
+
+
+def test_warm_start_gain_and_parity():
+    """Train on problems the method itself solved, then warm-start held-out
+    problems: same optima (KKT-certified), fewer outer iterations."""
+    X, y, ok = learned.collect(1024, seed=21, chunk=512, log2_n=(12.0, 14.0))
+    assert ok
+    mlp = rnnls.Mlp(learned.init_params(5))
+    learned.train(mlp, X, y, epochs=15, batch_rows=4096, lr=2e-3)
+    ev = learned.evaluate(mlp, 256, seed=22, chunk=256, reps=1, log2_n=(12.0, 14.0))
+    print(ev, flush=True)
+    assert ev.all_ok
+    assert ev.max_gap <= 1e-9
+    assert ev.warm_kept >= 0.9
+    assert ev.warm_iters < 0.5 * ev.cold_iters
+    # parity of warm-started solutions with the oracle on a few problems
+    shp = learned.shapes(256, 22, (12.0, 14.0))[:4]
+    probs = learned.device_problems(shp, 22 * 1_000_003, "cuda")
+    batch = rnnls.Batch(probs)
+    batch.set_model(mlp)
+    batch.run()
+    torch.cuda.synchronize()
+    for i, (A, b, r, seed) in enumerate(probs):
+        SA, Sb, _, _ = hadamard.srht_sketch(A.cpu().numpy().astype(np.float64),
+                                            b.cpu().numpy().astype(np.float64), r, seed)
+        ref = nnls.lawson_hanson(SA, Sb)
+        x = batch.x[i].cpu().numpy()
+        assert nnls.relative_residual_gap(SA, Sb, x, ref.x) <= 1e-6, i
+    batch.close()
