@@ -39,6 +39,10 @@ WORKLOADS = {
     "single_4096x16": (4096, 16, 512, 1, 1),
     "single_2p22x128": (1 << 22, 128, 8192, 3, 3),
 }
+# batching forms: 256 uneven tf-idf-like instances (n log-uniform in
+# [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
+# 2^20 x 64 with 512 right-hand sides (r = 2048)
+BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -99,15 +103,254 @@ def cpu_baseline(n, d, r, ds, planted, nsamples):
     }
 
 
+CPU_BATCH_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+from paper_0812_4547_amd import workloads
+from oracle import rand_nnls
+shapes = workloads.batch_shapes()[:{count}]
+probs = [workloads.batch_instance(i, n, d) for i, (n, d, r) in enumerate(shapes)]
+t0 = time.perf_counter()
+for i, ((n, d, r), p) in enumerate(zip(shapes, probs)):
+    rand_nnls.rand_nnls(p.A, p.b, r, 1000 + i)
+dt = time.perf_counter() - t0
+print(json.dumps({{"seconds": dt, "instances": len(shapes)}}))
+"""
+
+CPU_MULTI_SAMPLE = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, {root!r})
+from paper_0812_4547_amd import workloads
+from oracle import hadamard, nnls
+A, B, _ = workloads.tfidf_multi_rhs(1 << 20, 64, 512, seed=4)
+k = {count}
+t0 = time.perf_counter()
+Y, _, _, _ = hadamard.srht_sketch(np.column_stack([A, B[:, :k]]).astype(np.float64), None, 2048, 4)
+for j in range(k):
+    nnls.lawson_hanson(Y[:, :64], Y[:, 64 + j])
+dt = time.perf_counter() - t0
+print(json.dumps({{"seconds": dt, "instances": k}}))
+"""
+
+
+def _run_cpu_sample(code, what):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": res["instances"] / res["seconds"], "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{what}: {res['instances']} solves, FP64 numpy oracle, one thread, "
+                      f"{res['seconds']:.1f} s"}
+
+
+def _timed(fn, steps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def _base_record(args, value, ms, config, dtype="f32"):
+    return {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def bench_batch(args):
+    """One step = one pass of the batch plan (graph replay) over 256 uneven
+    instances resident in HBM."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    shapes = workloads.batch_shapes()
+    probs, dev = [], []
+    alg = 0
+    for i, (n, d, r) in enumerate(shapes):
+        p = workloads.batch_instance(i, n, d)
+        A = rnnls.colmajor(p.A)
+        b = torch.from_numpy(p.b).cuda()
+        dev.append((A, b, r, 1000 + i))
+        probs.append(p)
+        alg += 4 * n * (d + 1) + 4 * r * (d + 1)
+    del probs
+    batch = rnnls.Batch(dev)
+    stream = torch.cuda.current_stream()
+    batch.run()
+    torch.cuda.synchronize()
+    eager_ms_default = _timed(batch.run, max(3, args.steps // 5), stream)
+    choice = batch.autotune()
+    batch.capture()
+    for _ in range(args.warmup):
+        batch.launch()
+    ms = _timed(batch.launch, args.steps, stream)
+    eager_ms = _timed(batch.run, max(3, args.steps // 5), stream)
+    # sketch stage alone, eager, with the library's event timers
+    rnnls.timing_enable(True)
+    for t in (rnnls.TIMER_SKETCH, rnnls.TIMER_MOMENTS, rnnls.TIMER_SOLVE):
+        rnnls.timing_read(t)
+    reps = 5
+    for _ in range(reps):
+        batch.run()
+    torch.cuda.synchronize()
+    sk_ms, sk_n = rnnls.timing_read(rnnls.TIMER_SKETCH)
+    mo_ms, _ = rnnls.timing_read(rnnls.TIMER_MOMENTS)
+    lh_ms, _ = rnnls.timing_read(rnnls.TIMER_SOLVE)
+    rnnls.timing_enable(False)
+    st = batch.status.cpu().numpy()
+    sketch_ms = sk_ms / reps
+    achieved = alg / (sketch_ms * 1e-3) / 1e9
+    rec = _base_record(args, len(shapes) * 1000.0 / ms, ms, {
+        "workload": f"batch of {len(shapes)} tf-idf-like instances, n log-uniform in "
+                    f"[2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)",
+        "instances": len(shapes), "batch_seed": 4, "sketch_seeds": "1000 + i",
+        "algorithmic_bytes": alg, "autotuned_tile": list(choice),
+        "launch": "hipGraph replay of the batch plan"})
+    rec["roofline"] = {"kernel": "srht_tiled_kernel (all sketch launches of the pass)",
+                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sketch_ms,
+                       "sketch_launches_per_pass": sk_n / reps}
+    rec["breakdown_ms_per_pass_eager"] = {"sketch": sketch_ms, "moments": mo_ms / reps,
+                                          "lawson_hanson": lh_ms / reps}
+    rec["eager_ms_per_pass"] = eager_ms
+    rec["eager_ms_per_pass_default_tile"] = eager_ms_default
+    rec["status_ok"] = int((st == 0).sum())
+    batch.close()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = _run_cpu_sample(
+            CPU_BATCH_SAMPLE.format(root=ROOT, count=args.cpu_samples or 12),
+            "the first instances of the same batch")
+    print(json.dumps(rec), flush=True)
+
+
+def bench_multi(args):
+    """One step = Algorithm 1 for 512 right-hand sides sharing one A of
+    2^20 x 64 (one sketch, one G, 512 Lawson-Hanson solves)."""
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    n, d, k, r = 1 << 20, 64, 512, 2048
+    A_h, B_h, _ = workloads.tfidf_multi_rhs(n, d, k, seed=4)
+    A = rnnls.colmajor(A_h)
+    B = rnnls.colmajor(B_h)
+    del A_h, B_h
+    ws = rnnls.multi_workspace(n, d, k, r)
+    out = rnnls.rand_nnls_multi(A, B, r, 4, ws=ws)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        rnnls.rand_nnls_multi(A, B, r, 4 + i, ws=ws, out=out)
+    rnnls.timing_enable(True)
+    for t in (rnnls.TIMER_SKETCH, rnnls.TIMER_MOMENTS, rnnls.TIMER_SOLVE):
+        rnnls.timing_read(t)
+    it = iter(range(10**9))
+    ms = _timed(lambda: rnnls.rand_nnls_multi(A, B, r, 4 + next(it), ws=ws, out=out),
+                args.steps, stream)
+    sk_ms, sk_n = rnnls.timing_read(rnnls.TIMER_SKETCH)
+    mo_ms, _ = rnnls.timing_read(rnnls.TIMER_MOMENTS)
+    lh_ms, _ = rnnls.timing_read(rnnls.TIMER_SOLVE)
+    rnnls.timing_enable(False)
+    alg = 4 * n * (d + k) + 4 * r * (d + k)
+    sk = sk_ms / max(sk_n, 1)
+    achieved = alg / (sk * 1e-3) / 1e9
+    st = out.status.cpu().numpy()
+    rec = _base_record(args, k * 1000.0 / ms, ms, {
+        "workload": "tf-idf-like A 2^20 x 64 FP32 with 512 right-hand sides B = A X* + 5% "
+                    "noise (nonnegative-factorisation-style update), r = 2048",
+        "n": n, "d": d, "k": k, "r": r, "data_seed": 4})
+    rec["roofline"] = {"kernel": "srht_tiled_kernel", "bound": "hbm", "achieved": achieved,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": None, "algorithmic_bytes_per_launch": alg,
+                       "avg_launch_ms": sk}
+    rec["breakdown_ms_per_step"] = {"sketch_kernel": sk_ms / args.steps,
+                                    "moments": mo_ms / args.steps,
+                                    "lawson_hanson": lh_ms / args.steps}
+    rec["status_ok"] = int((st == 0).sum())
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = _run_cpu_sample(
+            CPU_MULTI_SAMPLE.format(root=ROOT, count=args.cpu_samples or 8),
+            "one FP64 sketch of [A | 8 right-hand sides] and their 8 solves")
+    print(json.dumps(rec), flush=True)
+
+
+def bench_learned(args):
+    """Learned warm start: collect features and passive labels from problems of
+    the batch generator solved cold on the device, train the perceptron with
+    the device kernels, then solve held-out problems cold and warm-started
+    (KKT-judged).  One step = one pass of a 1024-problem batch plan."""
+    import torch
+
+    from paper_0812_4547_amd import learned, rnnls
+    train_count = args.train_instances
+    t0 = time.perf_counter()
+    Xs, ys, ok = [], [], True
+    chunk = 1024
+    for c0 in range(0, train_count, chunk):
+        X, y, o = learned.collect(min(chunk, train_count - c0), seed=100 + c0 // chunk)
+        Xs.append(X)
+        ys.append(y)
+        ok = ok and o
+        print(f"collected {c0 + chunk} / {train_count} training problems "
+              f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    collect_s = time.perf_counter() - t0
+    mlp = rnnls.Mlp(learned.init_params(1))
+    t1 = time.perf_counter()
+    hist = learned.train(mlp, X, y, epochs=args.epochs, batch_rows=8192, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    prob, _ = mlp.forward(X)
+    acc = float(((prob > 0.5).to(torch.uint8) == y).double().mean().item())
+    print(f"trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, accuracy {acc:.4f}",
+          file=sys.stderr, flush=True)
+    ev = learned.evaluate(mlp, args.heldout, seed=2_000_000, chunk=1024, reps=max(1, args.steps))
+    rec = _base_record(args, args.heldout * 1000.0 / ev.warm_ms, ev.warm_ms / (args.heldout / 1024),
+                       {"workload": f"learned warm start: {train_count} training and "
+                                    f"{args.heldout} held-out problems of the batch generator "
+                                    "(n log-uniform in [2^14, 2^18], d uniform in [8, 96], "
+                                    "r = max(32 d, 1024)), device-generated tf-idf-like data",
+                        "network": "8-128-128-1 perceptron, BF16 weights, FP32 accumulation",
+                        "step": "one eager pass of a 1024-problem batch plan"})
+    rec["vs_cold"] = {"warm_solves_per_s": args.heldout * 1000.0 / ev.warm_ms,
+                      "cold_solves_per_s": args.heldout * 1000.0 / ev.cold_ms,
+                      "speedup": ev.cold_ms / ev.warm_ms,
+                      "lawson_hanson_ms_cold": ev.cold_lh_ms, "lawson_hanson_ms_warm": ev.warm_lh_ms,
+                      "outer_iterations_cold": ev.cold_iters, "outer_iterations_warm": ev.warm_iters,
+                      "warm_start_kept": ev.warm_kept,
+                      "max_rel_residual_gap_vs_cold": ev.max_gap, "all_status_ok": ev.all_ok}
+    rec["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "loss_first": hist[0],
+                       "loss_last": hist[-1], "train_accuracy": acc, "collect_s": collect_s,
+                       "train_s": train_s, "labels_all_ok": ok}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="single_2p20x64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="single_2p20x64",
+                    choices=sorted(WORKLOADS) + list(BATCH_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=0,
                     help="instances the oracle times (default: about 10-30 s of CPU work)")
+    ap.add_argument("--train-instances", type=int, default=100_000)
+    ap.add_argument("--heldout", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies of this many MiB (the "
                          "reference kernel that scales the HBM byte counters)")
@@ -131,6 +374,13 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written":
                           dst.numel() * 4, "launches": 5}), flush=True)
         return
+
+    if args.workload == "batch_256":
+        return bench_batch(args)
+    if args.workload == "multi_2p20x64_k512":
+        return bench_multi(args)
+    if args.workload == "learned_4096":
+        return bench_learned(args)
 
     n, d, r, ds, ss = WORKLOADS[args.workload]
     planted = args.workload == "single_4096x16"

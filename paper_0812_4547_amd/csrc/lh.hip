@@ -212,10 +212,12 @@ __device__ __forceinline__ void mv(const Ptr (&row)[H], const double* vb, int n,
   for (int h = 0; h < H; ++h) u[h] = a[h][0] + a[h][1];
 }
 
-// row[h][k] += ya[h] * vb[k] for k < n (lane s updates its own row)
+// row[h][k] += ya[h] * vb[k] for k < n (lane s updates its own row).  Rows
+// of out-of-range lanes alias one dummy row and are not stored: stores of
+// many lanes to one LDS address serialise.
 template <int H>
 __device__ __forceinline__ void rank1(double* const (&row)[H], const double (&ya)[H],
-                                      const double* vb, int n) {
+                                      const double* vb, int n, const bool (&live)[H]) {
   int k = 0;
   for (; k + 16 <= n; k += 16) {
     double2 v2[8];
@@ -228,10 +230,12 @@ __device__ __forceinline__ void rank1(double* const (&row)[H], const double (&ya
     for (int i = 0; i < 8; ++i) v2[i] = *reinterpret_cast<const double2*>(vb + k + 2 * i);
 #pragma unroll
     for (int h = 0; h < H; ++h)
+      if (live[h]) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        row[h][k + 2 * i] = fma(ya[h], v2[i].x, r[h][2 * i]);
-        row[h][k + 2 * i + 1] = fma(ya[h], v2[i].y, r[h][2 * i + 1]);
+        for (int i = 0; i < 8; ++i) {
+          row[h][k + 2 * i] = fma(ya[h], v2[i].x, r[h][2 * i]);
+          row[h][k + 2 * i + 1] = fma(ya[h], v2[i].y, r[h][2 * i + 1]);
+        }
       }
   }
   for (; k + 4 <= n; k += 4) {
@@ -243,17 +247,19 @@ __device__ __forceinline__ void rank1(double* const (&row)[H], const double (&ya
     const double2 v0 = *reinterpret_cast<const double2*>(vb + k);
     const double2 v1 = *reinterpret_cast<const double2*>(vb + k + 2);
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-      row[h][k] = fma(ya[h], v0.x, r[h][0]);
-      row[h][k + 1] = fma(ya[h], v0.y, r[h][1]);
-      row[h][k + 2] = fma(ya[h], v1.x, r[h][2]);
-      row[h][k + 3] = fma(ya[h], v1.y, r[h][3]);
-    }
+    for (int h = 0; h < H; ++h)
+      if (live[h]) {
+        row[h][k] = fma(ya[h], v0.x, r[h][0]);
+        row[h][k + 1] = fma(ya[h], v0.y, r[h][1]);
+        row[h][k + 2] = fma(ya[h], v1.x, r[h][2]);
+        row[h][k + 3] = fma(ya[h], v1.y, r[h][3]);
+      }
   }
   for (; k < n; ++k) {
     const double vk = vb[k];
 #pragma unroll
-    for (int h = 0; h < H; ++h) row[h][k] = fma(ya[h], vk, row[h][k]);
+    for (int h = 0; h < H; ++h)
+      if (live[h]) row[h][k] = fma(ya[h], vk, row[h][k]);
   }
 }
 
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
 #pragma unroll
     for (int h = 0; h < H; ++h) ua[h] = u[h] * sinv;
     stage(vb, u);  // u is zero on free slots and on slot j
-    rank1(brow, ua, vb, hwm);
+    rank1(brow, ua, vb, hwm, valid);
     lh_sync<QPG>();
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
         ba[h] = -bvec[h] / bjj;
       }
       stage(vb, bvec);
-      rank1(brow, ba, vb, hwm);
+      rank1(brow, ba, vb, hwm, valid);
       lh_sync<QPG>();
 #pragma unroll
       for (int h = 0; h < H; ++h) {
@@ -466,26 +472,108 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
     status = RNNLS_SOLVE_OK;
 
     if (warm) {
-      // ---- warm start: border every proposed column (skipping dependent
-      // ones), then drop nonpositive coefficients until z > 0 on P
-      for (int t = 0; t < d; ++t) {
-        if (!p0[t]) continue;
-        double g[H], u[H], qnew[H];
+      // ---- warm start: the proposed columns take slots 0..p-1 in
+      // ascending order, QP gains their columns, and B = Q[P0,P0]^{-1} comes
+      // from an in-place Gauss-Jordan sweep over their Gram block (a pivot
+      // whose Schur complement is dependent, <= 1e-14 Q_tt, is removed before
+      // it is used); then nonpositive coefficients are dropped until z > 0
+      bool prop[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) prop[h] = valid[h] && p0[lane + h * kW] != 0;
+      const uint64_t pm0 = __ballot(prop[0]);
+      const uint64_t pm1 = H == 2 ? __ballot(prop[H - 1]) : 0ull;
+      const int p = uni((int)(__popcll(pm0) + __popcll(pm1)));
+      int* slot_col = reinterpret_cast<int*>(xcol);  // d ints fit in xcol
+      const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if (prop[h]) {
+          const int rk = (int)(h == 0 ? __popcll(pm0 & below)
+                                      : __popcll(pm0) + __popcll(pm1 & below));
+          cslot[h] = rk;
+          slot_col[rk] = lane + h * kW;
+        }
+      }
+      lh_sync<false>();
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int sl = lane + h * kW;
+        scol[h] = sl < p ? slot_col[sl] : -1;
+      }
+      // QP[col][s] = Q[P0[s]][col]: row P0[s] of Q is contiguous over col
+      for (int s0 = 0; s0 < p; s0 += 4) {
+        double v[4][H];
+        int cs[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cs[e] = uni(slot_col[s0 + e < p ? s0 + e : s0]);
+#pragma unroll
+          for (int h = 0; h < H; ++h)
+            v[e][h] = valid[h] ? Qg[(int64_t)cs[e] * d + lane + h * kW] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (s0 + e < p) {
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+              if (valid[h]) QP[(lane + h * kW) * ld + s0 + e] = v[e][h];
+          }
+      }
+      lh_sync<QPG>();
+      // B starts as the Gram block: row s of slot s is QP[P0[s]][0..p)
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        if (scol[h] >= 0) {
+          const double* src = QP + scol[h] * ld;
+          for (int k = 0; k < p; ++k) brow[h][k] = src[k];
+        }
+      hwm = p;
+      np = p;
+      lh_sync<QPG>();
+      for (int k = 0; k < p; ++k) {
+        const int colk = uni(slot_col[k]);
+        const double piv = uni(Bs[k * ld + k]);
+        const double qkk = uni(dq[colk]);
+        if (!(piv > kDependence * qkk)) {
+          // dependent on the columns before it: remove slot k
+#pragma unroll
+          for (int h = 0; h < H; ++h) {
+            const int sl = lane + h * kW;
+            if (valid[h]) {
+              Bs[sl * ld + k] = 0.0;
+              Bs[k * ld + sl] = 0.0;
+              QP[sl * ld + k] = 0.0;
+            }
+            if (sl == k) scol[h] = -1;
+            if (sl == colk) cslot[h] = -1;
+          }
+          --np;
+          lh_sync<QPG>();
+          continue;
+        }
+        const double pinv = uni(1.0 / piv);
+        // pivot row scaled (its diagonal becomes 1/piv); other rows
+        // M[i][.] -= M[i][k] * row, with M[i][k] reset to 0 first
+        double rk[H], ya[H];
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-          g[h] = valid[h] ? QP[t * ld + lane + h * kW] : 0.0;
-          qnew[h] = valid[h] ? Qg[(int64_t)t * d + lane + h * kW] : 0.0;
+          const int j = lane + h * kW;
+          rk[h] = valid[h] ? (j == k ? pinv : Bs[k * ld + j] * pinv) : 0.0;
+          ya[h] = (valid[h] && j != k) ? -brow[h][k] : 0.0;
+          if (valid[h] && j != k) brow[h][k] = 0.0;
         }
-        stage(vb, g);
-        mv(brow, vb, hwm, u);
-        double gu = 0.0;
+        stage(vb, rk);
+        rank1(brow, ya, vb, hwm, valid);
+        lh_sync<false>();
 #pragma unroll
-        for (int h = 0; h < H; ++h) gu += g[h] * u[h];
-        const double qtt = uni(dq[t]);
-        const double sval = uni(qtt - wave_sum(gu));
-        if (!(sval > kDependence * qtt)) continue;
-        border(t, u, qnew, uni(1.0 / sval));
+        for (int h = 0; h < H; ++h)
+          if (valid[h] && lane + h * kW < hwm) Bs[k * ld + lane + h * kW] = rk[h];
+        lh_sync<QPG>();
       }
+      while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
+      hwm = uni(hwm);
+      for (int j = lane; j < d; j += kW) xcol[j] = 0.0;
+      lh_sync<false>();
       while (np > 0) {
         solve_z();
         bool drop[H];
