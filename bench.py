@@ -348,6 +348,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=0,
                     help="instances the oracle times (default: about 10-30 s of CPU work)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
+                    help="sketch transform: FP32 vector units, or BF16 matrix cores with "
+                         "split hi + lo operands and FP32 accumulation")
     ap.add_argument("--train-instances", type=int, default=100_000)
     ap.add_argument("--heldout", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=8)
@@ -387,7 +390,7 @@ def main():
     p = workloads.uniform_planted(n=n, d=d, seed=ds) if planted else workloads.tfidf_like(n, d, seed=ds)
     A = rnnls.colmajor(p.A)
     b = torch.from_numpy(p.b).cuda()
-    opts = rnnls.Opts()
+    opts = rnnls.make_opts(precision=args.precision)
     ws = rnnls.workspace(rnnls.OP_RAND_NNLS, n, d, r, opts)
     out = rnnls.Solution(torch.empty(d, dtype=torch.float64, device="cuda"), None,
                          torch.empty(1, dtype=torch.float64, device="cuda"),
@@ -423,7 +426,7 @@ def main():
     sk_avg = sk_ms / max(sk_n, 1)
     alg_bytes = 4 * n * (d + 1) + 4 * r * (d + 1)
     achieved = alg_bytes / (sk_avg * 1e-3) / 1e9
-    traffic = load_traffic()
+    traffic = load_traffic() if (args.precision == "fp32" and args.workload == "single_2p20x64") else None
 
     # quality of x~ (untimed): the paper's residual loss against the exact NNLS
     # of the whole problem, both solved on the GPU (nnls_solve on all n rows is
@@ -448,16 +451,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16x2-f32acc",
         "data": "synthetic",
         "config": {
             "workload": (f"single RandomizedNNLS instance, tf-idf-like A {n}x{d} FP32 dense, "
                          f"r={r}") if not planted else f"single instance, U[0,1] A {n}x{d}, r={r}",
             "n": n, "d": d, "r": r, "data_seed": ds, "sketch_seed_first": ss,
-            "sample_mode": "exact", "precision": "sketch f32, moments and Lawson-Hanson f64",
+            "sample_mode": "exact",
+            "precision": ("sketch f32" if args.precision == "fp32" else
+                          "sketch: two Hadamard factors on BF16 matrix cores (x = hi + lo, FP32 "
+                          "accumulate), third factor and combine f32") +
+                         ", moments and Lawson-Hanson f64",
         },
         "roofline": {
-            "kernel": "srht_tiled_kernel",
+            "kernel": "srht_tiled_kernel" if args.precision == "fp32" else "srht_mfma_kernel",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -74,10 +74,19 @@ extern "C" {
 #define RNNLS_SAMPLE_BERNOULLI 1    /* r~ ~ Bin(n', r/n') rows                */
 
 #define RNNLS_PREC_FP32 0           /* FP32 transform                         */
-#define RNNLS_PREC_SPLIT_BF16 1     /* reserved: split-BF16 matrix-core path  */
+#define RNNLS_PREC_SPLIT_BF16 1     /* split-BF16 matrix-core transform (below) */
 
 /* Limits of this version: 1 <= d <= RNNLS_MAX_D; 1 <= r < n'; r (or r_cap)
- * <= RNNLS_MAX_R; n' <= 2^30. */
+ * <= RNNLS_MAX_R; n' <= 2^30.
+ *
+ * RNNLS_PREC_SPLIT_BF16: the in-tile Hadamard transform runs two of its three
+ * factors on BF16 matrix cores with every input split x = hi + lo
+ * (hi = bf16(x), lo = bf16(x - hi)) and FP32 accumulation; the third factor,
+ * the combine across tiles, moments and Lawson-Hanson are unchanged (FP32 /
+ * FP64).  Each split loses about 2^-16 relatively, so sketch columns agree
+ * with the exact transform to about 1e-4 norm-wise (FP32: about 1e-6).
+ * Needs r_cap <= 8192 when n' >= 2^14 (else RNNLS_E_UNSUPPORTED, nothing
+ * launched); problems with n' < 2^14 run the FP32 transform. */
 #define RNNLS_MAX_D 128
 #define RNNLS_MAX_R 32768
 

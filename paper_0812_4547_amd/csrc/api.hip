@@ -154,17 +154,27 @@ int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n
   return 0;
 }
 
+// The sketch plan for the requested precision.  Split-BF16 needs n' >= 2^14
+// (smaller problems run the FP32 transform, which is at least as accurate)
+// and at most 32 kept rows per thread of its 256-thread workgroups.
+SrhtPlan plan_for(int64_t n, int ncols, int r_cap, int cus, const Opts& o) {
+  if (o.precision == RNNLS_PREC_SPLIT_BF16 && next_pow2((uint64_t)n) >= (1ull << 14))
+    return srht_plan_split_bf16(n, ncols, r_cap, cus);
+  return srht_plan(n, ncols, r_cap, cus);
+}
+
 int sketch_core(const Sizes& z, const Opts& o, uint64_t seed, const float* A, int64_t lda,
                 const float* b, float* SA, int64_t ldsa, float* Sb, int32_t* rows,
                 int32_t* count, uint32_t* signs, uint32_t* sign_export, int32_t* status,
                 uint32_t* stream_scratch, float* partials, hipStream_t s) {
+  if (z.sp.log_t < 0) return RNNLS_E_UNSUPPORTED;  // nothing is launched
   StreamJob sj{};
   sj.seed = seed;
   sj.m = ilog2_exact((uint64_t)z.n_pad);
   sj.r = z.r;
   sj.r_cap = z.r_cap;
   sj.mode = o.sample_mode;
-  sj.sign_log_t = z.sp.log_t;
+  sj.sign_log_t = z.sp.mfma ? 0 : z.sp.log_t;
   sj.sign_words = signs;
   sj.sign_export = sign_export;
   sj.scratch = stream_scratch;
@@ -244,9 +254,9 @@ bool ws_ok(void* ws, size_t ws_bytes, size_t need) {
 
 // A sketch workspace serves calls with and without b.
 size_t sketch_ws_need(Sizes z, const Opts& o, int64_t n, int cus) {
-  z.sp = srht_plan(n, z.d + 1, z.r_cap, cus);
+  z.sp = plan_for(n, z.d + 1, z.r_cap, cus, o);
   const size_t with_b = layout_sketch(z, o, false, true).total;
-  z.sp = srht_plan(n, z.d, z.r_cap, cus);
+  z.sp = plan_for(n, z.d, z.r_cap, cus, o);
   const size_t without_b = layout_sketch(z, o, false, false).total;
   return with_b > without_b ? with_b : without_b;
 }
@@ -287,7 +297,7 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
   if (check_sketch_sizes(n, d, r, o, 1, 2, 3, 4, &z)) return 0;
   z.mp = moments_plan(z.r_cap, d, 1, cus);
   if (op == RNNLS_OP_RAND_NNLS) {
-    z.sp = srht_plan(n, d + 1, z.r_cap, cus);
+    z.sp = plan_for(n, d + 1, z.r_cap, cus, o);
     return layout_sketch(z, o, true, true).total;
   }
   return sketch_ws_need(z, o, n, cus);
@@ -301,7 +311,6 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed, const floa
   Sizes z;
   int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 15, &z);
   if (rc) return rc;
-  if (o.precision != RNNLS_PREC_FP32) return RNNLS_E_UNSUPPORTED;
   if (!A) return -5;
   if (lda < n) return -6;
   if (!SA) return -8;
@@ -310,7 +319,7 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed, const floa
   const int cus = device_cus();
   if (cus < 0) return cus;
   if (!ws_ok(ws, ws_bytes, sketch_ws_need(z, o, n, cus))) return RNNLS_E_WORKSPACE;
-  z.sp = srht_plan(n, d + (b ? 1 : 0), z.r_cap, cus);
+  z.sp = plan_for(n, d + (b ? 1 : 0), z.r_cap, cus, o);
   const Layout L = layout_sketch(z, o, false, b != nullptr);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return sketch_core(z, o, seed, A, lda, b, SA, ldsa, Sb,
@@ -361,7 +370,6 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   Sizes z;
   int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 17, &z);
   if (rc) return rc;
-  if (o.precision != RNNLS_PREC_FP32) return RNNLS_E_UNSUPPORTED;
   if (!A) return -5;
   if (lda < n) return -6;
   if (!b) return -7;
@@ -369,7 +377,7 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
   if (SA && ldsa < z.r_cap) return -13;
   const int cus = device_cus();
   if (cus < 0) return cus;
-  z.sp = srht_plan(n, d + 1, z.r_cap, cus);
+  z.sp = plan_for(n, d + 1, z.r_cap, cus, o);
   z.mp = moments_plan(z.r_cap, d, 1, cus);
   const Layout L = layout_sketch(z, o, true, true);
   if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
@@ -403,7 +411,7 @@ size_t rnnls_multi_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t r,
   const int cus = device_cus();
   if (cus < 0 || k < 1 || k > RNNLS_MAX_K) return 0;
   if (check_sketch_sizes(n, d, r, o, 1, 2, 4, 15, &z)) return 0;
-  z.sp = srht_plan(n, d + k, z.r_cap, cus);
+  z.sp = plan_for(n, d + k, z.r_cap, cus, o);
   z.mp = moments_plan(z.r_cap, d, k, cus);
   return layout_multi(z, k).total;
 }
@@ -417,7 +425,6 @@ int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t s
   if (k < 1 || k > RNNLS_MAX_K) return -3;
   int rc = check_sketch_sizes(n, d, r, o, 1, 2, 4, 15, &z);
   if (rc) return rc;
-  if (o.precision != RNNLS_PREC_FP32) return RNNLS_E_UNSUPPORTED;
   if (!A) return -6;
   if (lda < n) return -7;
   if (!B) return -8;
@@ -426,8 +433,9 @@ int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t s
   if (ldx < d) return -11;
   const int cus = device_cus();
   if (cus < 0) return cus;
-  z.sp = srht_plan(n, d + k, z.r_cap, cus);
+  z.sp = plan_for(n, d + k, z.r_cap, cus, o);
   z.mp = moments_plan(z.r_cap, d, k, cus);
+  if (z.sp.log_t < 0) return RNNLS_E_UNSUPPORTED;
   const Layout L = layout_multi(z, k);
   if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -443,7 +451,7 @@ int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t s
   sj.r = z.r;
   sj.r_cap = z.r_cap;
   sj.mode = o.sample_mode;
-  sj.sign_log_t = z.sp.log_t;
+  sj.sign_log_t = z.sp.mfma ? 0 : z.sp.log_t;
   sj.sign_words = signs;
   sj.scratch = at<uint32_t>(ws, L.bern);
   sj.rows = rows;

@@ -202,8 +202,11 @@ struct SrhtPlan {
   int pieces;       // partial slots per column (main launch + rag)
   int spt;          // samples per thread
   int r_cap;
+  int mfma;         // 1: split-BF16 matrix-core transform (natural-order signs)
 };
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus);
+// log_t = -1 when the split-BF16 transform cannot serve these sizes
+SrhtPlan srht_plan_split_bf16(int64_t n, int ncols, int r_cap, int cus);
 int srht_pref_log_t(int m, int r_cap, int log_t_cap);
 int srht_spt(int log_t, int r_cap);
 int srht_wgs_per_cu(int log_t);

@@ -375,6 +375,236 @@ int launch_tiled(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, h
   }
 }
 
+// ---------------------------------------------------------------- split-BF16 matrix cores
+// Precision form of the in-tile transform.  Tile row j = a*1024 + b*32 + c.
+// H_T = H_A (x) H_32 (x) H_32 with A = T/1024: the two 32-point factors over
+// c and b run on v_mfma_f32_32x32x16_bf16 with the operand split
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and FP32 accumulation (H is
+// +-1, exact in BF16); the factor over a runs in FP32 on the vector units
+// after an LDS exchange.  Each split leaves a relative error of about 2^-16
+// per element.
+//
+// Matrix-core lane layout (32x32x16): lane l supplies A[l%32][8(l/32)+e] and
+// B[8(l/32)+e][l%32], e < 8, per 16-wide K half; D holds column l%32, rows
+// (v%4) + 8(v/4) + 4(l/32) in register v.  Stage 1 multiplies X_a[b][c] (A
+// operand, loaded straight from memory) by H over c; stage 2 takes stage 1's
+// D registers as its B operand as they are, with the rows of H permuted to
+// the rows each lane holds.  Sign words are in natural order (bit j % 32 of
+// word j / 32), so one word per lane covers its 16 elements of a block.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaThreads = 256;
+
+__device__ __forceinline__ void split8(const float* x, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+__device__ __forceinline__ __bf16 hsign(uint32_t i, uint32_t j) {
+  return (__popc(i & j) & 1) ? (__bf16)(-1.0f) : (__bf16)(1.0f);
+}
+
+// the 16 elements lane l of a wave contributes to block a of a tile:
+// X_a[b = l%32][c = 16 kh + 8 (l/32) + e]
+template <int LOG_T, int MODE>
+__device__ __forceinline__ void load_block(const SketchJob& J, int col, int64_t tile, int a,
+                                           float (&x)[16]) {
+  constexpr int T = 1 << LOG_T;
+  const int l = threadIdx.x & 63;
+  const float* base =
+      ((col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb) + tile * T;
+  const int64_t rem = J.n - tile * T;
+  const int lim = rem < T ? (int)rem : T;
+  const uint32_t sw = J.sign_words[((tile * T) >> 5) + a * 32 + (l & 31)];
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t off = (uint32_t)(a * 1024 + (l & 31) * 32 + 16 * kh + 8 * (l >> 5) + 4 * q);
+      float* v = x + 8 * kh + 4 * q;
+      if (MODE == kFullVec || (MODE == kEdgeVec && off + 4 <= (uint32_t)lim)) {
+        const float4 f = *reinterpret_cast<const float4*>(base + off);
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+        v[3] = f.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (off + e < (uint32_t)lim) ? base[off + e] : 0.0f;
+      }
+    }
+  }
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      x[8 * kh + e] = flip(x[8 * kh + e], (sw >> (16 * kh + 8 * (l >> 5) + e)) & 1u);
+}
+
+template <int LOG_T, int SPT, int MODE, bool RAG>
+__global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) {
+  constexpr int T = 1 << LOG_T;
+  constexpr int NA = T / 1024;            // blocks per tile
+  constexpr int NT = kMfmaThreads;
+  constexpr int WAVES = NT / 64;
+  __shared__ __attribute__((aligned(16))) float lds[T];
+
+  const int tid = threadIdx.x;
+  const int l = tid & 63, wv = tid >> 6, g = l >> 5;
+  const int64_t w = blockIdx.x;
+  const int64_t item_begin = (w * L.items) / L.grid;
+  const int64_t item_end = ((w + 1) * L.items) / L.grid;
+  if (item_begin >= item_end) return;
+
+  // constant Hadamard operands: stage 1 B[c][c'], stage 2 A[b'][row held]
+  bf16x8 hb1[2], ha2[2];
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      hb1[kh][e] = hsign(16 * kh + 8 * g + e, l & 31);
+      const uint32_t row = (e & 3) + 8 * ((e >> 2) + 2 * kh) + 4 * g;
+      ha2[kh][e] = hsign(l & 31, row);
+    }
+
+  int ji = 0;
+  int col;
+  int64_t tile;
+  locate<false, RAG>(L, item_begin, ji, col, tile);
+  int32_t srow[SPT];
+  float acc[SPT];
+  int count = load_rows<SPT, NT>(L.one, srow);
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
+
+  float xn[16];
+  load_block<LOG_T, MODE>(L.one, col, tile, wv, xn);
+  for (int64_t item = item_begin; item < item_end; ++item) {
+    const int cur_col = col;
+    const int64_t cur_tile = tile;
+    const int64_t next = item + 1;
+    // ---- stages 1 and 2 on the matrix cores, block by block
+    for (int a = wv; a < NA; a += WAVES) {
+      float x[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) x[e] = xn[e];
+      if (a + WAVES < NA) load_block<LOG_T, MODE>(L.one, cur_col, cur_tile, a + WAVES, xn);
+      bf16x8 hi0, lo0, hi1, lo1;
+      split8(x, hi0, lo0);
+      split8(x + 8, hi1, lo1);
+      f32x16 d1 = {};
+      d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi0, hb1[0], d1, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo0, hb1[0], d1, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi1, hb1[1], d1, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo1, hb1[1], d1, 0, 0, 0);
+      float y[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) y[v] = d1[v];
+      split8(y, hi0, lo0);
+      split8(y + 8, hi1, lo1);
+      f32x16 d2 = {};
+      d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha2[0], hi0, d2, 0, 0, 0);
+      d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha2[0], lo0, d2, 0, 0, 0);
+      d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha2[1], hi1, d2, 0, 0, 0);
+      d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha2[1], lo1, d2, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int bq = (v & 3) + 8 * (v >> 2) + 4 * g;
+        lds[a * 1024 + bq * 32 + (l & 31)] = d2[v];
+      }
+    }
+    // next item's first block, in flight during the rest of this one
+    if (!RAG && next < item_end) {
+      locate<false, RAG>(L, next, ji, col, tile);
+      load_block<LOG_T, MODE>(L.one, col, tile, wv, xn);
+    }
+    __syncthreads();
+    // ---- stage 3 over a, FP32 on the vector units
+#pragma unroll
+    for (int q = 0; q < 1024 / NT; ++q) {
+      const int pidx = tid + q * NT;
+      float u[NA > 1 ? NA : 1];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) u[a] = lds[a * 1024 + pidx];
+#pragma unroll
+      for (int bit = 1; bit < NA; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+          if (!(a & bit)) {
+            const float p0 = u[a], p1 = u[a | bit];
+            u[a] = p0 + p1;
+            u[a | bit] = p0 - p1;
+          }
+#pragma unroll
+      for (int a = 0; a < NA; ++a) lds[a * 1024 + pidx] = u[a];
+    }
+    __syncthreads();
+    // ---- pruned combine: y[i] += (-1)^popcount(i_hi & t) * z_t[i_lo]
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+      const int i = srow[s];
+      const float z = lds[i & (T - 1)];
+      const uint32_t par = (uint32_t)__popcll((uint64_t)(i >> LOG_T) & (uint64_t)cur_tile) & 1u;
+      acc[s] += flip(z, par);
+    }
+    __syncthreads();
+    const bool last_of_col = RAG || (next >= item_end) || (col != cur_col);
+    if (last_of_col) {
+      const SketchJob& J = L.one;
+      const int64_t tl = job_tiles<RAG>(J);
+      const int64_t first = job_item0<RAG>(J) + (int64_t)cur_col * tl;
+      const int piece = (RAG ? J.pieces - 1 : 0) + (int)(w - owner_of(first, L.items, L.grid));
+      float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
+#pragma unroll
+      for (int s = 0; s < SPT; ++s) {
+        const int li = tid + s * NT;
+        if (li < count) dst[li] = acc[s];
+        acc[s] = 0.0f;
+      }
+    }
+  }
+}
+
+template <int LOG_T, int SPT>
+int launch_mfma_t(const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+  const dim3 g((unsigned)L.grid), b(kMfmaThreads);
+  if (rag && vec)
+    hipLaunchKernelGGL((srht_mfma_kernel<LOG_T, SPT, kEdgeVec, true>), g, b, 0, s, L);
+  else if (rag)
+    hipLaunchKernelGGL((srht_mfma_kernel<LOG_T, SPT, kScalar, true>), g, b, 0, s, L);
+  else if (vec)
+    hipLaunchKernelGGL((srht_mfma_kernel<LOG_T, SPT, kFullVec, false>), g, b, 0, s, L);
+  else
+    hipLaunchKernelGGL((srht_mfma_kernel<LOG_T, SPT, kScalar, false>), g, b, 0, s, L);
+  return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+}
+
+template <int LOG_T>
+int launch_mfma_spt(int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+  switch (spt) {
+    case 1: return launch_mfma_t<LOG_T, 1>(L, vec, rag, s);
+    case 2: return launch_mfma_t<LOG_T, 2>(L, vec, rag, s);
+    case 4: return launch_mfma_t<LOG_T, 4>(L, vec, rag, s);
+    case 8: return launch_mfma_t<LOG_T, 8>(L, vec, rag, s);
+    case 16: return launch_mfma_t<LOG_T, 16>(L, vec, rag, s);
+    case 32: return launch_mfma_t<LOG_T, 32>(L, vec, rag, s);
+    default: return RNNLS_E_UNSUPPORTED;
+  }
+}
+
+int launch_mfma(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+  switch (log_t) {
+    case 14: return launch_mfma_spt<14>(spt, L, vec, rag, s);
+    case 15: return launch_mfma_spt<15>(spt, L, vec, rag, s);
+    default: return RNNLS_E_UNSUPPORTED;
+  }
+}
+
 std::atomic<int> g_log_tile{0}, g_wgs_per_cu{0};
 
 rnnls_tuning current_tuning() {
@@ -446,6 +676,35 @@ int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, in
   return pieces;
 }
 
+// Split-BF16 matrix-core plan: tiles of 2^15 rows (2^14 when n' = 2^14),
+// 256 threads, at most 32 kept rows per thread.
+SrhtPlan srht_plan_split_bf16(int64_t n, int ncols, int r_cap, int cus) {
+  SrhtPlan p{};
+  p.n = n;
+  p.n_pad = (int64_t)next_pow2((uint64_t)n);
+  p.ncols = ncols;
+  p.r_cap = r_cap;
+  const int m = ilog2_exact((uint64_t)p.n_pad);
+  if (m < 14 || r_cap > 32 * kMfmaThreads) {
+    p.log_t = -1;  // not available: the caller falls back or reports
+    return p;
+  }
+  const int tuned = g_log_tile.load();
+  p.log_t = (m == 14 || tuned == 14) ? 14 : 15;
+  p.mfma = 1;
+  int spt = 1;
+  while (spt * kMfmaThreads < r_cap) spt <<= 1;
+  p.spt = spt;
+  p.tiles = n >> p.log_t;
+  p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;
+  const int64_t items = (int64_t)ncols * p.tiles;
+  const int per_cu = g_wgs_per_cu.load() > 0 ? g_wgs_per_cu.load() : (p.log_t == 15 ? 1 : 2);
+  const int64_t cap = (int64_t)cus * per_cu;
+  p.grid = (int)(items < cap ? items : cap);
+  p.pieces = srht_owner_pieces(0, p.tiles, ncols, items, p.grid) + p.rag;
+  return p;
+}
+
 SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   SrhtPlan p{};
   p.n = n;
@@ -466,13 +725,14 @@ SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
 }
 
 size_t srht_partials_bytes(const SrhtPlan& p) {
-  if (p.log_t == 0) return 0;
+  if (p.log_t <= 0) return 0;
   return (size_t)p.ncols * p.pieces * p.r_cap * sizeof(float);
 }
 
 static bool aligned16(const void* ptr) { return ((uintptr_t)ptr % 16) == 0; }
 
 int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
+  if (p.log_t < 0) return RNNLS_E_UNSUPPORTED;
   const int threads = 256;
   const dim3 rgrid((p.r_cap + threads - 1) / threads, p.ncols);
   j.n = p.n;
@@ -502,12 +762,14 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   if (p.tiles > 0) {  // tiles fully inside A
     L.items = main_items;
     L.grid = p.grid;
-    rc = launch_tiled<false>(p.log_t, p.spt, L, vec, false, s);
+    rc = p.mfma ? launch_mfma(p.log_t, p.spt, L, vec, false, s)
+                : launch_tiled<false>(p.log_t, p.spt, L, vec, false, s);
   }
   if (rc == RNNLS_OK && p.rag) {  // the tile straddling row n, one per column
     L.items = p.ncols;
     L.grid = p.ncols;
-    rc = launch_tiled<false>(p.log_t, p.spt, L, vec, true, s);
+    rc = p.mfma ? launch_mfma(p.log_t, p.spt, L, vec, true, s)
+                : launch_tiled<false>(p.log_t, p.spt, L, vec, true, s);
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
