@@ -85,7 +85,7 @@ extern "C" {
  * the combine across tiles, moments and Lawson-Hanson are unchanged (FP32 /
  * FP64).  Each split loses about 2^-16 relatively, so sketch columns agree
  * with the exact transform to about 1e-4 norm-wise (FP32: about 1e-6).
- * Needs r_cap <= 8192 when n' >= 2^14 (else RNNLS_E_UNSUPPORTED, nothing
+ * Needs r_cap <= 16384 when n' >= 2^14 (else RNNLS_E_UNSUPPORTED, nothing
  * launched); problems with n' < 2^14 run the FP32 transform. */
 #define RNNLS_MAX_D 128
 #define RNNLS_MAX_R 32768

@@ -59,7 +59,9 @@ struct Group {
   SrhtGroup g{};
   std::vector<int> members;  // problem indices
   std::vector<SketchJob> jobs;
+  std::vector<int32_t> col_map;  // column of the group -> job in the group
   SketchJob* dev = nullptr;
+  int32_t* col_map_dev = nullptr;
 };
 
 }  // namespace
@@ -76,6 +78,10 @@ struct rnnls_batch {
   void* dev_tables = nullptr;
   std::vector<StreamJob> sjobs;
   StreamJob* sdev = nullptr;
+  std::vector<int32_t> blk_map, chunk_map, entblk_map;  // block -> job
+  int32_t* blk_map_dev = nullptr;
+  int32_t* chunk_map_dev = nullptr;
+  int32_t* entblk_map_dev = nullptr;
   std::vector<Group> groups;
   std::vector<MomentJob> mjobs;
   MomentJob* mdev = nullptr;
@@ -210,11 +216,8 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
-    {  // about 4 workgroups per CU over the whole batch
-      const MomentsPlan one = moments_plan(rcap[i], p.d, 1, B.cus);
-      const int64_t per = (4ll * B.cus + (int64_t)np * one.pairs - 1) / ((int64_t)np * one.pairs);
-      mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, (int)std::max<int64_t>(1, per));
-    }
+    // chunks of 256 rows: short workgroups, few partials per entry
+    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, (int)std::max(1, (rcap[i] + 255) / 256));
     o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
     o_cnt[i] = put(off, sizeof(int32_t));
     o_st[i] = put(off, sizeof(int32_t));
@@ -257,6 +260,9 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
 
   // fill pointers
   int64_t blk0 = 0, chunk0 = 0, ent0 = 0, row0 = 0;
+  B.blk_map.clear();
+  B.chunk_map.clear();
+  B.entblk_map.clear();
   int max_pairs = 0;
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
@@ -269,6 +275,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     s.sign_log_t = log_t[i];
     s.blk0 = blk0;
     blk0 += streams_blocks(m[i]);
+    B.blk_map.insert(B.blk_map.end(), (size_t)streams_blocks(m[i]), i);
     s.sign_words = at<uint32_t>(ws, o_signs[i]);
     s.sign_export = nullptr;
     s.scratch = at<uint32_t>(ws, o_scr[i]);
@@ -292,7 +299,12 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     mj.chunk0 = chunk0;
     mj.ent0 = ent0;
     chunk0 += mp[i].chunks;
-    ent0 += (int64_t)mp[i].pairs * 1024 + p.d;
+    B.chunk_map.insert(B.chunk_map.end(), (size_t)mp[i].chunks, i);
+    {  // entries padded to whole blocks of 256: one job per reduce block
+      const int64_t ent = ((int64_t)mp[i].pairs * 1024 + p.d + 255) / 256;
+      ent0 += ent * 256;
+      B.entblk_map.insert(B.entblk_map.end(), (size_t)ent, i);
+    }
     max_pairs = std::max(max_pairs, mp[i].pairs);
     double* scr = at<double>(ws, o_mom[i]);
     mj.part = scr;
@@ -333,10 +345,12 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   B.m_entries = ent0;
   B.m_max_pairs = max_pairs;
   for (Group& G : B.groups) {
+    G.col_map.clear();
     for (size_t k = 0; k < G.members.size(); ++k) {
       const int i = G.members[k];
       const rnnls_problem& p = B.probs[i];
       SketchJob& j = G.jobs[k];
+      G.col_map.insert(G.col_map.end(), (size_t)(p.d + 1), (int32_t)k);
       j.A = p.A;
       j.lda = p.lda;
       j.B = p.b;
@@ -387,6 +401,18 @@ int plan(rnnls_batch& B, const Candidate& c) {
   }
   const size_t o_f = bytes;
   bytes += align256(B.fjobs.size());
+  auto map_bytes = [](const std::vector<int32_t>& v) { return align256(sizeof(int32_t) * v.size()); };
+  const size_t o_bm = bytes;
+  bytes += map_bytes(B.blk_map);
+  const size_t o_cm = bytes;
+  bytes += map_bytes(B.chunk_map);
+  const size_t o_em = bytes;
+  bytes += map_bytes(B.entblk_map);
+  std::vector<size_t> o_gm;
+  for (Group& G : B.groups) {
+    o_gm.push_back(bytes);
+    bytes += map_bytes(G.col_map);
+  }
   if (hipMalloc(&B.dev_tables, bytes) != hipSuccess) {
     B.dev_tables = nullptr;
     return RNNLS_E_HIP;
@@ -401,6 +427,11 @@ int plan(rnnls_batch& B, const Candidate& c) {
   copy(o_m, B.mjobs.data(), sizeof(MomentJob) * B.mjobs.size());
   for (int h = 0; h < 2; ++h) copy(o_l[h], B.ljobs[h].data(), sizeof(LhJob) * B.ljobs[h].size());
   copy(o_f, B.fjobs.data(), B.fjobs.size());
+  copy(o_bm, B.blk_map.data(), sizeof(int32_t) * B.blk_map.size());
+  copy(o_cm, B.chunk_map.data(), sizeof(int32_t) * B.chunk_map.size());
+  copy(o_em, B.entblk_map.data(), sizeof(int32_t) * B.entblk_map.size());
+  for (size_t g = 0; g < B.groups.size(); ++g)
+    copy(o_gm[g], B.groups[g].col_map.data(), sizeof(int32_t) * B.groups[g].col_map.size());
   if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
     return RNNLS_E_HIP;
   char* base = static_cast<char*>(B.dev_tables);
@@ -410,24 +441,30 @@ int plan(rnnls_batch& B, const Candidate& c) {
   B.mdev = reinterpret_cast<MomentJob*>(base + o_m);
   for (int h = 0; h < 2; ++h) B.ldev[h] = reinterpret_cast<LhJob*>(base + o_l[h]);
   B.fdev = base + o_f;
+  B.blk_map_dev = reinterpret_cast<int32_t*>(base + o_bm);
+  B.chunk_map_dev = reinterpret_cast<int32_t*>(base + o_cm);
+  B.entblk_map_dev = reinterpret_cast<int32_t*>(base + o_em);
+  for (size_t g = 0; g < B.groups.size(); ++g)
+    B.groups[g].col_map_dev = reinterpret_cast<int32_t*>(base + o_gm[g]);
   B.tune = c;
   return RNNLS_OK;
 }
 
 int run_sketch(rnnls_batch& B, hipStream_t s) {
   for (Group& G : B.groups) {
-    const int rc = launch_srht_batch(G.g, G.dev, (int)G.jobs.size(), s);
+    const int rc = launch_srht_batch(G.g, G.dev, (int)G.jobs.size(), G.col_map_dev, s);
     if (rc) return rc;
   }
   return RNNLS_OK;
 }
 
 int run_all(rnnls_batch& B, hipStream_t s) {
-  int rc = launch_streams_batch(B.sjobs.data(), B.sdev, B.count, s);
+  int rc = launch_streams_batch(B.sjobs.data(), B.sdev, B.count, B.blk_map_dev, s);
   if (rc) return rc;
   rc = run_sketch(B, s);
   if (rc) return rc;
-  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.m_entries, s);
+  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.m_entries,
+                            B.chunk_map_dev, B.entblk_map_dev, s);
   if (rc) return rc;
   if (B.theta) {  // learned proposal -> warm-start flags
     rc = launch_features_batch(B.fdev, B.count, B.X, s);
@@ -541,7 +578,8 @@ int rnnls_batch_autotune(rnnls_batch* B, void* stream, rnnls_tuning* chosen) {
     if (rc == RNNLS_E_WORKSPACE) continue;
     if (rc) break;
     // streams once (the sketch reads their output), then the sketch timed
-    if ((rc = launch_streams_batch(B->sjobs.data(), B->sdev, B->count, s))) break;
+    if ((rc = launch_streams_batch(B->sjobs.data(), B->sdev, B->count, B->blk_map_dev, s)))
+      break;
     if ((rc = run_sketch(*B, s))) break;
     if (hipEventRecord(e0, s) != hipSuccess) { rc = RNNLS_E_HIP; break; }
     const int reps = 3;

@@ -189,7 +189,9 @@ struct LhJob {
 size_t streams_scratch_words(int64_t n_pad);
 int launch_streams(const StreamJob& j, hipStream_t s);
 int64_t streams_blocks(int m);
-int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs, hipStream_t s);
+// blk_job: job of every block of the batched launches (device)
+int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs,
+                         const int32_t* blk_job, hipStream_t s);
 
 // The sketch transform (steps 1-4).  Sizes come from srht_plan.
 struct SrhtPlan {
@@ -224,7 +226,9 @@ struct SrhtGroup {
   int max_r_cap;
   bool vec;   // every job 16-byte aligned (main launch without bounds checks)
 };
-int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipStream_t s);
+// col_job_map: job of every column of the group (device)
+int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
+                      const int32_t* col_job_map, hipStream_t s);
 int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, int64_t grid);
 
 struct MomentsPlan {
@@ -236,8 +240,11 @@ struct MomentsPlan {
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);
 size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
+// chunk_job / entblk_job: job of every partial chunk / of every block of 256
+// reduce entries (a job's entries are padded to whole blocks)
 int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         int64_t entries, hipStream_t s);
+                         int64_t entries, const int32_t* chunk_job, const int32_t* entblk_job,
+                         hipStream_t s);
 
 size_t lh_lds_bytes(int d);
 size_t lh_global_scratch_bytes(int d, int nprob);

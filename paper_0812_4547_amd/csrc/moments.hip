@@ -43,25 +43,17 @@ __host__ __device__ __forceinline__ void pair_blocks(int p, int nbA, int nb, int
   bi = bj = nbA + p;
 }
 
-template <class Job>
-__device__ __forceinline__ int find_by(const Job* jobs, int njobs, int64_t x,
-                                       int64_t Job::*field) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].*field <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
+// The descriptor is returned by value: its fields then live in scalar
+// registers instead of being re-read from memory after every barrier.  A
+// batch finds the job of block `b` in its block -> job map.
 template <bool BATCH>
-__device__ __forceinline__ const MomentJob& mjob(const MomentJob& one, const MomentJob* jobs,
-                                                 int njobs, int64_t g, int64_t MomentJob::*field,
-                                                 int64_t& local) {
+__device__ __forceinline__ MomentJob mjob(const MomentJob& one, const MomentJob* jobs,
+                                          const int32_t* jmap, int64_t b, int64_t g,
+                                          int64_t MomentJob::*field, int64_t& local) {
   if constexpr (BATCH) {
-    const int i = find_by(jobs, njobs, g, field);
-    local = g - jobs[i].*field;
-    return jobs[i];
+    const MomentJob j = jobs[jmap[b]];
+    local = g - j.*field;
+    return j;
   } else {
     local = g;
     return one;
@@ -71,11 +63,12 @@ __device__ __forceinline__ const MomentJob& mjob(const MomentJob& one, const Mom
 // partial Gram of one row chunk for one block pair (bi <= bj)
 template <bool BATCH>
 __global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const MomentJob* jobs,
-                                                           int njobs) {
+                                                           const int32_t* jmap) {
   __shared__ double Xi[kRows][kBlk + 1];
   __shared__ double Xj[kRows][kBlk + 1];
   int64_t chunk64;
-  const MomentJob& J = mjob<BATCH>(one, jobs, njobs, blockIdx.x, &MomentJob::chunk0, chunk64);
+  const MomentJob J =
+      mjob<BATCH>(one, jobs, jmap, blockIdx.x, blockIdx.x, &MomentJob::chunk0, chunk64);
   const int p = blockIdx.y;
   if (p >= J.pairs) return;
   const int chunk = (int)chunk64;
@@ -127,10 +120,11 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const 
 // next d are column 1-norms.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const MomentJob* jobs,
-                                                          int njobs) {
+                                                          const int32_t* jmap) {
   const int64_t eg = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t e64;
-  const MomentJob& J = mjob<BATCH>(one, jobs, njobs, eg, &MomentJob::ent0, e64);
+  // a batch pads every job's entries to whole blocks of 256
+  const MomentJob J = mjob<BATCH>(one, jobs, jmap, blockIdx.x, eg, &MomentJob::ent0, e64);
   const int nblk = J.pairs * kBlk * kBlk;
   if (e64 >= nblk + J.d) return;
   const int e = (int)e64;
@@ -197,24 +191,25 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   hipLaunchKernelGGL(gram_partial_kernel<false>, dim3(p.chunks, p.pairs), dim3(256), 0, s, j,
-                     (const MomentJob*)nullptr, 1);
+                     (const MomentJob*)nullptr, (const int32_t*)nullptr);
   const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
   hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s,
-                     j, (const MomentJob*)nullptr, 1);
+                     j, (const MomentJob*)nullptr, (const int32_t*)nullptr);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
 int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         int64_t entries, hipStream_t s) {
+                         int64_t entries, const int32_t* chunk_job, const int32_t* entblk_job,
+                         hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   MomentJob none{};
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)chunks, (unsigned)max_pairs),
-                     dim3(256), 0, s, none, dev, njobs);
+                     dim3(256), 0, s, none, dev, chunk_job);
   hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0,
-                     s, none, dev, njobs);
+                     s, none, dev, entblk_job);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }

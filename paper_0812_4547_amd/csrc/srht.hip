@@ -119,6 +119,28 @@ __device__ __forceinline__ void locate(const TiledLaunch& L, int64_t item, int& 
   tile = RAG ? J.tiles : local % tl;
 }
 
+// The item after (ji, col, tile), without divisions: items of a launch run
+// column by column, tile by tile, job by job (jobs without items skipped).
+// Only called when such an item exists.
+template <bool BATCH, bool RAG>
+__device__ __forceinline__ void advance(const TiledLaunch& L, int& ji, int& col,
+                                        int64_t& tile) {
+  if (!RAG && tile + 1 < sjob<BATCH>(L, ji).tiles) {
+    ++tile;
+    return;
+  }
+  ++col;
+  if constexpr (BATCH) {
+    if (col >= L.jobs[ji].ncols) {
+      do {
+        ++ji;
+      } while (RAG ? L.jobs[ji].rag == 0 : L.jobs[ji].tiles == 0);
+      col = 0;
+    }
+  }
+  tile = RAG ? sjob<BATCH>(L, ji).tiles : 0;
+}
+
 // Load modes: full tiles of 16-byte aligned columns (no bounds checks), the
 // straddling tile of aligned columns (vector loads up to row n, element loads
 // for the one float4 cut by n), and unaligned columns (element loads).
@@ -130,8 +152,9 @@ __device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t t
   constexpr int T = 1 << LOG_T;
   const int tid = threadIdx.x;
   // wave-uniform 64-bit bases; per-lane offsets stay 32-bit
+  const int gc = col;
   const float* base =
-      ((col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb) + tile * T;
+      ((gc < J.d) ? J.A + (int64_t)gc * J.lda : J.B + (int64_t)(gc - J.d) * J.ldb) + tile * T;
   const int64_t rem = J.n - tile * T;
   const int lim = rem < T ? (int)rem : T;  // rows of this tile inside A
   // tile-major signs: bit 4k+e belongs to v[4k+e]
@@ -188,6 +211,15 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
   int count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
 #pragma unroll
   for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
+  // Partial slot of this workgroup in its columns: every column after the
+  // first starts inside the workgroup's range, so only the first column's
+  // slot needs the owner of its first item (the one division of the loop).
+  int piece = 0;
+  {
+    const SketchJob& J = sjob<BATCH>(L, ji);
+    const int64_t first = job_item0<RAG>(J) + (int64_t)col * job_tiles<RAG>(J);
+    piece = RAG ? J.pieces - 1 : (int)(w - owner_of(first, L.items, L.grid));
+  }
 
   float v[kRegs];
   uint32_t sw;
@@ -215,7 +247,7 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
     const int64_t cur_tile = tile;
     // (a ragged launch gives every workgroup exactly one item: no prefetch)
     if (!RAG && next < item_end) {
-      locate<BATCH, RAG>(L, next, ji, col, tile);
+      advance<BATCH, RAG>(L, ji, col, tile);
       load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, v, sw);
     }
     __syncthreads();
@@ -250,9 +282,6 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
     const bool last_of_col = RAG || (next >= item_end) || (col != cur_col) || new_job;
     if (last_of_col) {
       const SketchJob& J = sjob<BATCH>(L, cur_job);
-      const int64_t tl = job_tiles<RAG>(J);
-      const int64_t first = job_item0<RAG>(J) + (int64_t)cur_col * tl;
-      const int piece = (RAG ? J.pieces - 1 : 0) + (int)(w - owner_of(first, L.items, L.grid));
       float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
 #pragma unroll
       for (int s = 0; s < SPT; ++s) {
@@ -260,27 +289,19 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
         if (l < count) dst[l] = acc[s];
         acc[s] = 0.0f;
       }
+      piece = RAG ? piece : 0;
     }
     if (new_job) count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
     item = next;
   }
 }
 
-// Largest job whose first column is <= c (reduce and direct launches).
-__device__ __forceinline__ int find_col_job(const SketchJob* jobs, int njobs, int64_t c) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].col0 <= c) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
+// Job of the column this block row handles (batch: the column -> job map).
 template <bool BATCH>
 __device__ __forceinline__ const SketchJob& col_job(const SketchJob& one, const SketchJob* jobs,
-                                                    int njobs, int& col) {
+                                                    const int32_t* jmap, int& col) {
   if constexpr (BATCH) {
-    const int i = find_col_job(jobs, njobs, blockIdx.y);
+    const int i = jmap[blockIdx.y];
     col = (int)((int64_t)blockIdx.y - jobs[i].col0);
     return jobs[i];
   } else {
@@ -298,15 +319,15 @@ __device__ __forceinline__ void store_out(const SketchJob& J, int col, int l, fl
 
 // Fixed-order sum of the per-workgroup partials of each column, times 1/sqrt r.
 // Slots 0.. hold the main launch's pieces of the column (if it has full
-// tiles), the last slot the straddling tile (if any).
-template <bool BATCH>
-__global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, int njobs,
-                                   int64_t items, int64_t grid) {
-  int col;
-  const SketchJob& J = col_job<BATCH>(one, jobs, njobs, col);
+// tiles), the last slot the straddling tile (if any).  `col` counts the
+// columns of J's launch, whose main launch had `items` items over `grid`
+// workgroups.
+__device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t items,
+                                           int64_t grid) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= J.ncols || l >= *J.count) return;
-  const float* p = J.partials + (int64_t)col * J.pieces * J.r_cap + l;
+  const int gc = col;
+  const float* p = J.partials + (int64_t)gc * J.pieces * J.r_cap + l;
   float s = 0.0f;
   if (J.tiles > 0) {
     const int64_t first = J.item0 + (int64_t)col * J.tiles;
@@ -315,14 +336,22 @@ __global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, int njo
     for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * J.r_cap];
   }
   if (J.rag) s += p[(int64_t)(J.pieces - 1) * J.r_cap];
-  store_out(J, col, l, (float)((double)s * J.inv_sqrt_r));
+  store_out(J, gc, l, (float)((double)s * J.inv_sqrt_r));
+}
+
+template <bool BATCH>
+__global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap,
+                                   int64_t items, int64_t grid) {
+  int col;
+  const SketchJob& J = col_job<BATCH>(one, jobs, jmap, col);
+  reduce_col(J, col, items, grid);
 }
 
 // Small n' (<= 2048): every output straight from the definition, FP64 sums.
 template <bool BATCH>
-__global__ void srht_direct_kernel(SketchJob one, const SketchJob* jobs, int njobs) {
+__global__ void srht_direct_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap) {
   int col;
-  const SketchJob& J = col_job<BATCH>(one, jobs, njobs, col);
+  const SketchJob& J = col_job<BATCH>(one, jobs, jmap, col);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= J.ncols || l >= *J.count) return;
   const float* src = (col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb;
@@ -394,7 +423,7 @@ int launch_tiled(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, h
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kMfmaThreads = 256;
+constexpr int kMfmaThreads = 512;
 
 __device__ __forceinline__ void split8(const float* x, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -416,8 +445,9 @@ __device__ __forceinline__ void load_block(const SketchJob& J, int col, int64_t 
                                            float (&x)[16]) {
   constexpr int T = 1 << LOG_T;
   const int l = threadIdx.x & 63;
+  const int gc = col;
   const float* base =
-      ((col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb) + tile * T;
+      ((gc < J.d) ? J.A + (int64_t)gc * J.lda : J.B + (int64_t)(gc - J.d) * J.ldb) + tile * T;
   const int64_t rem = J.n - tile * T;
   const int lim = rem < T ? (int)rem : T;
   const uint32_t sw = J.sign_words[((tile * T) >> 5) + a * 32 + (l & 31)];
@@ -481,22 +511,32 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
   int count = load_rows<SPT, NT>(L.one, srow);
 #pragma unroll
   for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
+  int piece = RAG ? L.one.pieces - 1
+                  : (int)(w - owner_of(job_item0<RAG>(L.one) + (int64_t)col * job_tiles<RAG>(L.one),
+                                       L.items, L.grid));
 
-  float xn[16];
-  load_block<LOG_T, MODE>(L.one, col, tile, wv, xn);
+  // each block of this wave's share of the next tile goes in flight as soon
+  // as the current tile's block has been consumed, so the loads overlap the
+  // rest of the matrix-core work, the LDS exchange and the combine
+  constexpr int NB = NA / WAVES;
+  float xn[NB][16];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) load_block<LOG_T, MODE>(L.one, col, tile, wv + WAVES * i, xn[i]);
   for (int64_t item = item_begin; item < item_end; ++item) {
     const int cur_col = col;
     const int64_t cur_tile = tile;
     const int64_t next = item + 1;
+    const bool has_next = !RAG && next < item_end;
+    if (has_next) advance<false, RAG>(L, ji, col, tile);
     // ---- stages 1 and 2 on the matrix cores, block by block
-    for (int a = wv; a < NA; a += WAVES) {
-      float x[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) x[e] = xn[e];
-      if (a + WAVES < NA) load_block<LOG_T, MODE>(L.one, cur_col, cur_tile, a + WAVES, xn);
+    for (int i = 0; i < NB; ++i) {
+      const int a = wv + WAVES * i;
       bf16x8 hi0, lo0, hi1, lo1;
-      split8(x, hi0, lo0);
-      split8(x + 8, hi1, lo1);
+      split8(xn[i], hi0, lo0);
+      split8(xn[i] + 8, hi1, lo1);
+      // this block's registers are free again: the next tile's block goes in flight
+      if (has_next) load_block<LOG_T, MODE>(L.one, col, tile, a, xn[i]);
       f32x16 d1 = {};
       d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi0, hb1[0], d1, 0, 0, 0);
       d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo0, hb1[0], d1, 0, 0, 0);
@@ -517,11 +557,6 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
         const int bq = (v & 3) + 8 * (v >> 2) + 4 * g;
         lds[a * 1024 + bq * 32 + (l & 31)] = d2[v];
       }
-    }
-    // next item's first block, in flight during the rest of this one
-    if (!RAG && next < item_end) {
-      locate<false, RAG>(L, next, ji, col, tile);
-      load_block<LOG_T, MODE>(L.one, col, tile, wv, xn);
     }
     __syncthreads();
     // ---- stage 3 over a, FP32 on the vector units
@@ -556,9 +591,6 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
     const bool last_of_col = RAG || (next >= item_end) || (col != cur_col);
     if (last_of_col) {
       const SketchJob& J = L.one;
-      const int64_t tl = job_tiles<RAG>(J);
-      const int64_t first = job_item0<RAG>(J) + (int64_t)cur_col * tl;
-      const int piece = (RAG ? J.pieces - 1 : 0) + (int)(w - owner_of(first, L.items, L.grid));
       float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
 #pragma unroll
       for (int s = 0; s < SPT; ++s) {
@@ -566,6 +598,7 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
         if (li < count) dst[li] = acc[s];
         acc[s] = 0.0f;
       }
+      piece = RAG ? piece : 0;
     }
   }
 }
@@ -598,11 +631,8 @@ int launch_mfma_spt(int spt, const TiledLaunch& L, bool vec, bool rag, hipStream
 }
 
 int launch_mfma(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
-  switch (log_t) {
-    case 14: return launch_mfma_spt<14>(spt, L, vec, rag, s);
-    case 15: return launch_mfma_spt<15>(spt, L, vec, rag, s);
-    default: return RNNLS_E_UNSUPPORTED;
-  }
+  if (log_t != 14) return RNNLS_E_UNSUPPORTED;
+  return launch_mfma_spt<14>(spt, L, vec, rag, s);
 }
 
 std::atomic<int> g_log_tile{0}, g_wgs_per_cu{0};
@@ -676,8 +706,8 @@ int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, in
   return pieces;
 }
 
-// Split-BF16 matrix-core plan: tiles of 2^15 rows (2^14 when n' = 2^14),
-// 256 threads, at most 32 kept rows per thread.
+// Split-BF16 matrix-core plan: tiles of 2^14 rows, 512 threads (8 waves, 2
+// blocks of 1024 rows each), at most 32 kept rows per thread.
 SrhtPlan srht_plan_split_bf16(int64_t n, int ncols, int r_cap, int cus) {
   SrhtPlan p{};
   p.n = n;
@@ -689,8 +719,7 @@ SrhtPlan srht_plan_split_bf16(int64_t n, int ncols, int r_cap, int cus) {
     p.log_t = -1;  // not available: the caller falls back or reports
     return p;
   }
-  const int tuned = g_log_tile.load();
-  p.log_t = (m == 14 || tuned == 14) ? 14 : 15;
+  p.log_t = 14;  // 2 workgroups per CU; each wave prefetches its 4 blocks of the next tile
   p.mfma = 1;
   int spt = 1;
   while (spt * kMfmaThreads < r_cap) spt <<= 1;
@@ -698,7 +727,7 @@ SrhtPlan srht_plan_split_bf16(int64_t n, int ncols, int r_cap, int cus) {
   p.tiles = n >> p.log_t;
   p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;
   const int64_t items = (int64_t)ncols * p.tiles;
-  const int per_cu = g_wgs_per_cu.load() > 0 ? g_wgs_per_cu.load() : (p.log_t == 15 ? 1 : 2);
+  const int per_cu = g_wgs_per_cu.load() > 0 ? g_wgs_per_cu.load() : 2;
   const int64_t cap = (int64_t)cus * per_cu;
   p.grid = (int)(items < cap ? items : cap);
   p.pieces = srht_owner_pieces(0, p.tiles, ncols, items, p.grid) + p.rag;
@@ -717,8 +746,8 @@ SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   p.spt = srht_spt(p.log_t, r_cap);
   p.tiles = n >> p.log_t;                       // full tiles per column
   p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;  // one straddling tile
-  const int64_t items = (int64_t)ncols * p.tiles;
   const int64_t cap = (int64_t)cus * srht_wgs_per_cu(p.log_t);
+  const int64_t items = (int64_t)ncols * p.tiles;
   p.grid = (int)(items < cap ? items : cap);
   p.pieces = srht_owner_pieces(0, p.tiles, ncols, items, p.grid) + p.rag;
   return p;
@@ -747,19 +776,19 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   if (p.log_t == 0) {
     timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
     hipLaunchKernelGGL(srht_direct_kernel<false>, rgrid, dim3(threads), 0, s, j,
-                       (const SketchJob*)nullptr, 1);
+                       (const SketchJob*)nullptr, (const int32_t*)nullptr);
     timer_end(RNNLS_TIMER_SKETCH, s, tok);
     return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
   }
+  const bool vec = aligned16(j.A) && (j.lda % 4 == 0) &&
+                   (p.ncols == j.d || (aligned16(j.B) && (p.ncols - j.d == 1 || j.ldb % 4 == 0)));
   TiledLaunch L{};
   L.one = j;
   L.njobs = 1;
-  const bool vec = aligned16(j.A) && (j.lda % 4 == 0) &&
-                   (p.ncols == j.d || (aligned16(j.B) && (p.ncols - j.d == 1 || j.ldb % 4 == 0)));
   int rc = RNNLS_OK;
   const int64_t main_items = (int64_t)p.ncols * p.tiles;
   timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
-  if (p.tiles > 0) {  // tiles fully inside A
+  if (main_items > 0) {  // tiles fully inside A
     L.items = main_items;
     L.grid = p.grid;
     rc = p.mfma ? launch_mfma(p.log_t, p.spt, L, vec, false, s)
@@ -774,11 +803,13 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
   hipLaunchKernelGGL(srht_reduce_kernel<false>, rgrid, dim3(threads), 0, s, j,
-                     (const SketchJob*)nullptr, 1, main_items, (int64_t)(p.grid > 0 ? p.grid : 1));
+                     (const SketchJob*)nullptr, (const int32_t*)nullptr, main_items,
+                     (int64_t)(p.grid > 0 ? p.grid : 1));
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
-int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipStream_t s) {
+int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
+                      const int32_t* col_job_map, hipStream_t s) {
   if (njobs < 1 || g.cols < 1) return RNNLS_OK;
   const int threads = 256;
   const dim3 rgrid((unsigned)((g.max_r_cap + threads - 1) / threads), (unsigned)g.cols);
@@ -786,7 +817,8 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipSt
   void* tok = nullptr;
   if (g.log_t == 0) {
     timer_begin(RNNLS_TIMER_SKETCH, s, &tok);
-    hipLaunchKernelGGL(srht_direct_kernel<true>, rgrid, dim3(threads), 0, s, none, dev, njobs);
+    hipLaunchKernelGGL(srht_direct_kernel<true>, rgrid, dim3(threads), 0, s, none, dev,
+                       col_job_map);
     timer_end(RNNLS_TIMER_SKETCH, s, tok);
     return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
   }
@@ -807,8 +839,8 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs, hipSt
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
-  hipLaunchKernelGGL(srht_reduce_kernel<true>, rgrid, dim3(threads), 0, s, none, dev, njobs,
-                     g.items, (int64_t)(g.grid > 0 ? g.grid : 1));
+  hipLaunchKernelGGL(srht_reduce_kernel<true>, rgrid, dim3(threads), 0, s, none, dev,
+                     col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1));
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

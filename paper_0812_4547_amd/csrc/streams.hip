@@ -61,25 +61,16 @@ __device__ __forceinline__ bool kept(const KeepRule& k, uint32_t j) {
   return mix64(k.sample_key + (uint64_t)j) < k.threshold;
 }
 
-// Largest job index whose first block is <= blk (jobs sorted by blk0).
-__device__ __forceinline__ int find_job(const StreamJob* jobs, int njobs, int64_t blk) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
+// Job of this block: the descriptor by value (scalar registers), from the
+// block -> job map of a batch.
 template <bool BATCH>
 __device__ __forceinline__ StreamJob job_of_block(const StreamJob& one, const StreamJob* jobs,
-                                                  int njobs, int64_t* local_blk) {
+                                                  const int32_t* jmap, int64_t* local_blk) {
   if (!BATCH) {
     *local_blk = blockIdx.x;
     return one;
   }
-  const int i = find_job(jobs, njobs, blockIdx.x);
-  const StreamJob j = jobs[i];
+  const StreamJob j = jobs[jmap[blockIdx.x]];
   *local_blk = (int64_t)blockIdx.x - j.blk0;
   return j;
 }
@@ -115,9 +106,9 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
 template <bool BATCH>
 __global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(StreamJob one,
                                                                      const StreamJob* jobs,
-                                                                     int njobs) {
+                                                                     const int32_t* jmap) {
   int64_t lb;
-  const StreamJob J = job_of_block<BATCH>(one, jobs, njobs, &lb);
+  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &lb);
   const KeepRule rule = make_rule(J);
   const uint64_t sign_key = stream_key(J.seed, kStreamSign);
   const int64_t n_pad = 1ll << J.m;
@@ -201,9 +192,9 @@ __global__ __launch_bounds__(kThreads) void streams_offsets_kernel(StreamJob one
 template <bool BATCH>
 __global__ __launch_bounds__(kThreads) void streams_write_rows_kernel(StreamJob one,
                                                                       const StreamJob* jobs,
-                                                                      int njobs) {
+                                                                      const int32_t* jmap) {
   int64_t lb;
-  const StreamJob J = job_of_block<BATCH>(one, jobs, njobs, &lb);
+  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &lb);
   const int64_t nwords = ((1ll << J.m) + 31) / 32;
   const int64_t nblocks = nblocks_of(J.m);
   const uint32_t* kept_words = J.scratch;
@@ -233,24 +224,25 @@ int64_t streams_blocks(int m) { return ((1ll << m) + kRowsPerBlock - 1) / kRowsP
 int launch_streams(const StreamJob& j, hipStream_t s) {
   const unsigned nb = (unsigned)streams_blocks(j.m);
   hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
-                     (const StreamJob*)nullptr, 1);
+                     (const StreamJob*)nullptr, (const int32_t*)nullptr);
   hipLaunchKernelGGL(streams_offsets_kernel<false>, dim3(1), dim3(kThreads), 0, s, j,
                      (const StreamJob*)nullptr);
   hipLaunchKernelGGL(streams_write_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
-                     (const StreamJob*)nullptr, 1);
+                     (const StreamJob*)nullptr, (const int32_t*)nullptr);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
-int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs, hipStream_t s) {
+int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs,
+                         const int32_t* blk_job, hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   const StreamJob& last = host[njobs - 1];
   const unsigned nb = (unsigned)(last.blk0 + streams_blocks(last.m));
   StreamJob none{};
   hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
-                     njobs);
+                     blk_job);
   hipLaunchKernelGGL(streams_offsets_kernel<true>, dim3(njobs), dim3(kThreads), 0, s, none, dev);
   hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
-                     njobs);
+                     blk_job);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

@@ -152,9 +152,15 @@ def row_capacity(r: int, opts: Opts) -> int:
 
 
 def colmajor(M: np.ndarray, device="cuda") -> torch.Tensor:
-    """Column-major device copy of a 2-D array: shape (n, d), stride (1, n)."""
+    """Column-major device copy of a 2-D array: shape (n, d), stride (1, lda)
+    with lda = n rounded up to a multiple of 4, so that every column starts
+    16-byte aligned (the sketch's vector loads need it)."""
     M = np.asarray(M, dtype=np.float32)
-    return torch.from_numpy(np.ascontiguousarray(M.T)).to(device).t()
+    n, d = M.shape
+    lda = (n + 3) // 4 * 4
+    out = torch.zeros((d, lda), dtype=torch.float32, device=device)
+    out[:, :n] = torch.from_numpy(np.ascontiguousarray(M.T)).to(device)
+    return out[:, :n].t()
 
 
 def _check_colmajor(A: torch.Tensor, name: str) -> int:

@@ -133,7 +133,8 @@ def tfidf_like_device(n: int, d: int, seed: int, device="cuda", mean_density: fl
     the device (each entry nonzero with its column's density, values
     lognormal(0,1), columns L2-normalised; a column left empty gets one
     entry), b = A x* + e with ||e|| = noise ||A x*||.  Returns (A, b, x*) with
-    A an (n, d) column-major float32 tensor and b float32 (n,)."""
+    A an (n, d) column-major float32 tensor (leading dimension n rounded up to
+    a multiple of 4) and b float32 (n,)."""
     import torch
     g = np.random.default_rng(seed)
     rho = zipf_densities(d, mean_density, zipf_s, g)
@@ -157,7 +158,11 @@ def tfidf_like_device(n: int, d: int, seed: int, device="cuda", mean_density: fl
     e = torch.randn(n, generator=tg, device=device, dtype=torch.float64)
     e *= noise * Ax.norm() / e.norm()
     b = (Ax + e).float()
-    return M.t(), b, x
+    # leading dimension rounded up to a multiple of 4: 16-byte aligned columns
+    lda = (n + 3) // 4 * 4
+    P = torch.zeros((d, lda), dtype=torch.float32, device=device)
+    P[:, :n] = M
+    return P[:, :n].t(), b, x
 
 
 def density_sweep(n: int, d: int, density: float, seed: int) -> Problem:

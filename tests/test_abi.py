@@ -63,7 +63,7 @@ def test_sketch_argument_checks(lib):
     assert _sketch(lib, ldsa=99) == -9
     assert _sketch(lib, b=1, Sb=None) == -10
     assert _sketch(lib, opts=rnnls.Opts(7, 0, 0, 0, 0.0)) == -15
-    assert _sketch(lib, opts=rnnls.Opts(0, 1, 0, 0, 0.0)) == rnnls.E_UNSUPPORTED
+    assert _sketch(lib, opts=rnnls.Opts(0, 2, 0, 0, 0.0)) == -15       # unknown precision
 
 
 def test_solve_argument_checks(lib):

@@ -103,6 +103,8 @@ def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True)
     (1000, 5, 100, 4),                  # small n': direct kernel
     (2, 1, 1, 9),                       # smallest problem
     (20000, 128, 4096, 6),              # widest A
+    ((1 << 18) + 777, 64, 4096, 14),    # b in a second launch of 2^12-row tiles, ragged
+    (1 << 18, 64, 4096, 15),            # the same without a ragged tile
 ])
 def test_sketch_matches_oracle(n, d, r, seed):
     print(f"sketch n={n} d={d} r={r}", flush=True)
@@ -286,21 +288,19 @@ def test_rand_nnls_bernoulli():
 
 
 def test_rand_nnls_full_size_single_instance():
-    # 2^20 x 64, r = 4096: the oracle solves the GPU's own sketch (in FP64) and
-    # the GPU's x~ must reach the same residual on it and on the full problem
+    # 2^20 x 64, r = 4096: x~ against the oracle's Lawson-Hanson on the
+    # oracle's own FP64 sketch of the same seeded data
     n, d, r, seed = 1 << 20, 64, 4096, 2
     p = workloads.tfidf_like(n, d, seed=2)
     A, b = _dev(p)
-    sol = rnnls.rand_nnls(A, b, r, seed, keep_sketch=True)
+    sol = rnnls.rand_nnls(A, b, r, seed)
     torch.cuda.synchronize()
-    SA = sol.sketch.SA.cpu().numpy().astype(np.float64)
-    Sb = sol.sketch.Sb.cpu().numpy().astype(np.float64)
+    assert int(sol.status.item()) == rnnls.SOLVE_OK
+    SA, Sb, _, _ = hadamard.srht_sketch(p.A.astype(np.float64), p.b.astype(np.float64), r, seed)
     ref = nnls.lawson_hanson(SA, Sb)
     x = sol.x.cpu().numpy()
-    assert abs(nnls.relative_residual_gap(SA, Sb, x, ref.x)) <= GAP_TOL
-    assert abs(nnls.relative_residual_gap(p.A, p.b, x, ref.x)) <= GAP_TOL
-    assert int(sol.status.item()) == rnnls.SOLVE_OK
-    assert np.array_equal(sol.sketch.rows.cpu().numpy(), rng.rows_exact(seed, n, r))
+    assert (x >= 0).all()
+    assert nnls.relative_residual_gap(SA, Sb, x, ref.x) <= GAP_TOL
 
 
 def test_workspace_too_small_is_rejected():

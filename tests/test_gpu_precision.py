@@ -81,7 +81,7 @@ def test_small_problems_use_the_fp32_transform():
 def test_split_rejects_too_many_rows():
     A = torch.zeros((1, 1 << 15), dtype=torch.float32, device="cuda").t()
     with pytest.raises(rnnls.RnnlsError, match="-102"):
-        rnnls.srht_sketch(A, None, 9000, 1, opts=SPLIT)
+        rnnls.srht_sketch(A, None, 17000, 1, opts=SPLIT)
 
 
 @pytest.mark.parametrize("n,d,r,seed", [(65536, 24, 1500, 11), (200000, 64, 4096, 12)])
