@@ -4,8 +4,9 @@
 // Problems are grouped by the tile size their sketch uses (2^12..2^15, or the
 // direct kernel for n' <= 2048).  Per pass the plan launches: the random
 // streams of every problem (3 launches), per group the persistent sketch
-// kernel over all (problem, column, tile) items of the group, its ragged-tile
-// launch and its reduce, the moments of every problem (2 launches), and
+// kernel over all (problem, column, tile) items of the group (tiles cut by
+// row n included, with bounds-checked vector loads) and
+// its reduce, the moments of every problem (2 launches), and
 // Lawson-Hanson for every problem (one launch for d <= 64, one for d > 64;
 // one wavefront per problem).  Descriptors of every problem live in device
 // tables built once at plan time; the workspace is bound at plan time too, so
@@ -163,10 +164,8 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     for (int i : G.members) {
       const rnnls_problem& p = B.probs[i];
       const int ncols = p.d + 1;
-      if (G.g.log_t > 0) {
-        items += (int64_t)ncols * (p.n >> G.g.log_t);
-        items_rag += (p.n & ((1ll << G.g.log_t) - 1)) ? ncols : 0;
-      }
+      if (G.g.log_t > 0)  // tiles cut by row n run in the same launch
+        items += (int64_t)ncols * ((p.n + (1ll << G.g.log_t) - 1) >> G.g.log_t);
       cols += ncols;
       max_rc = std::max(max_rc, rcap[i]);
       vec = vec && aligned16(p.A) && p.lda % 4 == 0 && aligned16(p.b);
@@ -201,13 +200,12 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
       j.col0 = col0;
       col0 += ncols;
       if (G.g.log_t > 0) {
-        j.tiles = p.n >> G.g.log_t;
-        j.rag = (p.n & ((1ll << G.g.log_t) - 1)) ? 1 : 0;
+        j.tiles = (p.n + (1ll << G.g.log_t) - 1) >> G.g.log_t;
+        j.rag = 0;
         j.item0 = item0;
         j.item0_rag = item0_rag;
         item0 += (int64_t)ncols * j.tiles;
-        item0_rag += j.rag ? ncols : 0;
-        j.pieces = srht_owner_pieces(j.item0, j.tiles, ncols, G.g.items, G.g.grid) + j.rag;
+        j.pieces = srht_owner_pieces(j.item0, j.tiles, ncols, G.g.items, G.g.grid);
       }
       pieces[i] = j.pieces;
       G.jobs.push_back(j);

@@ -324,19 +324,22 @@ __device__ __forceinline__ void store_out(const SketchJob& J, int col, int l, fl
 // workgroups.
 __device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t items,
                                            int64_t grid) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= J.ncols || l >= *J.count) return;
-  const int gc = col;
-  const float* p = J.partials + (int64_t)gc * J.pieces * J.r_cap + l;
-  float s = 0.0f;
+  if (col >= J.ncols) return;
+  const int count = *J.count;
+  int64_t npieces = 0;
   if (J.tiles > 0) {
     const int64_t first = J.item0 + (int64_t)col * J.tiles;
-    const int64_t w0 = owner_of(first, items, grid);
-    const int64_t w1 = owner_of(first + J.tiles - 1, items, grid);
-    for (int64_t k = 0; k <= w1 - w0; ++k) s += p[k * J.r_cap];
+    npieces = owner_of(first + J.tiles - 1, items, grid) - owner_of(first, items, grid) + 1;
   }
-  if (J.rag) s += p[(int64_t)(J.pieces - 1) * J.r_cap];
-  store_out(J, gc, l, (float)((double)s * J.inv_sqrt_r));
+  const float* base = J.partials + (int64_t)col * J.pieces * J.r_cap;
+  // the block's threads stride over the kept rows of the column
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < count; l += gridDim.x * blockDim.x) {
+    const float* p = base + l;
+    float s = 0.0f;
+    for (int64_t k = 0; k < npieces; ++k) s += p[k * J.r_cap];
+    if (J.rag) s += p[(int64_t)(J.pieces - 1) * J.r_cap];
+    store_out(J, col, l, (float)((double)s * J.inv_sqrt_r));
+  }
 }
 
 template <bool BATCH>
@@ -352,24 +355,32 @@ template <bool BATCH>
 __global__ void srht_direct_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap) {
   int col;
   const SketchJob& J = col_job<BATCH>(one, jobs, jmap, col);
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= J.ncols || l >= *J.count) return;
+  if (col >= J.ncols) return;
+  const int count = *J.count;
   const float* src = (col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb;
-  const uint32_t i = (uint32_t)J.rows[l];
-  double acc = 0.0;
-  for (int64_t j = 0; j < J.n; ++j) {
-    const uint32_t sgn = ((J.sign_words[j >> 5] >> (j & 31)) ^ __popc(i & (uint32_t)j)) & 1u;
-    const double x = (double)src[j];
-    acc += sgn ? -x : x;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < count; l += gridDim.x * blockDim.x) {
+    const uint32_t i = (uint32_t)J.rows[l];
+    double acc = 0.0;
+    for (int64_t j = 0; j < J.n; ++j) {
+      const uint32_t sgn = ((J.sign_words[j >> 5] >> (j & 31)) ^ __popc(i & (uint32_t)j)) & 1u;
+      const double x = (double)src[j];
+      acc += sgn ? -x : x;
+    }
+    store_out(J, col, l, (float)(acc * J.inv_sqrt_r));
   }
-  store_out(J, col, l, (float)(acc * J.inv_sqrt_r));
 }
 
+// edge: the main launch also holds tiles cut by row n (batches), so its
+// vector loads are bounds-checked per float4.
 template <int LOG_T, int SPT, bool BATCH>
-int launch_tiled_t(const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+int launch_tiled_t(const TiledLaunch& L, bool vec, bool rag, hipStream_t s, bool edge = false) {
   constexpr int NT = (1 << LOG_T) / kRegs;
   const dim3 g((unsigned)L.grid), b(NT);
-  if (rag && vec)
+  if (BATCH && edge && vec && !rag)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kEdgeVec, BATCH, false>), g, b, 0, s, L);
+  else if (BATCH && edge && !rag)
+    hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kScalar, BATCH, false>), g, b, 0, s, L);
+  else if (rag && vec)
     hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kEdgeVec, BATCH, true>), g, b, 0, s, L);
   else if (rag)
     hipLaunchKernelGGL((srht_tiled_kernel<LOG_T, SPT, kScalar, BATCH, true>), g, b, 0, s, L);
@@ -381,25 +392,27 @@ int launch_tiled_t(const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
 }
 
 template <int LOG_T, bool BATCH>
-int launch_tiled_spt(int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+int launch_tiled_spt(int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s,
+                     bool edge) {
   switch (spt) {
-    case 1: return launch_tiled_t<LOG_T, 1, BATCH>(L, vec, rag, s);
-    case 2: return launch_tiled_t<LOG_T, 2, BATCH>(L, vec, rag, s);
-    case 4: return launch_tiled_t<LOG_T, 4, BATCH>(L, vec, rag, s);
-    case 8: return launch_tiled_t<LOG_T, 8, BATCH>(L, vec, rag, s);
-    case 16: return launch_tiled_t<LOG_T, 16, BATCH>(L, vec, rag, s);
-    case 32: return launch_tiled_t<LOG_T, 32, BATCH>(L, vec, rag, s);
+    case 1: return launch_tiled_t<LOG_T, 1, BATCH>(L, vec, rag, s, edge);
+    case 2: return launch_tiled_t<LOG_T, 2, BATCH>(L, vec, rag, s, edge);
+    case 4: return launch_tiled_t<LOG_T, 4, BATCH>(L, vec, rag, s, edge);
+    case 8: return launch_tiled_t<LOG_T, 8, BATCH>(L, vec, rag, s, edge);
+    case 16: return launch_tiled_t<LOG_T, 16, BATCH>(L, vec, rag, s, edge);
+    case 32: return launch_tiled_t<LOG_T, 32, BATCH>(L, vec, rag, s, edge);
     default: return RNNLS_E_UNSUPPORTED;
   }
 }
 
 template <bool BATCH>
-int launch_tiled(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s) {
+int launch_tiled(int log_t, int spt, const TiledLaunch& L, bool vec, bool rag, hipStream_t s,
+                 bool edge = false) {
   switch (log_t) {
-    case 12: return launch_tiled_spt<12, BATCH>(spt, L, vec, rag, s);
-    case 13: return launch_tiled_spt<13, BATCH>(spt, L, vec, rag, s);
-    case 14: return launch_tiled_spt<14, BATCH>(spt, L, vec, rag, s);
-    case 15: return launch_tiled_spt<15, BATCH>(spt, L, vec, rag, s);
+    case 12: return launch_tiled_spt<12, BATCH>(spt, L, vec, rag, s, edge);
+    case 13: return launch_tiled_spt<13, BATCH>(spt, L, vec, rag, s, edge);
+    case 14: return launch_tiled_spt<14, BATCH>(spt, L, vec, rag, s, edge);
+    case 15: return launch_tiled_spt<15, BATCH>(spt, L, vec, rag, s, edge);
     default: return RNNLS_E_UNSUPPORTED;
   }
 }
@@ -812,7 +825,7 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
                       const int32_t* col_job_map, hipStream_t s) {
   if (njobs < 1 || g.cols < 1) return RNNLS_OK;
   const int threads = 256;
-  const dim3 rgrid((unsigned)((g.max_r_cap + threads - 1) / threads), (unsigned)g.cols);
+  const dim3 rgrid(1u, (unsigned)g.cols);
   SketchJob none{};
   void* tok = nullptr;
   if (g.log_t == 0) {
@@ -830,7 +843,7 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
   if (g.items > 0) {
     L.items = g.items;
     L.grid = g.grid;
-    rc = launch_tiled<true>(g.log_t, g.spt, L, g.vec, false, s);
+    rc = launch_tiled<true>(g.log_t, g.spt, L, g.vec, false, s, true);
   }
   if (rc == RNNLS_OK && g.items_rag > 0) {
     L.items = g.items_rag;
