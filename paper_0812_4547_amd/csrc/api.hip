@@ -62,7 +62,7 @@ int row_capacity(int r, const Opts& o) {
 // Workspace layout; every region 256-byte aligned.
 struct Layout {
   size_t rows = 0, count = 0, status = 0, signs = 0, bern = 0, partials = 0, sa = 0, sb = 0,
-         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, lh = 0, total = 0;
+         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, total = 0;
 };
 
 size_t put(size_t& off, size_t bytes) {
@@ -95,7 +95,6 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
     L.q = put(off, sizeof(double) * (size_t)z.d);
     L.cc = put(off, sizeof(double));
     L.colabs = put(off, sizeof(double) * (size_t)z.d);
-    L.lh = put(off, lh_global_scratch_bytes(z.d, 1));
   }
   L.total = off;
   return L;
@@ -118,7 +117,6 @@ Layout layout_multi(const Sizes& z, int k) {
   L.q = put(off, sizeof(double) * (size_t)z.d * k);
   L.cc = put(off, sizeof(double) * (size_t)k);
   L.colabs = put(off, sizeof(double) * (size_t)z.d);
-  L.lh = put(off, lh_global_scratch_bytes(z.d, k));
   L.total = off;
   return L;
 }
@@ -131,7 +129,6 @@ Layout layout_solve(const Sizes& z) {
   L.q = put(off, sizeof(double) * (size_t)z.d);
   L.cc = put(off, sizeof(double));
   L.colabs = put(off, sizeof(double) * (size_t)z.d);
-  L.lh = put(off, lh_global_scratch_bytes(z.d, 1));
   L.total = off;
   return L;
 }
@@ -223,7 +220,7 @@ MomentJob moment_job(const MomentsPlan& mp, const float* M, int64_t ldm, const f
 
 LhJob lh_job(int d, int64_t m, const int32_t* m_dev, const Opts& o, const double* G,
              const double* q, const double* c, const double* colabs, const int32_t* pre_status,
-             double* x, double* w, double* rnorm, int32_t* iters, int32_t* status, double* qp) {
+             double* x, double* w, double* rnorm, int32_t* iters, int32_t* status) {
   LhJob j{};
   j.d = d;
   j.max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
@@ -244,7 +241,6 @@ LhJob lh_job(int d, int64_t m, const int32_t* m_dev, const Opts& o, const double
   j.rnorm = rnorm;
   j.iters = iters;
   j.status = status;
-  j.qp_global = qp;
   return j;
 }
 
@@ -357,9 +353,8 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   int rc = launch_moments(
       z.mp, moment_job(z.mp, M, ldm, f, m, m_dev, at<double>(ws, L.mom), G, q, d, cc, colabs), s);
   if (rc) return rc;
-  return launch_lawson_hanson(lh_job(d, m, m_dev, o, G, q, cc, colabs, nullptr, x, w, rnorm, iters,
-                                     status, at<double>(ws, L.lh)),
-                              1, s);
+  return launch_lawson_hanson(
+      lh_job(d, m, m_dev, o, G, q, cc, colabs, nullptr, x, w, rnorm, iters, status), 1, s);
 }
 
 int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A, int64_t lda,
@@ -399,9 +394,8 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
       z.mp, moment_job(z.mp, sa, ld, sb, z.r_cap, cnt, at<double>(ws, L.mom), G, q, d, cc, colabs),
       s);
   if (rc) return rc;
-  return launch_lawson_hanson(lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm,
-                                     iters, status, at<double>(ws, L.lh)),
-                              1, s);
+  return launch_lawson_hanson(
+      lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm, iters, status), 1, s);
 }
 
 size_t rnnls_multi_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t r,
@@ -485,8 +479,7 @@ int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t s
                                  Q, d, cc, colabs),
                       s);
   if (rc) return rc;
-  LhJob lj = lh_job(d, z.r_cap, cnt, o, G, Q, cc, colabs, st, X, nullptr, rnorm, iters, status,
-                    at<double>(ws, L.lh));
+  LhJob lj = lh_job(d, z.r_cap, cnt, o, G, Q, cc, colabs, st, X, nullptr, rnorm, iters, status);
   lj.G_stride = 0;        // one G for all right-hand sides
   lj.colabs_stride = 0;
   lj.m_dev_stride = 0;

@@ -182,7 +182,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
 
   size_t off = 0;
   std::vector<size_t> o_rows(np), o_cnt(np), o_st(np), o_signs(np), o_scr(np), o_part(np),
-      o_sa(np), o_sb(np), o_mom(np), o_G(np), o_q(np), o_c(np), o_abs(np), o_qp(np);
+      o_sa(np), o_sb(np), o_mom(np), o_G(np), o_q(np), o_c(np), o_abs(np);
   std::vector<int> pieces(np, 0);
   std::vector<MomentsPlan> mp(np);
   // sketch items and pieces per group
@@ -229,19 +229,6 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     o_q[i] = put(off, sizeof(double) * (size_t)p.d);
     o_c[i] = put(off, sizeof(double));
     o_abs[i] = put(off, sizeof(double) * (size_t)p.d);
-  }
-  // Lawson-Hanson: Q[:,P] goes to global memory when the launch's widest
-  // problem does not fit it in LDS
-  int maxd[2] = {0, 0};
-  for (int i = 0; i < np; ++i) {
-    const int h = B.probs[i].d > 64;
-    maxd[h] = std::max(maxd[h], B.probs[i].d);
-  }
-  for (int i = 0; i < np; ++i) {
-    const int h = B.probs[i].d > 64;
-    o_qp[i] = (maxd[h] > 0 && !lh_qp_in_lds(maxd[h]))
-                  ? put(off, sizeof(double) * (size_t)(B.probs[i].d + 1) * (B.probs[i].d | 1))
-                  : (size_t)-1;
   }
   int64_t columns = 0;
   for (int i = 0; i < np; ++i) columns += B.probs[i].d;
@@ -329,7 +316,6 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     lj.rnorm = p.rnorm;
     lj.iters = p.iters;
     lj.status = p.status;
-    lj.qp_global = o_qp[i] == (size_t)-1 ? nullptr : at<double>(ws, o_qp[i]);
     lj.p0 = B.theta ? B.flags + row0 : nullptr;
     lj.warm_used = B.warm_used + i;
     make_feat_job(B.fjobs.data() + (size_t)i * feat_job_bytes(), mj.G, mj.Q, mj.c, p.x, p.d,

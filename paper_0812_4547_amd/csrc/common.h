@@ -176,7 +176,6 @@ struct LhJob {
   double* rnorm;    // nullable, stride 1
   int32_t* iters;   // nullable, stride 1
   int32_t* status;  // nullable, stride 1
-  double* qp_global;  // lh_matrix_words per problem when Q[:,P] is not in LDS
   const uint8_t* p0;  // nullable: proposed passive set (d flags) for a warm start
   int64_t p0_stride;
   int32_t* warm_used;  // nullable, stride 1: 1 if the warm start was kept
@@ -247,8 +246,6 @@ int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int ma
                          hipStream_t s);
 
 size_t lh_lds_bytes(int d);
-size_t lh_global_scratch_bytes(int d, int nprob);
-bool lh_qp_in_lds(int d);
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);
 // every job of a batch has d <= max_d, one problem each
 int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s);

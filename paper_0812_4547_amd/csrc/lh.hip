@@ -1,38 +1,43 @@
 // Lawson-Hanson active-set NNLS (LH74 ch. 23; the exact solver of Algorithm 1,
-// step 5) in the Gram form of Section 3.4, FP64, one wavefront per problem.
+// step 5) in the Gram form of Section 3.4, FP64, one workgroup per problem.
 //
-// The passive-set systems Q[P,P] z = q_P are solved through B = Q[P,P]^{-1},
-// kept up to date by symmetric bordering when a column enters and by a rank-1
-// downdate when one leaves, so every step is a matrix-vector loop whose
-// iterations are independent (no serial triangular substitution).  After
-// downdates the solve z = B q_P is followed by one step of iterative
-// refinement, z += B (q_P - Q z).
+// The linear algebra is a symmetric sweep tableau (Beaton 1964; Goodnight
+// 1979, "A tutorial on the SWEEP operator") over T = [Q q] (Q = G, q the
+// moments of f).  Sweeping the passive set P leaves
+//   T[P,P] = -Q[P,P]^{-1},  T[Z,Z] = Q[Z,Z] - Q[Z,P] Q[P,P]^{-1} Q[P,Z],
+//   T[P,q] = Q[P,P]^{-1} q_P = z,  T[Z,q] = q_Z - Q[Z,P] z = w_Z,
+// so the passive least-squares solution z, the dual w off P and the Schur
+// complements of the candidates (the diagonal of T[Z,Z]) are all read off
+// the tableau.  A column entering P is one sweep, a column leaving P one
+// reverse sweep; each is a single rank-1 pass over T, whose rows are
+// independent.  In exact arithmetic the iterates are those of LH74.
 //
-// Passive columns live in "slots" (0 <= slot < d): B is indexed by slot, a
-// freed slot has a zero row and column in B, and new columns take the lowest
-// free slot.  QP = Q[:, P] is kept by slot as well (QP[col][slot]), so the dual
-// vector w = q - QP x_P, the candidate column g = QP[t][.] and the refinement
-// residual are all "one row per lane times a broadcast vector".  Each lane
-// owns a contiguous row (reads at fixed offsets, odd leading dimension so a
-// fixed column hits distinct banks); the broadcast vector is staged in LDS and
-// read by all lanes at one address.  Out-of-range lanes use a dummy row.
-// B and QP sit in LDS when both fit, otherwise QP lives in a global scratch
-// buffer (L2-resident).  Slot- and column-indexed vectors live in registers,
-// lane l holding entries l and l+64 (d <= 128).  Loop trip counts and the
-// results of wave reductions are scalar, so control flow stays uniform.
+// Layout: a workgroup of four wavefronts solves one problem.  T lives in
+// registers: with d padded to D = 64 or 128, thread t holds the (D/16) x
+// (D/16) block at block row t / 16 and block column t % 16 (padding stays
+// exactly zero).  A sweep stages the pivot row in LDS (two buffers used in
+// turn, so one barrier per sweep suffices) and every thread updates its block
+// from it.  The q column, the diagonal of T, x and the other column-indexed
+// vectors are kept in registers too, replicated in every wavefront (lane l:
+// entries l and l + 64): each wavefront runs the same control flow on the
+// same values.  Q itself stays in LDS for the certificate.  Loop trip counts,
+// the passive and refused sets (64-bit ballot masks) and reduction results
+// are scalar, so control flow stays uniform.
 //
 // Steps (the same readings as the oracle: tolerance tau, lowest index on ties,
 // refusal of dependent or non-positive entering columns, outer cap):
-//   outer:  w = q - Q x; t = argmax_{j not in P, not refused} w_j; stop if
-//           w_t <= tau.  With g = Q[P,t], u = B g, s = Q_tt - g.u: refuse t if
-//           s <= 1e-14 Q_tt (dependent) or if its least-squares coefficient
-//           z_t = (q_t - g.x_P) / s is not positive; otherwise border B with
-//           t and take z = (x_P - u z_t, z_t).
+//   outer:  t = argmax_{j not in P, not refused} w_j; stop if w_t <= tau.
+//           Refuse t if its Schur complement s = T_tt <= 1e-14 Q_tt
+//           (dependent) or if its least-squares coefficient w_t / s is not
+//           positive; otherwise sweep t into P.
 //   inner:  if z > 0 on P, x_P = z; else step to the boundary
 //           (alpha = min x/(x-z) over z <= 0), drop the index that hit zero
-//           and every x_j <= tau (rank-1 downdates of B), z = B q_P refined.
-//   end:    w = q - Q x; KKT certificate (x >= 0, w_j <= tau off P,
-//           |w_j| <= 1e3 tau on P); ||M x - f||^2 = c - q.x - x.w.
+//           and every x_j <= tau (reverse sweeps); z is the new T[P,q].
+//   end:    w = q - Q x from Q itself; KKT certificate (x >= 0, w_j <= tau off
+//           P, |w_j| <= 1e3 tau on P).  A failed certificate restarts the
+//           outer loop from the exact dual (twice at most), since the
+//           tableau's copy of w carries the rounding of every sweep.
+//           ||M x - f||^2 = c - q.x - x.w.
 #include <float.h>
 
 #include "common.h"
@@ -44,7 +49,6 @@ namespace {
 constexpr int kW = 64;
 constexpr double kDependence = 1e-14;
 constexpr int kNone = 0x7fffffff;
-constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 __host__ __device__ inline int lds_ld(int d) { return d | 1; }
 
@@ -59,9 +63,24 @@ __device__ __forceinline__ double uni(double v) {
 // every lane's predicate holds (ballot is an intrinsic known to be uniform)
 __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
 
+// v[k / 64] of lane k % 64 for a uniform index k, as a scalar.  Each entry
+// is read out first and the scalars are selected afterwards: a select of the
+// entries themselves would become a variable index into the register array,
+// which the compiler places in scratch memory.
+__device__ __forceinline__ double readlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 template <int H>
-__device__ __forceinline__ int bcast(const int (&v)[H], int k) {
-  return __builtin_amdgcn_readlane((H == 1 || k < kW) ? v[0] : v[H - 1], k & (kW - 1));
+__device__ __forceinline__ double bcast(const double (&v)[H], int k) {
+  const double a = readlane(v[0], k & (kW - 1));
+  if constexpr (H == 1) {
+    return a;
+  } else {
+    const double b = readlane(v[H - 1], k & (kW - 1));
+    return k < kW ? a : b;
+  }
 }
 
 // ---- wave reductions with DPP row shifts and row broadcasts.  The result
@@ -92,21 +111,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   RNNLS_DPP_STEPS(RNNLS_SUM_STEP)
 #undef RNNLS_SUM_STEP
   return lane63(v);
-}
-
-// two sums at once (their DPP chains interleave)
-__device__ __forceinline__ void wave_sum2(double& a, double& b) {
-#define RNNLS_SUM2_STEP(C, R) \
-  {                           \
-    const double oa = dpp<C, R>(0.0, a); \
-    const double ob = dpp<C, R>(0.0, b); \
-    a += oa;                  \
-    b += ob;                  \
-  }
-  RNNLS_DPP_STEPS(RNNLS_SUM2_STEP)
-#undef RNNLS_SUM2_STEP
-  a = lane63(a);
-  b = lane63(b);
 }
 
 template <bool MAX>
@@ -141,144 +145,80 @@ __device__ __forceinline__ int wave_arg(const double (&v)[H], const bool (&ok)[H
   return kNone;
 }
 
-// Order LDS traffic of the (single) wavefront: its DS operations complete in
-// issue order, so only the compiler must not move them across this point.
-template <bool GLOBAL>
-__device__ __forceinline__ void lh_sync() {
-  if (GLOBAL) {
-    __syncthreads();  // global scratch: wait for the stores as well
-  } else {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// Stage a slot- or column-indexed vector in LDS for broadcast reads.
 template <int H>
-__device__ __forceinline__ void stage(double* vb, const double (&v)[H]) {
+__device__ __forceinline__ bool has(const uint64_t (&m)[H], int h, int lane) {
+  return (m[h] >> lane) & 1ull;
+}
+template <int H>
+__device__ __forceinline__ void set_bit(uint64_t (&m)[H], int k, bool on) {
 #pragma unroll
-  for (int h = 0; h < H; ++h) vb[threadIdx.x + h * kW] = v[h];
-  lh_sync<false>();
+  for (int h = 0; h < H; ++h)
+    if ((k >> 6) == h) m[h] = on ? (m[h] | (1ull << (k & 63))) : (m[h] & ~(1ull << (k & 63)));
+}
+// lowest set index of m and clear it; -1 when m is empty (selects on values
+// only, so that m stays in registers)
+template <int H>
+__device__ __forceinline__ int pop_lowest(uint64_t (&m)[H]) {
+  const bool first = H == 1 || m[0] != 0ull;
+  const uint64_t v = first ? m[0] : m[H - 1];
+  if (!v) return -1;
+  const int k = (first ? 0 : kW) + (int)__builtin_ctzll(v);
+  const uint64_t rest = v & (v - 1ull);
+  if constexpr (H == 1) {
+    m[0] = rest;
+  } else {
+    m[0] = first ? rest : m[0];
+    m[H - 1] = first ? m[H - 1] : rest;
+  }
+  return k;
 }
 
-// u[h] = sum_{k < n} row[h][k] * vb[k]  (two accumulators per row).  Blocks
-// of 16: all loads of a block are issued before its FMAs.
-template <int H, class Ptr>
-__device__ __forceinline__ void mv(const Ptr (&row)[H], const double* vb, int n,
-                                   double (&u)[H]) {
-  double a[H][2];
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// The padded order DP (64 or 128) fixes the workgroup: 256 threads in a 16 x
+// 16 grid, each holding a (DP/16) x (DP/16) block of the tableau.
+__host__ __device__ constexpr int lh_threads(int) { return 256; }
+__host__ __device__ constexpr int lh_waves(int dp) { return lh_threads(dp) / kW; }
+inline int padded_order(int d) { return d <= kW ? kW : 2 * kW; }
+
+// partial sums (one row of 2*kW per wavefront), two pivot-row buffers
+// (2 x 128), Q (d x ld)
+inline size_t lds_words(int d) {
+  return (size_t)lh_waves(padded_order(d)) * 2 * kW + 2 * 128 + (size_t)d * lds_ld(d);
+}
+
+// u[h] += sum_{i0 <= i < i1} M[i][col[h]] x_i (x_i a scalar read from the
+// lane that holds it).  Whole blocks of rows carry no per-row conditions, so
+// all their reads are in flight together.
+template <int H>
+__device__ __forceinline__ void mv_rows(const double* M, int ld, int i0, int i1,
+                                        const double (&x)[H], const int (&col)[H],
+                                        double (&u)[H]) {
+  constexpr int kBlock = 16 / H;
+  int i = i0;
+  for (; i + kBlock <= i1; i += kBlock) {
+    double v[kBlock][H];
 #pragma unroll
-  for (int h = 0; h < H; ++h) a[h][0] = a[h][1] = 0.0;
-  int k = 0;
-  for (; k + 16 <= n; k += 16) {
-    double2 v2[8];
-    double r[H][16];
+    for (int e = 0; e < kBlock; ++e)
 #pragma unroll
-    for (int h = 0; h < H; ++h)
+      for (int h = 0; h < H; ++h) v[e][h] = M[(i + e) * ld + col[h]];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) r[h][i] = row[h][k + i];
+    for (int e = 0; e < kBlock; ++e) {
+      const double xi = bcast(x, i + e);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v2[i] = *reinterpret_cast<const double2*>(vb + k + 2 * i);
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        a[h][0] = fma(r[h][2 * i], v2[i].x, a[h][0]);
-        a[h][1] = fma(r[h][2 * i + 1], v2[i].y, a[h][1]);
-      }
-  }
-  for (; k + 4 <= n; k += 4) {
-    double r[H][4];
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) r[h][i] = row[h][k + i];
-    const double2 v0 = *reinterpret_cast<const double2*>(vb + k);
-    const double2 v1 = *reinterpret_cast<const double2*>(vb + k + 2);
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      a[h][0] = fma(r[h][0], v0.x, a[h][0]);
-      a[h][1] = fma(r[h][1], v0.y, a[h][1]);
-      a[h][0] = fma(r[h][2], v1.x, a[h][0]);
-      a[h][1] = fma(r[h][3], v1.y, a[h][1]);
+      for (int h = 0; h < H; ++h) u[h] = fma(v[e][h], xi, u[h]);
     }
   }
-  for (; k < n; ++k) {
-    const double vk = vb[k];
+  for (; i < i1; ++i) {
+    const double xi = bcast(x, i);
 #pragma unroll
-    for (int h = 0; h < H; ++h) a[h][k & 1] = fma(row[h][k], vk, a[h][k & 1]);
-  }
-#pragma unroll
-  for (int h = 0; h < H; ++h) u[h] = a[h][0] + a[h][1];
-}
-
-// row[h][k] += ya[h] * vb[k] for k < n (lane s updates its own row).  Rows
-// of out-of-range lanes alias one dummy row and are not stored: stores of
-// many lanes to one LDS address serialise.
-template <int H>
-__device__ __forceinline__ void rank1(double* const (&row)[H], const double (&ya)[H],
-                                      const double* vb, int n, const bool (&live)[H]) {
-  int k = 0;
-  for (; k + 16 <= n; k += 16) {
-    double2 v2[8];
-    double r[H][16];
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) r[h][i] = row[h][k + i];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v2[i] = *reinterpret_cast<const double2*>(vb + k + 2 * i);
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-      if (live[h]) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          row[h][k + 2 * i] = fma(ya[h], v2[i].x, r[h][2 * i]);
-          row[h][k + 2 * i + 1] = fma(ya[h], v2[i].y, r[h][2 * i + 1]);
-        }
-      }
-  }
-  for (; k + 4 <= n; k += 4) {
-    double r[H][4];
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) r[h][i] = row[h][k + i];
-    const double2 v0 = *reinterpret_cast<const double2*>(vb + k);
-    const double2 v1 = *reinterpret_cast<const double2*>(vb + k + 2);
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-      if (live[h]) {
-        row[h][k] = fma(ya[h], v0.x, r[h][0]);
-        row[h][k + 1] = fma(ya[h], v0.y, r[h][1]);
-        row[h][k + 2] = fma(ya[h], v1.x, r[h][2]);
-        row[h][k + 3] = fma(ya[h], v1.y, r[h][3]);
-      }
-  }
-  for (; k < n; ++k) {
-    const double vk = vb[k];
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-      if (live[h]) row[h][k] = fma(ya[h], vk, row[h][k]);
+    for (int h = 0; h < H; ++h) u[h] = fma(M[i * ld + col[h]], xi, u[h]);
   }
 }
-
-__host__ __device__ inline size_t lh_matrix_words(int d) { return (size_t)(d + 1) * lds_ld(d); }
-__host__ __device__ inline size_t lh_vector_words(int d) { return 2 * kW + 3 * (size_t)d; }
 
 }  // namespace
 
-static bool qp_in_lds(int d) {
-  return (2 * lh_matrix_words(d) + lh_vector_words(d)) * sizeof(double) <= kMaxLdsBytes;
-}
-
-size_t lh_lds_bytes(int d) {
-  return ((qp_in_lds(d) ? 2 : 1) * lh_matrix_words(d) + lh_vector_words(d)) * sizeof(double);
-}
-
-size_t lh_global_scratch_bytes(int d, int nprob) {
-  return qp_in_lds(d) ? 0 : (size_t)nprob * lh_matrix_words(d) * sizeof(double);
-}
+size_t lh_lds_bytes(int d) { return lds_words(d) * sizeof(double); }
 
 template <bool BATCH>
 __device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jobs) {
@@ -288,39 +228,67 @@ __device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jo
 
 // The problem of workgroup blockIdx.x: job blockIdx.x of a batch table
 // (BATCH), or sub-problem blockIdx.x of the job `one`, whose inputs sit at the
-// job's strides.  Q (= G) is d x d row-major (symmetric).
-template <int H, bool QPG, bool BATCH>
-__global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJob* jobs) {
+// job's strides.  Q (= G) is d x d row-major (symmetric), d <= DP.
+template <int DP, bool BATCH>
+__global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one,
+                                                                     const LhJob* jobs) {
+  constexpr int H = DP / kW;      // column-indexed entries per lane
+  constexpr int GB = 16;          // blocks per row of the tableau
+  constexpr int B = DP / GB;      // the tableau block of a thread is B x B
+  constexpr int kNW = lh_waves(DP);
+  constexpr int kBlock = 16 / H;  // rows of Q whose loads are in flight together
   extern __shared__ __attribute__((aligned(16))) double lh_lds[];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kW - 1);
+  const int wv = uni((int)(threadIdx.x / kW));
+  const int br = threadIdx.x / GB;  // block row: rows br*B .. br*B + B - 1
+  const int bc = threadIdx.x % GB;  // block column
   const LhJob& J = lh_job<BATCH>(one, jobs);
   const int64_t sub = BATCH ? 0 : blockIdx.x;
   const int d = J.d;
-  const int max_iter = J.max_iter;
   const double* Qg = J.G + sub * J.G_stride;
+  const int ld = lds_ld(d);
+  const int rw = (d + kNW - 1) / kNW;
+  const int r0 = min(d, wv * rw);  // this wavefront's rows of Q to load
+  const int r1 = min(d, r0 + rw);
+  bool valid[H];
+  int col[H];  // this lane's columns, clamped into range
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    valid[h] = lane + h * kW < d;
+    col[h] = valid[h] ? lane + h * kW : d - 1;
+  }
+
+  // rows [i0, i0 + kBlock) of Q (below r1), read coalesced
+  auto fetch = [&](int i0, double (&v)[kBlock][H]) {
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e)
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        v[e][h] = (i0 + e < r1 && valid[h]) ? Qg[(int64_t)(i0 + e) * d + lane + h * kW] : 0.0;
+  };
+  // this wavefront's first rows of Q are requested before anything else, so
+  // their latency overlaps the set-up
+  double v0[kBlock][H];
+  fetch(r0, v0);
+
+  const int max_iter = J.max_iter;
   const double* qg = J.q + sub * J.q_stride;
   const double* colabs_p = J.colabs + sub * J.colabs_stride;
   double* x_out = J.x + sub * J.x_stride;
   double* w_out = J.w ? J.w + sub * J.w_stride : nullptr;
-  const int ld = lds_ld(d);
-  const int mw = (int)lh_matrix_words(d);
-  double* vb = lh_lds;  // broadcast staging, 2*kW
-  double* Bs = vb + 2 * kW;
-  double* QP = QPG ? J.qp_global + sub * mw : Bs + mw;
-  double* qs = (QPG ? Bs + mw : QP + mw);
-  double* dq = qs + d;
-  double* xcol = dq + d;
+  double* part = lh_lds;            // partial sums, one row per wavefront
+  double* buf = part + kNW * 2 * kW;  // pivot rows, two buffers of 128
+  double* Qs = buf + 2 * 128;       // Q
 
-  for (int e = lane; e < mw; e += kW) {
-    Bs[e] = 0.0;
-    QP[e] = 0.0;
-  }
+  // column-indexed registers (entry j = lane + 64 h)
+  double qv[H], dq[H];
   double amax = 0.0;
-  for (int j = lane; j < d; j += kW) {
-    qs[j] = qg[j];
-    dq[j] = Qg[(int64_t)j * d + j];
-    xcol[j] = 0.0;
-    amax = fmax(amax, colabs_p[j]);
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int j = lane + h * kW;
+    qv[h] = valid[h] ? qg[j] : 0.0;
+    dq[h] = valid[h] ? Qg[(int64_t)j * d + j] : 0.0;
+    if (valid[h]) amax = fmax(amax, colabs_p[j]);
   }
 #pragma unroll
   for (int off = 1; off < kW; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, kW));
@@ -329,128 +297,129 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
   const double tau =
       uni(J.tol > 0.0 ? J.tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
 
-  // per-lane rows: B by slot, QP by column (dummy row d when out of range)
-  double* brow[H];
-  const double* qrow[H];
-  bool valid[H];
+  // Q into LDS (each wavefront its rows)
+  for (int i0 = r0; i0 < r1; i0 += kBlock) {
+    double v[kBlock][H];
+    if (i0 == r0) {
 #pragma unroll
-  for (int h = 0; h < H; ++h) {
-    const int s = lane + h * kW;
-    valid[h] = s < d;
-    brow[h] = Bs + (valid[h] ? s : d) * ld;
-    qrow[h] = QP + (valid[h] ? s : d) * ld;
+      for (int e = 0; e < kBlock; ++e)
+#pragma unroll
+        for (int h = 0; h < H; ++h) v[e][h] = v0[e][h];
+    } else {
+      fetch(i0, v);
+    }
+#pragma unroll
+    for (int e = 0; e < kBlock; ++e)
+      if (i0 + e < r1) {
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          if (valid[h]) Qs[(i0 + e) * ld + lane + h * kW] = v[e][h];
+      }
   }
   __syncthreads();
 
-  // slot-distributed state
-  int scol[H];     // column held by a slot, -1 if free
-  double xs[H];    // x of the slot's column (0 if free)
-  double z[H];
-  // column-distributed state
-  int cslot[H];    // slot of a column, -1 if not passive
-  int hwm = 0, np = 0, iters = 0;
+  double T[B][B];  // this thread's block of the tableau (indices fixed at compile time)
+  double wz[H];    // the q column of T: z on P, w off P
+  double dg[H];    // the diagonal of T
+  double xs[H];    // x
+  uint64_t pm[H];  // passive set
+  int np = 0, iters = 0, nsweep = 0;
   int status = RNNLS_SOLVE_OK;
 
-  // Border B with column t (u = B g, g = Q[P, t], sinv = 1 / Schur
-  // complement) in the lowest free slot; QP gains column t (qnew = Q[:, t]).
-  auto border = [&](int t, const double (&u)[H], const double (&qnew)[H], double sinv) {
-    const uint64_t free0 = __ballot(scol[0] < 0 && valid[0]);
-    const uint64_t free1 = H == 2 ? __ballot(scol[H - 1] < 0 && valid[H - 1]) : 0ull;
-    const int j = uni(free0 ? __ffsll((unsigned long long)free0) - 1
-                            : kW + __ffsll((unsigned long long)free1) - 1);
-    double ua[H];
+  // T = Q and x = 0, P empty
+  auto start = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < H; ++h) ua[h] = u[h] * sinv;
-    stage(vb, u);  // u is zero on free slots and on slot j
-    rank1(brow, ua, vb, hwm, valid);
-    lh_sync<QPG>();
+    for (int a = 0; a < B; ++a) {
+      const int i = br * B + a;
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const int s = lane + h * kW;
-      if (valid[h] && s != j) {
-        Bs[s * ld + j] = -ua[h];
-        Bs[j * ld + s] = -ua[h];
+      for (int b = 0; b < B; ++b) {
+        const int j = bc * B + b;
+        T[a][b] = (i < d && j < d) ? Qs[i * ld + j] : 0.0;
       }
-      if (valid[h]) QP[s * ld + j] = qnew[h];
     }
-    if (lane == 0) Bs[j * ld + j] = sinv;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      const int s = lane + h * kW;
-      if (s == j) scol[h] = t;
-      if (s == t) cslot[h] = j;
+      wz[h] = qv[h];
+      dg[h] = dq[h];
+      xs[h] = 0.0;
+      pm[h] = 0ull;
     }
-    hwm = uni(j + 1 > hwm ? j + 1 : hwm);
-    ++np;
-    lh_sync<QPG>();
-    return j;
+    np = iters = 0;
+    status = RNNLS_SOLVE_OK;
   };
 
-  // Remove the slots flagged in (m0, m1): B <- B - b b^T / b_jj with
-  // b = B[:, jd], then clear row and column jd of B and column jd of QP.
-  auto drop_slots = [&](uint64_t m0, uint64_t m1) {
-    while (m0 | m1) {
-      const int jd = uni(m0 ? __ffsll((unsigned long long)m0) - 1
-                            : kW + __ffsll((unsigned long long)m1) - 1);
-      if (jd < kW) m0 &= m0 - 1; else m1 &= m1 - 1;
-      const double bjj = uni(Bs[jd * ld + jd]);
-      double bvec[H], ba[H];
+  // Sweep (sigma = +1) or reverse sweep (sigma = -1) on pivot k, with
+  // D = T_kk, r = T[k,.] (= T[.,k]) and rd = T[k,q]:
+  //   T_ij -= r_i r_j / D (i, j != k),  T_ik = T_ki = sigma r_i / D,
+  //   T_kk = -1 / D,  and the q column likewise.
+  // All four cases are one update T_ij <- m_i m_j T_ij + u_i v_j with
+  //   u_i = -r_i / D, v_j = r_j, m_i = 1 off k;  u_k = sigma / D, v_k = -sigma,
+  //   m_k = 0,
+  // whose products at row and column k are exact.  The threads that hold row
+  // k stage it (picked out by 0/1 weights, so no register index depends on k);
+  // after the barrier every thread reads the entries of its rows and columns.
+  auto sweep = [&](int k, double sigma) __attribute__((always_inline)) {
+    double* rowk = buf + (nsweep & 1) * 128;
+    ++nsweep;
+    if (br == k / B) {
+      double e[B];
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int s = lane + h * kW;
-        bvec[h] = (valid[h] && s != jd) ? brow[h][jd] : 0.0;
-        ba[h] = -bvec[h] / bjj;
-      }
-      stage(vb, bvec);
-      rank1(brow, ba, vb, hwm, valid);
-      lh_sync<QPG>();
+      for (int a = 0; a < B; ++a) e[a] = (br * B + a == k) ? 1.0 : 0.0;
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int s = lane + h * kW;
-        if (valid[h]) {
-          Bs[s * ld + jd] = 0.0;
-          Bs[jd * ld + s] = 0.0;
-          QP[s * ld + jd] = 0.0;
+      for (int b = 0; b < B; b += 2) {
+        double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+        for (int a = 0; a < B; ++a) {
+          r0 = fma(e[a], T[a][b], r0);
+          r1 = fma(e[a], T[a][b + 1], r1);
         }
+        *reinterpret_cast<double2*>(rowk + bc * B + b) = make_double2(r0, r1);
       }
-      const int col = uni(bcast(scol, jd));
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (lane + h * kW == jd) {
-          scol[h] = -1;
-          xs[h] = 0.0;
-        }
-        if (lane + h * kW == col) cslot[h] = -1;
-      }
-      --np;
-      lh_sync<QPG>();
     }
-    while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
-    hwm = uni(hwm);
-  };
-
-  // z = B q_P, then one refinement step z += B (q_P - Q[P,P] z)
-  auto solve_z = [&]() {
-    double qp[H], r[H], dz[H];
-    const double* prow[H];
+    const double D = uni(bcast(dg, k));
+    const double rd = uni(bcast(wz, k));
+    const double inv = uni(1.0 / D);
+    __syncthreads();
+    double rc[B], rr[B], rj[H];
+#pragma unroll
+    for (int b = 0; b < B; b += 2) {
+      const double2 u = *reinterpret_cast<const double2*>(rowk + bc * B + b);
+      const double2 v = *reinterpret_cast<const double2*>(rowk + br * B + b);
+      rc[b] = u.x;
+      rc[b + 1] = u.y;
+      rr[b] = v.x;
+      rr[b + 1] = v.y;
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) rj[h] = rowk[lane + h * kW];
+    double u[B], v[B], mr[B], mc[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      const bool rk = br * B + a == k;
+      const bool ck = bc * B + a == k;
+      u[a] = rk ? sigma * inv : -rr[a] * inv;
+      mr[a] = rk ? 0.0 : 1.0;
+      v[a] = ck ? -sigma : rc[a];
+      mc[a] = ck ? 0.0 : 1.0;
+    }
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int b = 0; b < B; ++b) T[a][b] = fma(u[a], v[b], T[a][b] * mr[a] * mc[b]);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      qp[h] = scol[h] >= 0 ? qs[scol[h]] : 0.0;
-      prow[h] = QP + (scol[h] >= 0 ? scol[h] : d) * ld;
+      const int j = lane + h * kW;
+      if (j != k) {
+        const double beta = -rj[h] * inv;
+        wz[h] = fma(beta, rd, wz[h]);
+        dg[h] = fma(beta, rj[h], dg[h]);
+      } else {
+        wz[h] = sigma * rd * inv;
+        dg[h] = -inv;
+      }
     }
-    stage(vb, qp);
-    mv(brow, vb, hwm, z);
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-      if (scol[h] < 0) z[h] = 0.0;
-    stage(vb, z);
-    mv(prow, vb, hwm, r);
-#pragma unroll
-    for (int h = 0; h < H; ++h) r[h] = scol[h] >= 0 ? qp[h] - r[h] : 0.0;
-    stage(vb, r);
-    mv(brow, vb, hwm, dz);
-#pragma unroll
-    for (int h = 0; h < H; ++h) z[h] += dz[h];
+    set_bit(pm, k, sigma > 0.0);
+    np += sigma > 0.0 ? 1 : -1;
   };
 
   // A proposed passive set (warm start) is tried first; its result must pass
@@ -460,284 +429,163 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
   int total_iters = 0;
   bool ok = true;
   double xq = 0.0, xw = 0.0;
+  double wf[H];
+  start();
   for (;;) {
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      scol[h] = -1;
-      xs[h] = 0.0;
-      z[h] = 0.0;
-      cslot[h] = -1;
-    }
-    hwm = np = iters = 0;
-    status = RNNLS_SOLVE_OK;
-
     if (warm) {
-      // ---- warm start: the proposed columns take slots 0..p-1 in
-      // ascending order, QP gains their columns, and B = Q[P0,P0]^{-1} comes
-      // from an in-place Gauss-Jordan sweep over their Gram block (a pivot
-      // whose Schur complement is dependent, <= 1e-14 Q_tt, is removed before
-      // it is used); then nonpositive coefficients are dropped until z > 0
-      bool prop[H];
+      // ---- warm start: sweep the proposed columns in ascending order (a
+      // column whose Schur complement is dependent, <= 1e-14 Q_tt, is
+      // skipped), then reverse-sweep nonpositive coefficients until z > 0
+      uint64_t prop[H];
 #pragma unroll
-      for (int h = 0; h < H; ++h) prop[h] = valid[h] && p0[lane + h * kW] != 0;
-      const uint64_t pm0 = __ballot(prop[0]);
-      const uint64_t pm1 = H == 2 ? __ballot(prop[H - 1]) : 0ull;
-      const int p = uni((int)(__popcll(pm0) + __popcll(pm1)));
-      int* slot_col = reinterpret_cast<int*>(xcol);  // d ints fit in xcol
-      const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (prop[h]) {
-          const int rk = (int)(h == 0 ? __popcll(pm0 & below)
-                                      : __popcll(pm0) + __popcll(pm1 & below));
-          cslot[h] = rk;
-          slot_col[rk] = lane + h * kW;
-        }
+      for (int h = 0; h < H; ++h) prop[h] = __ballot(valid[h] && p0[lane + h * kW] != 0);
+      for (int k = pop_lowest(prop); k >= 0; k = pop_lowest(prop)) {
+        const double s = uni(bcast(dg, k));
+        const double qkk = uni(bcast(dq, k));
+        if (s > kDependence * qkk) sweep(k, 1.0);
       }
-      lh_sync<false>();
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int sl = lane + h * kW;
-        scol[h] = sl < p ? slot_col[sl] : -1;
-      }
-      // QP[col][s] = Q[P0[s]][col]: row P0[s] of Q is contiguous over col
-      for (int s0 = 0; s0 < p; s0 += 4) {
-        double v[4][H];
-        int cs[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          cs[e] = uni(slot_col[s0 + e < p ? s0 + e : s0]);
-#pragma unroll
-          for (int h = 0; h < H; ++h)
-            v[e][h] = valid[h] ? Qg[(int64_t)cs[e] * d + lane + h * kW] : 0.0;
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (s0 + e < p) {
-#pragma unroll
-            for (int h = 0; h < H; ++h)
-              if (valid[h]) QP[(lane + h * kW) * ld + s0 + e] = v[e][h];
-          }
-      }
-      lh_sync<QPG>();
-      // B starts as the Gram block: row s of slot s is QP[P0[s]][0..p)
-#pragma unroll
-      for (int h = 0; h < H; ++h)
-        if (scol[h] >= 0) {
-          const double* src = QP + scol[h] * ld;
-          for (int k = 0; k < p; ++k) brow[h][k] = src[k];
-        }
-      hwm = p;
-      np = p;
-      lh_sync<QPG>();
-      for (int k = 0; k < p; ++k) {
-        const int colk = uni(slot_col[k]);
-        const double piv = uni(Bs[k * ld + k]);
-        const double qkk = uni(dq[colk]);
-        if (!(piv > kDependence * qkk)) {
-          // dependent on the columns before it: remove slot k
-#pragma unroll
-          for (int h = 0; h < H; ++h) {
-            const int sl = lane + h * kW;
-            if (valid[h]) {
-              Bs[sl * ld + k] = 0.0;
-              Bs[k * ld + sl] = 0.0;
-              QP[sl * ld + k] = 0.0;
-            }
-            if (sl == k) scol[h] = -1;
-            if (sl == colk) cslot[h] = -1;
-          }
-          --np;
-          lh_sync<QPG>();
-          continue;
-        }
-        const double pinv = uni(1.0 / piv);
-        // pivot row scaled (its diagonal becomes 1/piv); other rows
-        // M[i][.] -= M[i][k] * row, with M[i][k] reset to 0 first
-        double rk[H], ya[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const int j = lane + h * kW;
-          rk[h] = valid[h] ? (j == k ? pinv : Bs[k * ld + j] * pinv) : 0.0;
-          ya[h] = (valid[h] && j != k) ? -brow[h][k] : 0.0;
-          if (valid[h] && j != k) brow[h][k] = 0.0;
-        }
-        stage(vb, rk);
-        rank1(brow, ya, vb, hwm, valid);
-        lh_sync<false>();
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (valid[h] && lane + h * kW < hwm) Bs[k * ld + lane + h * kW] = rk[h];
-        lh_sync<QPG>();
-      }
-      while (hwm > 0 && bcast(scol, hwm - 1) < 0) --hwm;
-      hwm = uni(hwm);
-      for (int j = lane; j < d; j += kW) xcol[j] = 0.0;
-      lh_sync<false>();
       while (np > 0) {
-        solve_z();
-        bool drop[H];
+        uint64_t dm[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) drop[h] = scol[h] >= 0 && !(z[h] > 0.0);
-        const uint64_t m0 = __ballot(drop[0]);
-        const uint64_t m1 = H == 2 ? __ballot(drop[H - 1]) : 0ull;
-        if (!(m0 | m1)) break;
-        drop_slots(m0, m1);
+        for (int h = 0; h < H; ++h) dm[h] = __ballot(has(pm, h, lane) && !(wz[h] > 0.0));
+        int k = pop_lowest(dm);
+        if (k < 0) break;
+        for (; k >= 0; k = pop_lowest(dm)) sweep(k, -1.0);
       }
 #pragma unroll
-      for (int h = 0; h < H; ++h) xs[h] = scol[h] >= 0 ? z[h] : 0.0;
+      for (int h = 0; h < H; ++h) xs[h] = has(pm, h, lane) ? wz[h] : 0.0;
     }
 
-    for (;;) {
-      // ---- outer step: w = q - QP x_P
-      double w[H];
-      stage(vb, xs);
-      mv(qrow, vb, hwm, w);
-#pragma unroll
-      for (int h = 0; h < H; ++h) w[h] = (valid[h] ? qs[lane + h * kW] : 0.0) - w[h];
-      bool refused[H];
-#pragma unroll
-      for (int h = 0; h < H; ++h) refused[h] = false;
-      int t = -1;
-      double u[H], g[H], qnew[H], zt = 0.0, sval = 0.0, sinv = 0.0;
+    for (int refresh = 0;; ++refresh) {
       for (;;) {
-        bool cand[H];
+        // ---- outer step: the entering column.  With s > 0 and w_t > tau
+        // >= 0 its least-squares coefficient w_t / s is positive, so only the
+        // dependence test can refuse it.
+        uint64_t refused[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) cand[h] = valid[h] && cslot[h] < 0 && !refused[h];
-        double best;
-        const int bidx = uni(wave_arg<true>(w, cand, best));
-        if (bidx == kNone || !(best > tau)) break;
-        // the entering column of Q (read from global memory now, used when
-        // QP gains it, so its latency overlaps the candidate test)
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          qnew[h] = valid[h] ? Qg[(int64_t)bidx * d + lane + h * kW] : 0.0;
-        // candidate: g = Q[P, t] = QP[t][slot], u = B g, Schur complement s,
-        // coefficient z_t
-#pragma unroll
-        for (int h = 0; h < H; ++h) g[h] = valid[h] ? QP[bidx * ld + lane + h * kW] : 0.0;
-        stage(vb, g);
-        const double qtt = uni(dq[bidx]);
-        const double qt = uni(qs[bidx]);
-        mv(brow, vb, hwm, u);
-        double gu = 0.0, gx = 0.0;
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          gu += g[h] * u[h];
-          gx += g[h] * xs[h];
-        }
-        wave_sum2(gu, gx);
-        sval = uni(qtt - gu);
-        sinv = uni(1.0 / sval);
-        zt = uni((qt - gx) * sinv);
-        if (!((sval > kDependence * qtt) && (zt > 0.0))) {
+        for (int h = 0; h < H; ++h) refused[h] = 0ull;
+        int t = -1;
+        for (;;) {
+          bool cand[H];
 #pragma unroll
           for (int h = 0; h < H; ++h)
-            if (lane + h * kW == bidx) refused[h] = true;
-          continue;
-        }
-        t = bidx;
-        break;
-      }
-      if (t < 0) break;
-      if (iters >= max_iter) {
-        status = RNNLS_SOLVE_MAX_ITER;
-        break;
-      }
-      ++iters;
-      // ---- border B with t; z = (x_P - u z_t, z_t)
-#pragma unroll
-      for (int h = 0; h < H; ++h) z[h] = (scol[h] >= 0) ? xs[h] - u[h] * zt : 0.0;
-      const int j = border(t, u, qnew, sinv);
-#pragma unroll
-      for (int h = 0; h < H; ++h)
-        if (lane + h * kW == j) z[h] = zt;
-      // ---- inner loop
-      for (;;) {
-        bool allpos = true;
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (scol[h] >= 0 && !(z[h] > 0.0)) allpos = false;
-        if (wave_all(allpos)) {
-#pragma unroll
-          for (int h = 0; h < H; ++h) xs[h] = z[h];
+            cand[h] = valid[h] && !has(pm, h, lane) && !has(refused, h, lane);
+          double best;
+          const int bidx = uni(wave_arg<true>(wz, cand, best));
+          if (bidx == kNone || !(best > tau)) break;
+          const double s = uni(bcast(dg, bidx));
+          const double qtt = uni(bcast(dq, bidx));
+          if (!(s > kDependence * qtt)) {
+            set_bit(refused, bidx, true);
+            continue;
+          }
+          t = bidx;
           break;
         }
-        double rat[H];
-        bool neg[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          neg[h] = scol[h] >= 0 && !(z[h] > 0.0);
-          const double den = xs[h] - z[h];
-          rat[h] = den > 0.0 ? xs[h] / den : 0.0;
+        if (t < 0) break;
+        if (iters >= max_iter) {
+          status = RNNLS_SOLVE_MAX_ITER;
+          break;
         }
-        double ratio;
-        const int ridx = uni(wave_arg<false>(rat, neg, ratio));
-        // non-finite data can leave no valid ratio: then stay put and drop
-        // every nonpositive coefficient, so each pass removes at least one index
-        const bool stuck = (ridx == kNone);
-        const double alpha = stuck ? 0.0 : ratio;
-        bool drop[H];
+        ++iters;
+        sweep(t, 1.0);
+        // ---- inner loop
+        for (;;) {
+          bool allpos = true;
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const int s = lane + h * kW;
-          drop[h] = false;
-          if (scol[h] >= 0) {
-            const double xn = xs[h] + alpha * (z[h] - xs[h]);
-            drop[h] = (s == ridx) || !(xn > tau) || (stuck && !(z[h] > 0.0));
-            xs[h] = drop[h] ? 0.0 : xn;
+          for (int h = 0; h < H; ++h)
+            if (has(pm, h, lane) && !(wz[h] > 0.0)) allpos = false;
+          if (wave_all(allpos)) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) xs[h] = has(pm, h, lane) ? wz[h] : 0.0;
+            break;
           }
+          double rat[H];
+          bool neg[H];
+#pragma unroll
+          for (int h = 0; h < H; ++h) {
+            neg[h] = has(pm, h, lane) && !(wz[h] > 0.0);
+            const double den = xs[h] - wz[h];
+            rat[h] = den > 0.0 ? xs[h] / den : 0.0;
+          }
+          double ratio;
+          const int ridx = uni(wave_arg<false>(rat, neg, ratio));
+          // non-finite data can leave no valid ratio: then stay put and drop
+          // every nonpositive coefficient, so each pass removes at least one index
+          const bool stuck = (ridx == kNone);
+          const double alpha = stuck ? 0.0 : ratio;
+          uint64_t dm[H];
+#pragma unroll
+          for (int h = 0; h < H; ++h) {
+            const int j = lane + h * kW;
+            bool drop = false;
+            if (has(pm, h, lane)) {
+              const double xn = xs[h] + alpha * (wz[h] - xs[h]);
+              drop = (j == ridx) || !(xn > tau) || (stuck && !(wz[h] > 0.0));
+              xs[h] = drop ? 0.0 : xn;
+            }
+            dm[h] = __ballot(drop);
+          }
+          for (int k = pop_lowest(dm); k >= 0; k = pop_lowest(dm)) sweep(k, -1.0);
+          if (np == 0) break;
         }
-        drop_slots(__ballot(drop[0]), H == 2 ? __ballot(drop[H - 1]) : 0ull);
-        if (np == 0) break;
-        solve_z();
       }
-    }
 
-    // ---- certificate: x by column through LDS, w = q - Q x
-    for (int j = lane; j < d; j += kW) xcol[j] = 0.0;
-    lh_sync<false>();
+      // ---- certificate: w = q - Q x from Q itself, each wavefront taking
+      // its rows of Q, the shares summed in a fixed order
+      double u[H];
 #pragma unroll
-    for (int h = 0; h < H; ++h)
-      if (scol[h] >= 0) xcol[scol[h]] = xs[h];
-    double wf[H];
-    stage(vb, xs);
-    mv(qrow, vb, hwm, wf);
-    ok = true;
-    xq = 0.0;
-    xw = 0.0;
+      for (int h = 0; h < H; ++h) u[h] = 0.0;
+      mv_rows(Qs, ld, r0, r1, xs, col, u);
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const int col = lane + h * kW;
-      if (valid[h]) {
-        const double acc = qs[col] - wf[h];
-        const double xj = xcol[col];
-        if (xj < 0.0) ok = false;
-        if (xj > 0.0) {
-          if (!(fabs(acc) <= 1e3 * tau)) ok = false;
-        } else if (!(acc <= tau)) {
-          ok = false;
-        }
-        xq += xj * qs[col];
-        xw += xj * acc;
-        x_out[col] = xj;
-        if (w_out) w_out[col] = acc;
+      for (int h = 0; h < H; ++h) part[wv * 2 * kW + lane + h * kW] = u[h];
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) acc += part[w * 2 * kW + lane + h * kW];
+        wf[h] = qv[h] - acc;
       }
+      __syncthreads();  // the partial sums are read before they are reused
+      ok = true;
+      xq = 0.0;
+      xw = 0.0;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if (valid[h]) {
+          const double xj = xs[h];
+          if (xj < 0.0) ok = false;
+          if (xj > 0.0) {
+            if (!(fabs(wf[h]) <= 1e3 * tau)) ok = false;
+          } else if (!(wf[h] <= tau)) {
+            ok = false;
+          }
+          xq += xj * qv[h];
+          xw += xj * wf[h];
+        }
+      }
+      ok = wave_all(ok);
+      if (ok || status != RNNLS_SOLVE_OK || refresh >= 2) break;
+      // the tableau's dual has drifted: continue from the exact one
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        if (!has(pm, h, lane)) wz[h] = wf[h];
     }
-    ok = wave_all(ok);
     xq = wave_sum(xq);
     xw = wave_sum(xw);
     total_iters += iters;
     if (!warm || (ok && status == RNNLS_SOLVE_OK)) break;
-    // the warm start failed its certificate: clear B and QP, start cold
-    warm = 0;
-    lh_sync<QPG>();
-    for (int e = lane; e < mw; e += kW) {
-      Bs[e] = 0.0;
-      QP[e] = 0.0;
-    }
-    lh_sync<QPG>();
+    warm = 0;  // the warm start failed its certificate: start cold
+    start();
   }
+  if (wv != 0) return;
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+    if (valid[h]) {
+      x_out[lane + h * kW] = xs[h];
+      if (w_out) w_out[lane + h * kW] = wf[h];
+    }
   if (lane == 0) {
     if (status == RNNLS_SOLVE_OK && !ok) status = RNNLS_SOLVE_KKT_FAIL;
     if (J.pre_status) {
@@ -752,35 +600,31 @@ __global__ __launch_bounds__(kW) void lawson_hanson_kernel(LhJob one, const LhJo
   }
 }
 
-bool lh_qp_in_lds(int d) { return qp_in_lds(d); }
+template <int DP, bool BATCH>
+int launch_lh_t(const LhJob& one, const LhJob* jobs, int nblocks, size_t lds, hipStream_t s) {
+  const void* fn = (const void*)lawson_hanson_kernel<DP, BATCH>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess)
+    return RNNLS_E_HIP;
+  hipLaunchKernelGGL((lawson_hanson_kernel<DP, BATCH>), dim3(nblocks), dim3(lh_threads(DP)), lds,
+                     s, one, jobs);
+  return RNNLS_OK;
+}
 
 template <bool BATCH>
 int launch_lh(const LhJob& one, const LhJob* jobs, int nblocks, int d, hipStream_t s) {
   const size_t lds = lh_lds_bytes(d);
-  const bool qpg = !qp_in_lds(d);
-  const void* fn = d <= kW ? (const void*)lawson_hanson_kernel<1, false, BATCH>
-                   : !qpg  ? (const void*)lawson_hanson_kernel<2, false, BATCH>
-                           : (const void*)lawson_hanson_kernel<2, true, BATCH>;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess)
-    return RNNLS_E_HIP;
+  if (lds > kMaxLdsBytes) return RNNLS_E_UNSUPPORTED;
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_SOLVE, s, &tok);
-  if (d <= kW)
-    hipLaunchKernelGGL((lawson_hanson_kernel<1, false, BATCH>), dim3(nblocks), dim3(kW), lds, s,
-                       one, jobs);
-  else if (!qpg)
-    hipLaunchKernelGGL((lawson_hanson_kernel<2, false, BATCH>), dim3(nblocks), dim3(kW), lds, s,
-                       one, jobs);
-  else
-    hipLaunchKernelGGL((lawson_hanson_kernel<2, true, BATCH>), dim3(nblocks), dim3(kW), lds, s,
-                       one, jobs);
+  const int rc = d <= kW ? launch_lh_t<64, BATCH>(one, jobs, nblocks, lds, s)
+                         : launch_lh_t<128, BATCH>(one, jobs, nblocks, lds, s);
   timer_end(RNNLS_TIMER_SOLVE, s, tok);
+  if (rc) return rc;
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s) {
-  if (!qp_in_lds(j.d) && !j.qp_global) return RNNLS_E_WORKSPACE;
   return launch_lh<false>(j, nullptr, nsub, j.d, s);
 }
 
