@@ -1,10 +1,13 @@
 // Random streams of Algorithm 1 on the device: the +-1 diagonal D (step 4) and
 // the kept rows of S (step 2), from the counter hash defined in rnnls.h.
 //
-// One pass over the padded rows j < n' (32 rows per thread) writes the sign
-// words and a kept-row bit mask and counts kept rows per block; a one-block
-// scan turns the counts into offsets; a last pass writes the kept rows in
-// ascending order.
+// Two launches.  The padded rows j < n' are cut into at most 2048 segments
+// (2048 rows each, more for n' > 2^22).  The first launch (one workgroup per
+// segment, four threads per 32-row word) writes the sign words and a kept-row
+// bit mask and counts the kept rows of its segment; the second (one
+// wavefront per segment) sums the counts of the segments before its own and
+// writes its kept rows in ascending order; the last segment also writes the
+// kept count and the status.
 //   EXACT:     j is kept iff pi^{-1}(j) < r, i.e. j is in {pi(0..r-1)}.  The
 //              inverse runs the rounds backwards: x ^= x >> ceil(m/2) is its
 //              own inverse on m bits, the odd multiplier is inverted mod 2^m.
@@ -15,8 +18,14 @@ namespace rnnls {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = kThreads * 32;
+constexpr int kScanThreads = 256;  // four threads per word: 64 words per pass
+constexpr int kWriteThreads = 64;  // one wavefront per segment
+
+// log2 of the rows of a segment, and the number of segments, for n' = 2^m
+__host__ __device__ inline int seg_log(int m) { return m - 11 > 11 ? m - 11 : 11; }
+__host__ __device__ inline int64_t n_segments(int m) {
+  return m <= 11 ? 1 : (1ll << (m - seg_log(m)));
+}
 
 struct KeepRule {
   int mode;             // RNNLS_SAMPLE_*
@@ -75,113 +84,133 @@ __device__ __forceinline__ StreamJob job_of_block(const StreamJob& one, const St
   return j;
 }
 
-__device__ __forceinline__ int64_t nblocks_of(int m) {
-  return ((1ll << m) + kRowsPerBlock - 1) / kRowsPerBlock;
+// words [w0, w1) of segment `seg`
+__device__ __forceinline__ void segment_words(int m, int64_t seg, int64_t* w0, int64_t* w1) {
+  const int64_t nwords = ((1ll << m) + 31) / 32;
+  const int sl = seg_log(m);
+  *w0 = (seg << sl) >> 5;
+  const int64_t e = ((seg + 1) << sl) >> 5;
+  *w1 = e < nwords ? e : nwords;
 }
 
-__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
-  __shared__ int wave_sums[kThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += t;
-  }
-  if (lane == 63) wave_sums[wave] = incl;
-  __syncthreads();
-  int before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
-    if (w < wave) before += wave_sums[w];
-    all += wave_sums[w];
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - v;
-}
-
-// signs + kept mask + per-block kept counts.  Scratch of a job: kept words
-// [n'/32], block counts [blocks], block offsets [blocks].
+// Signs + kept mask + kept count of one segment.  Scratch of a job: kept
+// words [n'/32], segment counts [segments].
 template <bool BATCH>
-__global__ __launch_bounds__(kThreads) void streams_scan_rows_kernel(StreamJob one,
-                                                                     const StreamJob* jobs,
-                                                                     const int32_t* jmap) {
-  int64_t lb;
-  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &lb);
+__global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJob one,
+                                                                         const StreamJob* jobs,
+                                                                         const int32_t* jmap) {
+  __shared__ int wave_counts[kScanThreads / 64];
+  int64_t seg;
+  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &seg);
   const KeepRule rule = make_rule(J);
   const uint64_t sign_key = stream_key(J.seed, kStreamSign);
   const int64_t n_pad = 1ll << J.m;
   const int64_t nwords = (n_pad + 31) / 32;
   uint32_t* kept_words = J.scratch;
   uint32_t* counts = J.scratch + nwords;
-  const int64_t w = lb * kThreads + threadIdx.x;
-  uint32_t sbits = 0, kbits = 0;
-  if (w < nwords) {
-    const uint64_t base = (uint64_t)w * 32ull;
-#pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      const uint64_t j = base + (uint64_t)k;
-      if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << k;
-    }
-    // sign word w: natural layout (rows 32w..32w+31), or the tile-major
-    // layout of the sketch kernel: w = tile * (T/32) + tid, bit 4k+e holding
-    // row tile*T + k*(T/8) + 4*tid + e
-    uint64_t first = base;
-    int kstride = 4;
-    if (J.sign_log_t > 0) {
-      const int64_t nt = (1ll << J.sign_log_t) >> 5;
-      first = ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt);
-      kstride = (int)((1ll << J.sign_log_t) >> 3);
-    }
-#pragma unroll 4
-    for (int b = 0; b < 32; ++b) {
-      const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
-      if ((int64_t)j < n_pad) sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
-    }
-    J.sign_words[w] = sbits;
-    kept_words[w] = kbits;
-    if (J.sign_export && J.sign_export != J.sign_words) {
-      uint32_t nat = 0;
-      if (J.sign_log_t > 0) {
-#pragma unroll 4
-        for (int k = 0; k < 32; ++k)
-          nat |= (uint32_t)(mix64(sign_key + base + (uint64_t)k) >> 63) << k;
-      } else {
-        nat = sbits;
+  int64_t w0, w1;
+  segment_words(J.m, seg, &w0, &w1);
+  const int part = threadIdx.x & 3;  // this thread's 8 bits of the word
+  // sign word w: natural layout (rows 32w..32w+31), or the tile-major
+  // layout of the sketch kernel: w = tile * (T/32) + tid, bit 4k+e holding
+  // row tile*T + k*(T/8) + 4*tid + e
+  const int64_t nt = J.sign_log_t > 0 ? ((1ll << J.sign_log_t) >> 5) : 1;
+  const int kstride = J.sign_log_t > 0 ? (int)((1ll << J.sign_log_t) >> 3) : 4;
+  const bool export_nat = J.sign_export && J.sign_export != J.sign_words && J.sign_log_t > 0;
+  int count = 0;
+  for (int64_t wb = w0; wb < w1; wb += kScanThreads / 4) {
+    const int64_t w = wb + (threadIdx.x >> 2);
+    uint32_t kbits = 0, sbits = 0, nat = 0;
+    if (w < w1) {
+      const uint64_t base = (uint64_t)w * 32ull;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint64_t j = base + (uint64_t)(8 * part + k);
+        if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << (8 * part + k);
       }
-      J.sign_export[w] = nat;
+      const uint64_t first =
+          J.sign_log_t > 0 ? ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt)
+                           : base;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int b = 8 * part + k;
+        const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
+        if ((int64_t)j < n_pad) sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
+      }
+      if (export_nat) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint64_t j = base + (uint64_t)(8 * part + k);
+          nat |= (uint32_t)(mix64(sign_key + j) >> 63) << (8 * part + k);
+        }
+      }
+    }
+    // the four threads of a word are neighbouring lanes of one wavefront
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+      kbits |= (uint32_t)__shfl_xor((int)kbits, off, 64);
+      sbits |= (uint32_t)__shfl_xor((int)sbits, off, 64);
+      nat |= (uint32_t)__shfl_xor((int)nat, off, 64);
+    }
+    if (part == 0 && w < w1) {
+      J.sign_words[w] = sbits;
+      kept_words[w] = kbits;
+      if (J.sign_export && J.sign_export != J.sign_words) J.sign_export[w] = export_nat ? nat : sbits;
+      count += __popc(kbits);
     }
   }
-  int total;
-  (void)block_exclusive_scan(__popc(kbits), &total);
-  if (threadIdx.x == 0) counts[lb] = (uint32_t)total;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) count += __shfl_xor(count, off, 64);
+  if ((threadIdx.x & 63) == 0) wave_counts[threadIdx.x >> 6] = count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) total += wave_counts[w];
+    counts[seg] = (uint32_t)total;
+  }
 }
 
-// One workgroup per job: block counts -> block offsets, kept count, status.
+// Kept rows of one segment in ascending order, after the kept rows of the
+// segments before it; the last segment writes the count and the status.
 template <bool BATCH>
-__global__ __launch_bounds__(kThreads) void streams_offsets_kernel(StreamJob one,
-                                                                   const StreamJob* jobs) {
-  const StreamJob J = BATCH ? jobs[blockIdx.x] : one;
+__global__ __launch_bounds__(kWriteThreads) void streams_write_rows_kernel(StreamJob one,
+                                                                           const StreamJob* jobs,
+                                                                           const int32_t* jmap) {
+  int64_t seg;
+  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &seg);
+  const int lane = threadIdx.x;
   const int64_t nwords = ((1ll << J.m) + 31) / 32;
-  const int64_t nblocks = nblocks_of(J.m);
+  const uint32_t* kept_words = J.scratch;
   const uint32_t* counts = J.scratch + nwords;
-  uint32_t* offsets = J.scratch + nwords + nblocks;
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < nblocks; base += kThreads) {
-    const int64_t i = base + threadIdx.x;
-    const int v = (i < nblocks) ? (int)counts[i] : 0;
-    int total;
-    const int ex = block_exclusive_scan(v, &total);
-    if (i < nblocks) offsets[i] = carry + (uint32_t)ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += (uint32_t)total;
-    __syncthreads();
+  int before = 0;
+  for (int64_t b = lane; b < seg; b += kWriteThreads) before += (int)counts[b];
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) before += __shfl_xor(before, off, 64);
+  int64_t w0, w1;
+  segment_words(J.m, seg, &w0, &w1);
+  int pos = before;
+  for (int64_t wb = w0; wb < w1; wb += kWriteThreads) {
+    const int64_t w = wb + lane;
+    uint32_t bits = w < w1 ? kept_words[w] : 0u;
+    const int c = __popc(bits);
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    int q = pos + incl - c;
+    while (bits) {
+      const int k = __ffs(bits) - 1;
+      bits &= bits - 1;
+      if (q < J.r_cap) J.rows[q] = (int32_t)(w * 32 + k);
+      ++q;
+    }
+    pos += __shfl(incl, 63, 64);
   }
-  if (threadIdx.x == 0) {
-    const uint32_t k = carry;
+  if (seg == n_segments(J.m) - 1 && lane == 0) {
+    const uint32_t k = (uint32_t)pos;
     const uint32_t cap = (uint32_t)J.r_cap;
     *J.count = (int32_t)(k > cap ? cap : k);
     if (J.status)
@@ -189,45 +218,22 @@ __global__ __launch_bounds__(kThreads) void streams_offsets_kernel(StreamJob one
   }
 }
 
-template <bool BATCH>
-__global__ __launch_bounds__(kThreads) void streams_write_rows_kernel(StreamJob one,
-                                                                      const StreamJob* jobs,
-                                                                      const int32_t* jmap) {
-  int64_t lb;
-  const StreamJob J = job_of_block<BATCH>(one, jobs, jmap, &lb);
-  const int64_t nwords = ((1ll << J.m) + 31) / 32;
-  const int64_t nblocks = nblocks_of(J.m);
-  const uint32_t* kept_words = J.scratch;
-  const uint32_t* offsets = J.scratch + nwords + nblocks;
-  const int64_t w = lb * kThreads + threadIdx.x;
-  uint32_t bits = (w < nwords) ? kept_words[w] : 0u;
-  int total;
-  int pos = (int)offsets[lb] + block_exclusive_scan(__popc(bits), &total);
-  while (bits) {
-    const int k = __ffs(bits) - 1;
-    bits &= bits - 1;
-    if (pos < J.r_cap) J.rows[pos] = (int32_t)(w * 32 + k);
-    ++pos;
-  }
-}
-
 }  // namespace
 
 size_t streams_scratch_words(int64_t n_pad) {
+  int m = 0;
+  while ((1ll << m) < n_pad) ++m;
   const int64_t nwords = (n_pad + 31) / 32;
-  const int64_t nblocks = (n_pad + kRowsPerBlock - 1) / kRowsPerBlock;
-  return (size_t)(nwords + 2 * nblocks + 2);
+  return (size_t)(nwords + n_segments(m) + 2);
 }
 
-int64_t streams_blocks(int m) { return ((1ll << m) + kRowsPerBlock - 1) / kRowsPerBlock; }
+int64_t streams_blocks(int m) { return n_segments(m); }
 
 int launch_streams(const StreamJob& j, hipStream_t s) {
   const unsigned nb = (unsigned)streams_blocks(j.m);
-  hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
+  hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kScanThreads), 0, s, j,
                      (const StreamJob*)nullptr, (const int32_t*)nullptr);
-  hipLaunchKernelGGL(streams_offsets_kernel<false>, dim3(1), dim3(kThreads), 0, s, j,
-                     (const StreamJob*)nullptr);
-  hipLaunchKernelGGL(streams_write_rows_kernel<false>, dim3(nb), dim3(kThreads), 0, s, j,
+  hipLaunchKernelGGL(streams_write_rows_kernel<false>, dim3(nb), dim3(kWriteThreads), 0, s, j,
                      (const StreamJob*)nullptr, (const int32_t*)nullptr);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
@@ -238,11 +244,10 @@ int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs,
   const StreamJob& last = host[njobs - 1];
   const unsigned nb = (unsigned)(last.blk0 + streams_blocks(last.m));
   StreamJob none{};
-  hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
-                     blk_job);
-  hipLaunchKernelGGL(streams_offsets_kernel<true>, dim3(njobs), dim3(kThreads), 0, s, none, dev);
-  hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kThreads), 0, s, none, dev,
-                     blk_job);
+  hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kScanThreads), 0, s, none,
+                     dev, blk_job);
+  hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kWriteThreads), 0, s, none,
+                     dev, blk_job);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
