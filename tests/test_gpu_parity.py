@@ -103,12 +103,23 @@ def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True)
     (1000, 5, 100, 4),                  # small n': direct kernel
     (2, 1, 1, 9),                       # smallest problem
     (20000, 128, 4096, 6),              # widest A
-    ((1 << 18) + 777, 64, 4096, 14),    # b in a second launch of 2^12-row tiles, ragged
+    ((1 << 18) + 777, 64, 4096, 14),    # 2^15 tiles, the ragged tail in a second launch
     (1 << 18, 64, 4096, 15),            # the same without a ragged tile
 ])
 def test_sketch_matches_oracle(n, d, r, seed):
     print(f"sketch n={n} d={d} r={r}", flush=True)
     _sketch_case(n, d, r, seed, data_seed=seed + 100)
+
+
+@pytest.mark.parametrize("log_tile,wgs", [(15, 1), (14, 2), (13, 4)])
+def test_sketch_with_tuned_tiles(log_tile, wgs):
+    """Tuned tile sizes and workgroups per CU (the default is 2^15 rows, one
+    workgroup per CU): same outputs."""
+    rnnls.set_tuning(log_tile, wgs)
+    try:
+        _sketch_case((1 << 18) + 777, 64, 4096, 21, data_seed=5)
+    finally:
+        rnnls.set_tuning(0, 0)
 
 
 def test_sketch_unaligned_leading_dimension():
