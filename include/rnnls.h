@@ -159,9 +159,10 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed,
  *  iters       output int32[1]: outer iterations; may be NULL
  *  status      output int32[1]: RNNLS_SOLVE_*; may be NULL
  * The solve runs in FP64: the Gram matrix M^T M and M^T f are accumulated in
- * FP64 from the FP32 inputs (products are exact); the passive-set systems are
- * solved through an inverse of Q[P,P] updated as columns enter and leave,
- * with a step of iterative refinement after every removal.
+ * FP64 from the FP32 inputs (products are exact); the passive-set systems go
+ * through a symmetric sweep tableau of [Q q] (one sweep when a column enters,
+ * one reverse sweep when it leaves), and the returned w and the KKT status
+ * are computed from Q itself.
  */
 int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm,
                      const float* f, const int32_t* m_dev,
