@@ -208,8 +208,7 @@ MomentJob moment_job(const MomentsPlan& mp, const float* M, int64_t ldm, const f
   j.ldf = ldf;
   j.m_dev = m_dev;
   j.part = scratch;
-  j.part_abs = scratch + align256((size_t)mp.chunks * mp.pairs * 1024 * sizeof(double)) /
-                             sizeof(double);
+  j.part_abs = moments_abs_scratch(mp, scratch);
   j.G = G;
   j.Q = Q;
   j.ldq = ldq;

@@ -79,14 +79,13 @@ struct rnnls_batch {
   void* dev_tables = nullptr;
   std::vector<StreamJob> sjobs;
   StreamJob* sdev = nullptr;
-  std::vector<int32_t> blk_map, chunk_map, entblk_map;  // block -> job
+  std::vector<int32_t> blk_map, chunk_map;  // block -> job
   int32_t* blk_map_dev = nullptr;
   int32_t* chunk_map_dev = nullptr;
-  int32_t* entblk_map_dev = nullptr;
   std::vector<Group> groups;
   std::vector<MomentJob> mjobs;
   MomentJob* mdev = nullptr;
-  int64_t m_chunks = 0, m_entries = 0;
+  int64_t m_chunks = 0;
   int m_max_pairs = 0;
   std::vector<LhJob> ljobs[2];  // d <= 64, d > 64
   LhJob* ldev[2] = {nullptr, nullptr};
@@ -215,7 +214,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
     // chunks of 256 rows: short workgroups, few partials per entry
-    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, (int)std::max(1, (rcap[i] + 255) / 256));
+    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, 1);  // one chunk: no partials
     o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
     o_cnt[i] = put(off, sizeof(int32_t));
     o_st[i] = put(off, sizeof(int32_t));
@@ -244,10 +243,9 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   B.fjobs.assign((size_t)np * feat_job_bytes(), 0);
 
   // fill pointers
-  int64_t blk0 = 0, chunk0 = 0, ent0 = 0, row0 = 0;
+  int64_t blk0 = 0, chunk0 = 0, row0 = 0;
   B.blk_map.clear();
   B.chunk_map.clear();
-  B.entblk_map.clear();
   int max_pairs = 0;
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
@@ -282,19 +280,13 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     mj.nb = mp[i].nb;
     mj.pairs = mp[i].pairs;
     mj.chunk0 = chunk0;
-    mj.ent0 = ent0;
+    mj.ent0 = 0;
     chunk0 += mp[i].chunks;
     B.chunk_map.insert(B.chunk_map.end(), (size_t)mp[i].chunks, i);
-    {  // entries padded to whole blocks of 256: one job per reduce block
-      const int64_t ent = ((int64_t)mp[i].pairs * 1024 + p.d + 255) / 256;
-      ent0 += ent * 256;
-      B.entblk_map.insert(B.entblk_map.end(), (size_t)ent, i);
-    }
     max_pairs = std::max(max_pairs, mp[i].pairs);
     double* scr = at<double>(ws, o_mom[i]);
     mj.part = scr;
-    mj.part_abs = scr + align256((size_t)mp[i].chunks * mp[i].pairs * 1024 * sizeof(double)) /
-                            sizeof(double);
+    mj.part_abs = moments_abs_scratch(mp[i], scr);
     mj.G = at<double>(ws, o_G[i]);
     mj.Q = at<double>(ws, o_q[i]);
     mj.ldq = p.d;
@@ -326,7 +318,6 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     B.l_max_d[h] = std::max(B.l_max_d[h], p.d);
   }
   B.m_chunks = chunk0;
-  B.m_entries = ent0;
   B.m_max_pairs = max_pairs;
   for (Group& G : B.groups) {
     G.col_map.clear();
@@ -390,8 +381,6 @@ int plan(rnnls_batch& B, const Candidate& c) {
   bytes += map_bytes(B.blk_map);
   const size_t o_cm = bytes;
   bytes += map_bytes(B.chunk_map);
-  const size_t o_em = bytes;
-  bytes += map_bytes(B.entblk_map);
   std::vector<size_t> o_gm;
   for (Group& G : B.groups) {
     o_gm.push_back(bytes);
@@ -413,7 +402,6 @@ int plan(rnnls_batch& B, const Candidate& c) {
   copy(o_f, B.fjobs.data(), B.fjobs.size());
   copy(o_bm, B.blk_map.data(), sizeof(int32_t) * B.blk_map.size());
   copy(o_cm, B.chunk_map.data(), sizeof(int32_t) * B.chunk_map.size());
-  copy(o_em, B.entblk_map.data(), sizeof(int32_t) * B.entblk_map.size());
   for (size_t g = 0; g < B.groups.size(); ++g)
     copy(o_gm[g], B.groups[g].col_map.data(), sizeof(int32_t) * B.groups[g].col_map.size());
   if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -427,7 +415,6 @@ int plan(rnnls_batch& B, const Candidate& c) {
   B.fdev = base + o_f;
   B.blk_map_dev = reinterpret_cast<int32_t*>(base + o_bm);
   B.chunk_map_dev = reinterpret_cast<int32_t*>(base + o_cm);
-  B.entblk_map_dev = reinterpret_cast<int32_t*>(base + o_em);
   for (size_t g = 0; g < B.groups.size(); ++g)
     B.groups[g].col_map_dev = reinterpret_cast<int32_t*>(base + o_gm[g]);
   B.tune = c;
@@ -447,8 +434,7 @@ int run_all(rnnls_batch& B, hipStream_t s) {
   if (rc) return rc;
   rc = run_sketch(B, s);
   if (rc) return rc;
-  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.m_entries,
-                            B.chunk_map_dev, B.entblk_map_dev, s);
+  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.chunk_map_dev, s);
   if (rc) return rc;
   if (B.theta) {  // learned proposal -> warm-start flags
     rc = launch_features_batch(B.fdev, B.count, B.X, s);

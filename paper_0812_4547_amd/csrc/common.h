@@ -140,7 +140,7 @@ struct MomentJob {
   int32_t chunks, nbA, nb, pairs;
   int64_t chunk0;  // first chunk in a batched partial launch
   int64_t ent0;    // first entry in a batched reduce launch
-  double* part;    // [chunks][pairs][32][32]
+  double* part;    // [chunks][pairs][16][16] (chunks > 1)
   double* part_abs;  // [chunks][d]
   double* G;
   double* Q;
@@ -239,11 +239,12 @@ struct MomentsPlan {
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);
 size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
-// chunk_job / entblk_job: job of every partial chunk / of every block of 256
-// reduce entries (a job's entries are padded to whole blocks)
+// one chunk per job (max_chunks = 1 plans); chunk_job: job of every block
+// column of the launch
 int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         int64_t entries, const int32_t* chunk_job, const int32_t* entblk_job,
-                         hipStream_t s);
+                         const int32_t* chunk_job, hipStream_t s);
+// start of the column 1-norm partials inside a moments scratch of plan p
+double* moments_abs_scratch(const MomentsPlan& p, double* scratch);
 
 size_t lh_lds_bytes(int d);
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);

@@ -5,30 +5,36 @@
 //
 // [M | F] is one m x (d+k) matrix (k = 1 for a single right-hand side f, k
 // up to hundreds for many right-hand sides sharing M).  Its Gram matrix is
-// cut into 32 x 32 blocks; only the blocks that hold M^T M, M^T F and the
+// cut into 16 x 16 blocks; only the blocks that hold M^T M, M^T F and the
 // diagonal of F^T F are formed: block rows that contain columns of M (all
-// block columns to their right) plus the diagonal blocks of F.  A workgroup
-// of 256 threads (2 x 2 register tile each) computes one such block over one
-// chunk of rows staged in LDS 64 at a time, so even a 4096-row sketch spreads
-// over hundreds of workgroups.  The per-chunk partials are then summed in a
-// fixed order (one thread per entry: deterministic).
+// block columns to their right) plus the diagonal blocks of F.  One
+// workgroup forms one block over one chunk of rows on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: 16 x 16 outputs, 4 rows per instruction).  Lane l
+// supplies A[i = l % 16][k = l / 16] and B[k][j = l % 16]; since the rows of a
+// Gram sum may be taken in any order, lane l loads rows g + 4 (l / 16) .. + 3
+// of its column for a group of 16 rows g and feeds them to four consecutive
+// instructions, and D[4 v + l / 16][l % 16] comes back in accumulator v (the
+// layouts were measured on the device).  The wavefronts of the workgroup
+// take the 16-row groups in turn; their tiles are added in LDS in a fixed
+// order.  With one chunk (every sketch) the workgroup writes G, Q, c and the
+// column 1-norms itself; long inputs (a plain solve on all n rows) are cut
+// into chunks whose partial blocks a second kernel adds in a fixed order
+// (one thread per output entry: deterministic).
 //
 // One problem travels by value in the kernel arguments; a batch of problems
 // (different m, d) reads its descriptors from a device table.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rnnls {
 
 namespace {
 
-constexpr int kBlk = 32;
-constexpr int kRows = 64;
+constexpr int kBlk = 16;
+constexpr int kRowsPerChunk = 4096;
 
-__device__ __forceinline__ float col_elem(const MomentJob& J, int c, int64_t row) {
-  if (c < J.d) return J.M[(int64_t)c * J.ldm + row];
-  if (c < J.d + J.k) return J.F[(int64_t)(c - J.d) * J.ldf + row];
-  return 0.0f;
-}
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // block pair p -> (bi, bj): block rows of M first, then diagonal blocks of F
 __host__ __device__ __forceinline__ void pair_blocks(int p, int nbA, int nb, int& bi, int& bj) {
@@ -60,12 +66,28 @@ __device__ __forceinline__ MomentJob mjob(const MomentJob& one, const MomentJob*
   }
 }
 
-// partial Gram of one row chunk for one block pair (bi <= bj)
-template <bool BATCH>
-__global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const MomentJob* jobs,
-                                                           const int32_t* jmap) {
-  __shared__ double Xi[kRows][kBlk + 1];
-  __shared__ double Xj[kRows][kBlk + 1];
+__device__ __forceinline__ const float* col_ptr(const MomentJob& J, int c) {
+  if (c < J.d) return J.M + (int64_t)c * J.ldm;
+  if (c < J.d + J.k) return J.F + (int64_t)(c - J.d) * J.ldf;
+  return nullptr;
+}
+
+// rows rr .. rr+3 of a column (zero past `hi` or for a missing column)
+__device__ __forceinline__ float4 load_rows4(const float* col, int64_t rr, int64_t hi, bool vec) {
+  if (!col || rr >= hi) return make_float4(0.f, 0.f, 0.f, 0.f);
+  if (vec && rr + 4 <= hi) return *reinterpret_cast<const float4*>(col + rr);
+  float t[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) t[e] = rr + e < hi ? col[rr + e] : 0.0f;
+  return make_float4(t[0], t[1], t[2], t[3]);
+}
+
+// One block pair (bi <= bj) over one chunk of rows, NW wavefronts.
+template <bool BATCH, int NW>
+__global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const MomentJob* jobs,
+                                                            const int32_t* jmap) {
+  __shared__ double red[NW][4][64];
+  __shared__ double red_abs[NW][16];
   int64_t chunk64;
   const MomentJob J =
       mjob<BATCH>(one, jobs, jmap, blockIdx.x, blockIdx.x, &MomentJob::chunk0, chunk64);
@@ -74,50 +96,92 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(MomentJob one, const 
   const int chunk = (int)chunk64;
   int bi, bj;
   pair_blocks(p, J.nbA, J.nb, bi, bj);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
   const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
   const int64_t r0 = (J.m * chunk) / J.chunks;
   const int64_t r1 = (J.m * (chunk + 1)) / J.chunks;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[2][2] = {};
-  double abs_acc = 0.0;
-  for (int64_t base = r0; base < r1; base += kRows) {
-    for (int e = threadIdx.x; e < kRows * kBlk; e += 256) {
-      const int rr = e % kRows, cc = e / kRows;  // rows fastest: coalesced
-      const int64_t row = base + rr;
-      const bool ok = row < r1 && row < m_eff;
-      Xi[rr][cc] = ok ? (double)col_elem(J, bi * kBlk + cc, row) : 0.0;
-      Xj[rr][cc] = ok ? (double)col_elem(J, bj * kBlk + cc, row) : 0.0;
+  const int64_t hi = r1 < m_eff ? r1 : m_eff;
+  const int ci = bi * kBlk + (lane & 15);
+  const int cj = bj * kBlk + (lane & 15);
+  const float* pi = col_ptr(J, ci);
+  const float* pj = col_ptr(J, cj);
+  const bool diag = bi == bj;
+  const int kq = lane >> 4;
+  // 16-byte loads when every column starts 16-byte aligned
+  const bool vec = ((uintptr_t)J.M % 16 == 0) && (J.ldm % 4 == 0) &&
+                   (J.k == 0 || (((uintptr_t)J.F % 16 == 0) && (J.ldf % 4 == 0)));
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double aabs = 0.0;
+  // kU groups of 16 rows per round: all their loads are in flight before the
+  // round's 4 kU matrix-core instructions
+  constexpr int kU = 8;
+  for (int64_t g0 = r0 + 16 * wv; g0 < hi; g0 += 16 * NW * kU) {
+    float4 xa[kU], xb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t rr = g0 + 16 * NW * u + 4 * kq;
+      xa[u] = load_rows4(pi, rr, hi, vec);
+      xb[u] = diag ? xa[u] : load_rows4(pj, rr, hi, vec);
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < kRows; ++rr) {
-      const double a0 = Xi[rr][tx * 2], a1 = Xi[rr][tx * 2 + 1];
-      const double b0 = Xj[rr][ty * 2], b1 = Xj[rr][ty * 2 + 1];
-      acc[0][0] = fma(a0, b0, acc[0][0]);
-      acc[0][1] = fma(a0, b1, acc[0][1]);
-      acc[1][0] = fma(a1, b0, acc[1][0]);
-      acc[1][1] = fma(a1, b1, acc[1][1]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float a4[4] = {xa[u].x, xa[u].y, xa[u].z, xa[u].w};
+      const float b4[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4[e], (double)b4[e], acc, 0, 0, 0);
+        aabs += fabs((double)a4[e]);
+      }
     }
-    if (bi == bj && bi < J.nbA && threadIdx.x < kBlk) {
-      for (int rr = 0; rr < kRows; ++rr) abs_acc += fabs(Xi[rr][threadIdx.x]);
-    }
-    __syncthreads();
   }
-  double* out = J.part + ((int64_t)chunk * J.pairs + p) * (kBlk * kBlk);
+  // column 1-norms: the four row groups of a column, then the wavefronts
+  aabs += __shfl_xor(aabs, 16, 64);
+  aabs += __shfl_xor(aabs, 32, 64);
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int v = 0; v < 4; ++v) red[wv][v][lane] = acc[v];
+  if (lane < 16) red_abs[wv][lane] = aabs;
+  __syncthreads();
+  if (wv != 0) return;
+  const bool abs_out = diag && bi < J.nbA && lane < 16 && ci < J.d;
+  double sabs = 0.0;
+  if (abs_out) {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) out[(tx * 2 + u) * kBlk + ty * 2 + v] = acc[u][v];
-  if (bi == bj && bi < J.nbA && threadIdx.x < kBlk) {
-    const int c = bi * kBlk + threadIdx.x;
-    if (c < J.d) J.part_abs[(int64_t)chunk * J.d + c] = abs_acc;
+    for (int w = 0; w < NW; ++w) sabs += red_abs[w][lane];
+  }
+  const int D1 = J.d + J.k;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double val = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) val += red[w][v][lane];
+    const int a = 4 * v + kq;  // row of the block
+    const int i = bi * kBlk + a;
+    const int j = cj;
+    if (J.chunks > 1) {
+      J.part[((int64_t)chunk * J.pairs + p) * (kBlk * kBlk) + a * kBlk + (lane & 15)] = val;
+      continue;
+    }
+    if (i > j || j >= D1) continue;
+    if (j < J.d) {
+      J.G[(int64_t)i * J.d + j] = val;
+      J.G[(int64_t)j * J.d + i] = val;
+    } else if (i < J.d) {
+      J.Q[(int64_t)(j - J.d) * J.ldq + i] = val;
+    } else if (i == j) {
+      J.c[i - J.d] = val;
+    }
+  }
+  if (abs_out) {
+    if (J.chunks > 1) J.part_abs[(int64_t)chunk * J.d + ci] = sabs;
+    else J.colabs[ci] = sabs;
   }
 }
 
 // One thread per output entry, summing the chunks in order (deterministic;
 // consecutive threads read consecutive entries of each chunk).  Entry
-// e < pairs*1024 is element (e/32 % 32, e % 32) of block pair e/1024; the
-// next d are column 1-norms.
+// e < pairs*256 is element (e/16 % 16, e % 16) of block pair e/256; the next
+// d are column 1-norms.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const MomentJob* jobs,
                                                           const int32_t* jmap) {
@@ -167,16 +231,26 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   p.nbA = (d + kBlk - 1) / kBlk;
   p.nb = (d + k + kBlk - 1) / kBlk;
   p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
-  const int64_t want = (m + kRows - 1) / kRows;
-  int64_t cap = 2 * (int64_t)cus;
+  // at most kRowsPerChunk rows per chunk, and enough chunks (of at least 512
+  // rows) that the blocks fill about two workgroups per CU
+  int64_t want = (m + kRowsPerChunk - 1) / kRowsPerChunk;
+  const int64_t fill = std::min((m + 511) / 512, (2 * (int64_t)cus + p.pairs - 1) / p.pairs);
+  want = std::max(want, fill);
+  int64_t cap = 4 * (int64_t)cus;
   if (max_chunks > 0 && max_chunks < cap) cap = max_chunks;
   p.chunks = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
   return p;
 }
 
 size_t moments_scratch_bytes(const MomentsPlan& p) {
+  if (p.chunks <= 1) return 0;
   return align256((size_t)p.chunks * p.pairs * kBlk * kBlk * sizeof(double)) +
          align256((size_t)p.chunks * p.d * sizeof(double));
+}
+
+double* moments_abs_scratch(const MomentsPlan& p, double* scratch) {
+  return scratch + align256((size_t)p.chunks * p.pairs * kBlk * kBlk * sizeof(double)) /
+                       sizeof(double);
 }
 
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
@@ -190,26 +264,31 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   j.chunk0 = j.ent0 = 0;
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
-  hipLaunchKernelGGL(gram_partial_kernel<false>, dim3(p.chunks, p.pairs), dim3(256), 0, s, j,
-                     (const MomentJob*)nullptr, (const int32_t*)nullptr);
-  const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
-  hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s,
-                     j, (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  const dim3 grid(p.chunks, p.pairs);
+  if (p.m / p.chunks > 2048)  // long chunks: more wavefronts share each one's rows
+    hipLaunchKernelGGL((gram_mfma_kernel<false, 16>), grid, dim3(16 * 64), 0, s, j,
+                       (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL((gram_mfma_kernel<false, 4>), grid, dim3(4 * 64), 0, s, j,
+                       (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  if (p.chunks > 1) {
+    const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
+    hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)), dim3(256),
+                       0, s, j, (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  }
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
+// Batches: one chunk per problem (its rows are a sketch), so no reduce.
 int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         int64_t entries, const int32_t* chunk_job, const int32_t* entblk_job,
-                         hipStream_t s) {
+                         const int32_t* chunk_job, hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   MomentJob none{};
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
-  hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)chunks, (unsigned)max_pairs),
-                     dim3(256), 0, s, none, dev, chunk_job);
-  hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0,
-                     s, none, dev, entblk_job);
+  hipLaunchKernelGGL((gram_mfma_kernel<true, 4>), dim3((unsigned)chunks, (unsigned)max_pairs),
+                     dim3(4 * 64), 0, s, none, dev, chunk_job);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }

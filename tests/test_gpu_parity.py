@@ -215,6 +215,7 @@ def _solve_case(m, d, seed, planted_zeros=None):
     (50, 1, 1, None), (200, 5, 2, 2), (300, 16, 3, 8), (600, 40, 4, 15),
     (1000, 64, 5, 20), (1000, 66, 5, 20), (1000, 70, 5, 20), (2000, 96, 6, 30),
     (3000, 128, 7, 40), (130, 128, 8, 60),
+    (4097, 33, 9, 10), (20000, 80, 10, 25),   # more than one chunk of rows in the moments
 ])
 def test_nnls_solve_matches_oracle(m, d, seed, zeros):
     print(f"solve m={m} d={d}", flush=True)
