@@ -81,6 +81,7 @@ __global__ __launch_bounds__(64) void features_kernel(const FeatJob* jobs, FeatJ
                                                       float* __restrict__ X) {
   __shared__ double cosv[RNNLS_MAX_D];
   __shared__ double diag[RNNLS_MAX_D];
+  __shared__ double isd[RNNLS_MAX_D];
   const FeatJob J = jobs ? jobs[blockIdx.x] : one;
   const int d = J.d, lane = threadIdx.x;
   const double c = *J.c;
@@ -99,14 +100,17 @@ __global__ __launch_bounds__(64) void features_kernel(const FeatJob* jobs, FeatJ
   double qv = 0.0;
   for (int j = lane; j < d; j += 64) qv += (J.q[j] - qmean) * (J.q[j] - qmean);
   const double qstd = sqrt(wsum(qv) / d);
+  // 1/sqrt of the diagonal once per column (0 for a zero column)
+  for (int j = lane; j < d; j += 64) isd[j] = diag[j] > 0.0 ? 1.0 / sqrt(diag[j]) : 0.0;
   __syncthreads();
   for (int j = lane; j < d; j += 64) {
-    const double gjj = diag[j], qj = J.q[j];
+    const double gjj = diag[j], qj = J.q[j], isdj = isd[j];
     double csum = 0.0, cmax = -1.0, cw = 0.0;
+#pragma unroll 8
     for (int k = 0; k < d; ++k) {
       if (k == j) continue;
-      const double gkk = diag[k];
-      const double ck = (gjj > 0.0 && gkk > 0.0) ? J.G[(int64_t)j * d + k] / sqrt(gjj * gkk) : 0.0;
+      // G is symmetric: row k holds G[k][j] for consecutive j (coalesced)
+      const double ck = J.G[(int64_t)k * d + j] * isdj * isd[k];
       csum += ck;
       cmax = fmax(cmax, ck);
       cw += ck * cosv[k];
@@ -353,6 +357,103 @@ __global__ void mlp_adam_kernel(float* __restrict__ theta, uint16_t* __restrict_
   if (b >= 0) wb[b] = f32_to_bf16(th);
 }
 
+// ------------------------------------------------------------ inference
+// Forward pass only, for proposals: persistent workgroups stage the BF16
+// weights once (as FP32, W2 transposed to [input][unit]), then walk blocks of
+// 64 rows.  Thread t holds rows 4 (t / 16) .. + 3 and units 8 (t % 16) .. + 7
+// of a block: in the 128 x 128 layer every input k costs three 16-byte LDS
+// reads (4 activations, 8 weights) for 32 FMAs.  The output layer's dot
+// product is summed over the 16 threads of a row group by lane shuffles.
+struct InferShared {
+  float w2t[kH][kH];
+  float w1[kH][kF];
+  float b1[kH], b2[kH], w3[kH];
+  float x[kRows][kF];
+  float h1t[kH][kRows];
+};
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t rows, const float* __restrict__ X,
+                                                        const float* __restrict__ theta,
+                                                        const uint16_t* __restrict__ wb,
+                                                        float* __restrict__ prob,
+                                                        uint8_t* __restrict__ flags,
+                                                        float threshold) {
+  extern __shared__ __attribute__((aligned(16))) char infer_smem[];
+  InferShared& S = *reinterpret_cast<InferShared*>(infer_smem);
+  const int t = threadIdx.x;
+  const int rg = t >> 4;
+  const int ug = t & 15;
+  // consecutive threads fill consecutive units of one input (no LDS bank conflicts)
+  for (int e = t; e < kH * kH; e += 256) S.w2t[e / kH][e % kH] = bf16_to_f32(wb[bW2 + (e % kH) * kH + e / kH]);
+  for (int e = t; e < kH * kF; e += 256) S.w1[e / kF][e % kF] = bf16_to_f32(wb[bW1 + e]);
+  if (t < kH) {
+    S.b1[t] = theta[ob1 + t];
+    S.b2[t] = theta[ob2 + t];
+    S.w3[t] = bf16_to_f32(wb[bw3 + t]);
+  }
+  const float b3 = theta[ob3];
+  __syncthreads();
+  for (int64_t blk = blockIdx.x; blk * kRows < rows; blk += gridDim.x) {
+    const int64_t row0 = blk * kRows;
+    for (int e = t; e < kRows * kF; e += 256) {
+      const int64_t rr = row0 + e / kF;
+      S.x[e / kF][e % kF] = rr < rows ? X[rr * kF + e % kF] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int u = 8 * ug + b;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = 4 * rg + a;
+        float h = S.b1[u];
+#pragma unroll
+        for (int i = 0; i < kF; ++i) h = fmaf(S.w1[u][i], S.x[r][i], h);
+        S.h1t[u][r] = fmaxf(h, 0.0f);
+      }
+    }
+    __syncthreads();
+    float acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[a][b] = S.b2[8 * ug + b];
+#pragma unroll 4
+    for (int k = 0; k < kH; ++k) {
+      const float4 hv = *reinterpret_cast<const float4*>(&S.h1t[k][4 * rg]);
+      const float4 wa = *reinterpret_cast<const float4*>(&S.w2t[k][8 * ug]);
+      const float4 wc = *reinterpret_cast<const float4*>(&S.w2t[k][8 * ug + 4]);
+      const float h4[4] = {hv.x, hv.y, hv.z, hv.w};
+      const float w8[8] = {wa.x, wa.y, wa.z, wa.w, wc.x, wc.y, wc.z, wc.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(w8[b], h4[a], acc[a][b]);
+    }
+    float z[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      z[a] = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) z[a] = fmaf(S.w3[8 * ug + b], fmaxf(acc[a][b], 0.0f), z[a]);
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) z[a] += __shfl_xor(z[a], off, 64);
+    }
+    if (ug == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t row = row0 + 4 * rg + a;
+        if (row < rows) {
+          const float p = 1.0f / (1.0f + expf(-(z[a] + b3)));
+          if (prob) prob[row] = p;
+          if (flags) flags[row] = p > threshold ? 1 : 0;
+        }
+      }
+    }
+    __syncthreads();  // x and h1t are rewritten by the next block
+  }
+}
+
 __global__ void mlp_sync_kernel(const float* __restrict__ theta, uint16_t* __restrict__ wb) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kParams) return;
@@ -368,8 +469,9 @@ int mlp_set_lds() {
   const int bytes = (int)mlp_lds();
   if (hipFuncSetAttribute((const void*)mlp_kernel<true>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
-      hipFuncSetAttribute((const void*)mlp_kernel<false>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+      hipFuncSetAttribute((const void*)mlp_infer_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sizeof(InferShared)) != hipSuccess)
     return RNNLS_E_HIP;
   done = 1;
   return RNNLS_OK;
@@ -411,10 +513,10 @@ int launch_mlp_forward(int64_t rows, const float* X, const float* theta, const u
   if (rows < 1) return RNNLS_OK;
   int rc = mlp_set_lds();
   if (rc) return rc;
-  const unsigned nwg = (unsigned)((rows + kRows - 1) / kRows);
-  hipLaunchKernelGGL(mlp_kernel<false>, dim3(nwg), dim3(kT), mlp_lds(), s, rows, X,
-                     (const uint8_t*)nullptr, theta, wb, prob, flags, threshold,
-                     (float*)nullptr, (float*)nullptr);
+  const int64_t blocks = (rows + kRows - 1) / kRows;
+  const unsigned nwg = (unsigned)(blocks < 256 ? blocks : 256);
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(nwg), dim3(256), sizeof(InferShared), s, rows, X,
+                     theta, wb, prob, flags, threshold);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
