@@ -125,7 +125,8 @@ __device__ __forceinline__ void locate(const TiledLaunch& L, int64_t item, int& 
 template <bool BATCH, bool RAG>
 __device__ __forceinline__ void advance(const TiledLaunch& L, int& ji, int& col,
                                         int64_t& tile) {
-  if (!RAG && tile + 1 < sjob<BATCH>(L, ji).tiles) {
+  // 32-bit compare (tile counts are below 2^31): stays on the scalar unit
+  if (!RAG && (int32_t)tile + 1 < (int32_t)sjob<BATCH>(L, ji).tiles) {
     ++tile;
     return;
   }
@@ -146,8 +147,27 @@ __device__ __forceinline__ void advance(const TiledLaunch& L, int& ji, int& col,
 // for the one float4 cut by n), and unaligned columns (element loads).
 enum LoadMode { kFullVec = 0, kEdgeVec = 1, kScalar = 2 };
 
+// Word 3 of a raw buffer resource on gfx9-family parts (32-bit data, no
+// swizzle); word 2 holds the byte range, loads past it return zero.
+constexpr int kBufferFlags = 0x00020000;
+
+// Raw buffer loads bound to the LLVM intrinsics themselves: the clang builtin
+// for 128-bit buffer loads is lowered to a 32-bit load here.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ f32x4_t buffer_load_f32x4(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset,
+                                     int aux) __asm("llvm.amdgcn.raw.ptr.buffer.load.v4f32");
+__device__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset,
+                                    int aux) __asm("llvm.amdgcn.raw.ptr.buffer.load.i32");
+
+// Loads of one tile (and its sign word).  With `live` false nothing is read
+// and v is zero: the buffer range is empty.  Aligned columns use buffer loads
+// issued unconditionally, so that the compiler keeps them in flight across
+// the caller's branches (a load under a branch makes it wait for all loads at
+// the join).  One lane offset serves all eight loads; the k T/8 row offset
+// sits in a scalar register.  The range ends at row n: a 16-byte load that
+// straddles it returns its in-range words and zeros after them.
 template <int LOG_T, int MODE>
-__device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t tile,
+__device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t tile, bool live,
                                           float (&v)[kRegs], uint32_t& sw) {
   constexpr int T = 1 << LOG_T;
   const int tid = threadIdx.x;
@@ -158,31 +178,56 @@ __device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t t
   const int64_t rem = J.n - tile * T;
   const int lim = rem < T ? (int)rem : T;  // rows of this tile inside A
   // tile-major signs: bit 4k+e belongs to v[4k+e]
-  sw = (J.sign_words + tile * (T / kRegs))[(uint32_t)tid];
+  const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(J.sign_words + tile * (T / kRegs)), (short)0, live ? (T / kRegs) * 4 : 0,
+      kBufferFlags);
+  sw = buffer_load_u32(srsrc, 4 * tid, 0, 0);
+  if constexpr (MODE != kScalar) {
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)base, (short)0, live ? (MODE == kFullVec ? T : lim) * 4 : 0, kBufferFlags);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    // unsigned 32-bit offsets from a scalar base (no 64-bit lane arithmetic)
-    const uint32_t off = 4u * (uint32_t)tid + (uint32_t)(k * (T / 8));
-    if (MODE == kFullVec || (MODE == kEdgeVec && off + 4 <= (uint32_t)lim)) {
-      const float4 q = *reinterpret_cast<const float4*>(base + off);
+    for (int k = 0; k < 8; ++k) {
+      const f32x4_t q = buffer_load_f32x4(rsrc, 16 * tid, k * (T / 8) * 4, 0);
       v[4 * k + 0] = q.x;
       v[4 * k + 1] = q.y;
       v[4 * k + 2] = q.z;
       v[4 * k + 3] = q.w;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * k + e] = (off + e < (uint32_t)lim) ? base[off + e] : 0.0f;
     }
+    return;
+  }
+  // columns without 16-byte alignment: element loads up to row n
+  const int lv = live ? lim : 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t off = 4u * (uint32_t)tid + (uint32_t)(k * (T / 8));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[4 * k + e] = (off + e < (uint32_t)lv) ? base[off + e] : 0.0f;
   }
 }
 
 template <int SPT, int NT>
-__device__ __forceinline__ int load_rows(const SketchJob& J, int32_t (&srow)[SPT]) {
+__device__ __forceinline__ int load_kept_rows(const SketchJob& J, int32_t (&srow)[SPT]) {
   const int count = *J.count;
 #pragma unroll
   for (int s = 0; s < SPT; ++s) {
     const int l = threadIdx.x + s * NT;
     srow[s] = (l < count) ? J.rows[l] : 0;
+  }
+  return count;
+}
+
+// Kept rows handled by this thread, split for the combine: the LDS word of
+// z_t[i_lo] (padded) and the tile bits i_hi = i >> tau (rows are < 2^31).
+template <int LOG_T, int SPT, int NT>
+__device__ __forceinline__ int load_rows(const SketchJob& J, uint32_t (&zidx)[SPT],
+                                         uint32_t (&ihi)[SPT]) {
+  const int count = *J.count;
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const int l = threadIdx.x + s * NT;
+    const uint32_t i = (l < count) ? (uint32_t)J.rows[l] : 0u;
+    zidx[s] = (uint32_t)lds_pad((int)(i & ((1u << LOG_T) - 1u)));
+    ihi[s] = i >> LOG_T;
   }
   return count;
 }
@@ -206,9 +251,9 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
   int64_t tile;
   locate<BATCH, RAG>(L, item_begin, ji, col, tile);
 
-  int32_t srow[SPT];
+  uint32_t zidx[SPT], ihi[SPT];
   float acc[SPT];
-  int count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
+  int count = load_rows<LOG_T, SPT, NT>(sjob<BATCH>(L, ji), zidx, ihi);
 #pragma unroll
   for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
   // Partial slot of this workgroup in its columns: every column after the
@@ -221,15 +266,29 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
     piece = RAG ? J.pieces - 1 : (int)(w - owner_of(first, L.items, L.grid));
   }
 
-  float v[kRegs];
-  uint32_t sw;
+  // Two register buffers alternate between the tile being transformed and
+  // the next tile's loads, so the loads are in flight during every pass.
+  float va[kRegs], vb[kRegs];
+  uint32_t swa, swb;
   int64_t item = item_begin;
-  load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, v, sw);
+  load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, true, va, swa);
 
+  // pass-1 stores: padded word k*T/8 + 4 tid = lds_pad(4 tid) + k*(T/8 + T/256)
+  // (T/8 is a multiple of 128), one base and constant offsets
+  float* const p1 = lds + lds_pad(4 * tid);
   const int p2_base = (tid & 3) + ((tid >> 2) << 7) + ((tid >> 2) << 2);
   const int p3_base = (tid & 127) + (tid >> 7) * (4096 + 128);
 
-  while (item < item_end) {
+  auto step = [&](float (&v)[kRegs], uint32_t sw, float (&vn)[kRegs],
+                  uint32_t& swn) __attribute__((always_inline)) {
+    const int64_t next = item + 1;
+    const int cur_col = col;
+    const int cur_job = ji;
+    const int64_t cur_tile = tile;
+    // (a ragged launch gives every workgroup exactly one item: no prefetch)
+    const bool has_next = !RAG && next < item_end;
+    if (has_next) advance<BATCH, RAG>(L, ji, col, tile);
+    load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, has_next, vn, swn);
     // step 4 of Algorithm 1: the sign flip, fused into the load
 #pragma unroll
     for (int e = 0; e < kRegs; ++e) v[e] = flip(v[e], (sw >> e) & 1u);
@@ -238,17 +297,7 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       float4 q = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-      *reinterpret_cast<float4*>(&lds[lds_pad(k * (T / 8) + 4 * tid)]) = q;
-    }
-    // prefetch the next item while the LDS passes run
-    const int64_t next = item + 1;
-    const int cur_col = col;
-    const int cur_job = ji;
-    const int64_t cur_tile = tile;
-    // (a ragged launch gives every workgroup exactly one item: no prefetch)
-    if (!RAG && next < item_end) {
-      advance<BATCH, RAG>(L, ji, col, tile);
-      load_tile<LOG_T, MODE>(sjob<BATCH>(L, ji), col, tile, v, sw);
+      *reinterpret_cast<float4*>(p1 + k * (T / 8 + T / 256)) = q;
     }
     __syncthreads();
     {  // pass 2: bits 2..6
@@ -272,14 +321,12 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
     // pruned combine: y[i] += (-1)^popcount(i_hi & t) * z_t[i_lo]
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-      const int i = srow[s];
-      const float z = lds[lds_pad(i & (T - 1))];
-      const uint32_t par = (uint32_t)__popcll((uint64_t)(i >> LOG_T) & (uint64_t)cur_tile) & 1u;
-      acc[s] += flip(z, par);
+      const float z = lds[zidx[s]];
+      acc[s] += flip(z, (uint32_t)__popc(ihi[s] & (uint32_t)cur_tile) & 1u);
     }
     __syncthreads();
-    const bool new_job = BATCH && !RAG && (next < item_end) && (ji != cur_job);
-    const bool last_of_col = RAG || (next >= item_end) || (col != cur_col) || new_job;
+    const bool new_job = BATCH && !RAG && has_next && (ji != cur_job);
+    const bool last_of_col = RAG || !has_next || (col != cur_col) || new_job;
     if (last_of_col) {
       const SketchJob& J = sjob<BATCH>(L, cur_job);
       float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
@@ -291,8 +338,14 @@ __global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledL
       }
       piece = RAG ? piece : 0;
     }
-    if (new_job) count = load_rows<SPT, NT>(sjob<BATCH>(L, ji), srow);
+    if (new_job) count = load_rows<LOG_T, SPT, NT>(sjob<BATCH>(L, ji), zidx, ihi);
     item = next;
+  };
+
+  while (item < item_end) {
+    step(va, swa, vb, swb);
+    if (item >= item_end) break;
+    step(vb, swb, va, swa);
   }
 }
 
@@ -521,7 +574,7 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
   locate<false, RAG>(L, item_begin, ji, col, tile);
   int32_t srow[SPT];
   float acc[SPT];
-  int count = load_rows<SPT, NT>(L.one, srow);
+  int count = load_kept_rows<SPT, NT>(L.one, srow);
 #pragma unroll
   for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
   int piece = RAG ? L.one.pieces - 1
@@ -694,7 +747,10 @@ int get_tuning(rnnls_tuning* t) {
 int srht_pref_log_t(int m, int r_cap, int log_t_cap) {
   if (m <= 11) return 0;
   int cap = log_t_cap > 0 ? log_t_cap : g_log_tile.load();
-  int lt = cap > 0 ? cap : 15;
+  // untuned: 2^14-row tiles (two workgroups per CU, whose barrier phases
+  // interleave) while 8 kept rows per thread hold r_cap, else 2^15
+  if (cap <= 0) cap = (r_cap <= 8 * ((1 << 14) / kRegs)) ? 14 : 15;
+  int lt = cap;
   if (lt > m) lt = m;
   while (((1 << lt) / kRegs) * 32 < r_cap && lt < 15 && lt < m) ++lt;
   return lt;

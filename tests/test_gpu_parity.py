@@ -96,14 +96,14 @@ def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True)
 
 @pytest.mark.parametrize("n,d,r,seed", [
     (4096, 16, 512, 1),                 # one 4096-row tile
-    (3 * 32768 + 1234, 20, 1000, 5),    # several 2^15 tiles and a ragged tail
+    (3 * 32768 + 1234, 20, 1000, 5),    # several full tiles and a ragged tail
     (1 << 16, 7, 4000, 11),             # two tiles, many samples per thread
     (40000, 3, 2048, 2),                # ragged, 2^16 padded
     (8192, 1, 8191, 3),                 # r = n' - 1
     (1000, 5, 100, 4),                  # small n': direct kernel
     (2, 1, 1, 9),                       # smallest problem
     (20000, 128, 4096, 6),              # widest A
-    ((1 << 18) + 777, 64, 4096, 14),    # 2^15 tiles, the ragged tail in a second launch
+    ((1 << 18) + 777, 64, 4096, 14),    # full tiles, the ragged tail in a second launch
     (1 << 18, 64, 4096, 15),            # the same without a ragged tile
 ])
 def test_sketch_matches_oracle(n, d, r, seed):
@@ -113,8 +113,8 @@ def test_sketch_matches_oracle(n, d, r, seed):
 
 @pytest.mark.parametrize("log_tile,wgs", [(15, 1), (14, 2), (13, 4)])
 def test_sketch_with_tuned_tiles(log_tile, wgs):
-    """Tuned tile sizes and workgroups per CU (the default is 2^15 rows, one
-    workgroup per CU): same outputs."""
+    """Tuned tile sizes and workgroups per CU (the automatic choice here is
+    2^14 rows, two workgroups per CU): same outputs."""
     rnnls.set_tuning(log_tile, wgs)
     try:
         _sketch_case((1 << 18) + 777, 64, 4096, 21, data_seed=5)
