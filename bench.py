@@ -42,7 +42,7 @@ WORKLOADS = {
 # batching forms: 256 uneven tf-idf-like instances (n log-uniform in
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
-BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096")
+BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -162,6 +162,39 @@ def _timed(fn, steps, stream):
     return start.elapsed_time(stop) / steps
 
 
+def read_stream_peak(mib=1024, reps=20):
+    """GB/s of the library's streaming-read reference kernel over a buffer of
+    `mib` MiB (larger than the 256 MB last-level cache): the practical read
+    ceiling the sketch's HBM fraction is also stated against."""
+    import torch
+
+    from paper_0812_4547_amd import rnnls
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    parts = rnnls.stream_read(x)
+    for _ in range(3):
+        rnnls.stream_read(x, parts)
+    torch.cuda.synchronize()
+    rnnls.timing_enable(True)
+    rnnls.timing_read(rnnls.TIMER_STREAM_READ)
+    for _ in range(reps):
+        rnnls.stream_read(x, parts)
+    torch.cuda.synchronize()
+    ms, k = rnnls.timing_read(rnnls.TIMER_STREAM_READ)
+    rnnls.timing_enable(False)
+    if abs(float(parts.double().sum().item()) - x.numel()) > 1e-3 * x.numel():
+        raise RuntimeError("streaming-read reference returned a wrong sum")
+    del x
+    return (mib << 20) / (ms / max(k, 1) * 1e-3) / 1e9
+
+
+def _with_read_peak(roof):
+    """Add the measured streaming-read ceiling to a roofline record."""
+    peak = read_stream_peak()
+    roof["read_stream_peak"] = peak
+    roof["frac_of_read_stream"] = roof["achieved"] / peak
+    return roof
+
+
 def _base_record(args, value, ms, config, dtype="f32"):
     return {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -219,11 +252,12 @@ def bench_batch(args):
         "instances": len(shapes), "batch_seed": 4, "sketch_seeds": "1000 + i",
         "algorithmic_bytes": alg, "autotuned_tile": list(choice),
         "launch": "hipGraph replay of the batch plan"})
-    rec["roofline"] = {"kernel": "srht_tiled_kernel (all sketch launches of the pass)",
-                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sketch_ms,
-                       "sketch_launches_per_pass": sk_n / reps}
+    rec["roofline"] = _with_read_peak({
+        "kernel": "srht_tiled_kernel (all sketch launches of the pass)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sketch_ms,
+        "sketch_launches_per_pass": sk_n / reps})
     rec["breakdown_ms_per_pass_eager"] = {"sketch": sketch_ms, "moments": mo_ms / reps,
                                           "lawson_hanson": lh_ms / reps}
     rec["eager_ms_per_pass"] = eager_ms
@@ -271,10 +305,10 @@ def bench_multi(args):
         "workload": "tf-idf-like A 2^20 x 64 FP32 with 512 right-hand sides B = A X* + 5% "
                     "noise (nonnegative-factorisation-style update), r = 2048",
         "n": n, "d": d, "k": k, "r": r, "data_seed": 4})
-    rec["roofline"] = {"kernel": "srht_tiled_kernel", "bound": "hbm", "achieved": achieved,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": None, "algorithmic_bytes_per_launch": alg,
-                       "avg_launch_ms": sk}
+    rec["roofline"] = _with_read_peak({
+        "kernel": "srht_tiled_kernel", "bound": "hbm", "achieved": achieved,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None, "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sk})
     rec["breakdown_ms_per_step"] = {"sketch_kernel": sk_ms / args.steps,
                                     "moments": mo_ms / args.steps,
                                     "lawson_hanson": lh_ms / args.steps}
@@ -338,6 +372,74 @@ def bench_learned(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_fig1(args):
+    """Figure 1's comparison on the tf-idf-like 2^20 x 64 workload: for
+    r = d + 50 i (i = 1..8), the randomized solve's time split into
+    preprocessing (signs and rows, sketch, moments) and small problem
+    (Lawson-Hanson), beside the exact NNLS of the whole problem (moments over
+    all n rows, then Lawson-Hanson), and the relative error of x~ (residual
+    ratio minus one, Figure 1's measure).  One step = one randomized solve at
+    the largest r; every point is a mean over `steps` solves."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    n, d, ds = 1 << 20, 64, 2
+    p = workloads.tfidf_like(n, d, seed=ds)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    stream = torch.cuda.current_stream()
+    timers = (rnnls.TIMER_SKETCH, rnnls.TIMER_MOMENTS, rnnls.TIMER_SOLVE)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        rnnls.timing_enable(True)
+        for t in timers:
+            rnnls.timing_read(t)
+        ms = _timed(fn, reps, stream)
+        lh_ms, _ = rnnls.timing_read(rnnls.TIMER_SOLVE)
+        for t in timers[:2]:
+            rnnls.timing_read(t)
+        rnnls.timing_enable(False)
+        return ms, lh_ms / reps
+
+    ws_plain = rnnls.workspace(rnnls.OP_SOLVE, n, d, 0)
+    plain = rnnls.nnls_solve(A, b, ws=ws_plain)
+    plain_ms, plain_lh = timed(lambda: rnnls.nnls_solve(A, b, ws=ws_plain), max(3, args.steps // 5))
+    xp = plain.x.cpu().numpy()
+    res_plain = float(np.linalg.norm(A64 @ xp - b64))
+    rows = []
+    for i in range(1, 9):
+        r = d + 50 * i
+        ws = rnnls.workspace(rnnls.OP_RAND_NNLS, n, d, r)
+        out = rnnls.rand_nnls(A, b, r, 1000, ws=ws)
+        it = iter(range(10**9))
+        ms, lh = timed(lambda: rnnls.rand_nnls(A, b, r, 1000 + next(it), ws=ws, out=out), args.steps)
+        errs = []
+        for s in range(5):
+            x = rnnls.rand_nnls(A, b, r, 2000 + s, ws=ws).x.cpu().numpy()
+            errs.append(float(np.linalg.norm(A64 @ x - b64)) / res_plain - 1.0)
+        rows.append({"r": r, "overall_ms": ms, "preprocessing_ms": ms - lh, "small_problem_ms": lh,
+                     "relative_error_mean": float(np.mean(errs)),
+                     "relative_error_max": float(np.max(errs)), "error_seeds": 5,
+                     "status": int(out.status.item())})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    last = rows[-1]
+    rec = _base_record(args, 1000.0 / last["overall_ms"], last["overall_ms"], {
+        "workload": f"Figure 1-shaped comparison on tf-idf-like A {n}x{d} FP32: "
+                    "r = d + 50 i, i = 1..8, against the exact NNLS of the whole problem",
+        "n": n, "d": d, "data_seed": ds, "r_values": [row["r"] for row in rows],
+        "step": "one randomized solve at the largest r"})
+    rec["plain_full"] = {"overall_ms": plain_ms, "moments_ms": plain_ms - plain_lh,
+                         "small_problem_ms": plain_lh, "status": int(plain.status.item()),
+                         "residual": res_plain}
+    rec["fig1"] = rows
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +486,8 @@ def main():
         return bench_multi(args)
     if args.workload == "learned_4096":
         return bench_learned(args)
+    if args.workload == "fig1_2p20x64":
+        return bench_fig1(args)
 
     n, d, r, ds, ss = WORKLOADS[args.workload]
     planted = args.workload == "single_4096x16"
@@ -489,6 +593,7 @@ def main():
             "plain_status": int(plain.status.item()),
         },
     }
+    _with_read_peak(rec["roofline"])
     if not args.no_cpu_baseline:
         ns = args.cpu_samples or CPU_SAMPLES[args.workload]
         rec["cpu_baseline"] = cpu_baseline(n, d, r, ds, planted, ns)

@@ -362,10 +362,25 @@ int rnnls_get_tuning(rnnls_tuning* tuning);
 #define RNNLS_TIMER_SKETCH 0   /* the sketch transform kernel (steps 1-4)      */
 #define RNNLS_TIMER_MOMENTS 1  /* Gram-form moments of the small problem       */
 #define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel                         */
-#define RNNLS_TIMER_COUNT 3
+#define RNNLS_TIMER_STREAM_READ 3  /* the streaming-read reference kernel      */
+#define RNNLS_TIMER_COUNT 4
 
 int rnnls_timing_enable(int on);
 int rnnls_timing_read(int32_t which, double* total_ms, int64_t* launches);
+
+/* ---- streaming-read reference -------------------------------------------
+ * Not a step of the method: the sketch reads A once, so the fastest plain
+ * read of a buffer on the same device is its practical bandwidth ceiling, and
+ * its fraction of HBM peak is also stated against this measured rate.
+ * rnnls_stream_read reads x[0..n) (device, FP32, 16-byte aligned, n >= 0)
+ * once with 16-byte loads on a persistent grid of rnnls_stream_read_blocks()
+ * workgroups and writes partials[w] = the sum of the elements workgroup w
+ * read (device, caller-owned, that many floats; their total is sum(x) up to
+ * FP32 rounding).  Asynchronous on `stream`; timed as RNNLS_TIMER_STREAM_READ.
+ * Returns RNNLS_OK, -1 for an invalid argument (NULL, negative n, misaligned
+ * x) or RNNLS_E_HIP. */
+int rnnls_stream_read_blocks(void);
+int rnnls_stream_read(const float* x, int64_t n, float* partials, void* stream);
 
 #ifdef __cplusplus
 }

@@ -33,10 +33,10 @@ EXPORTS = (
     "rnnls_mlp_workspace_bytes", "rnnls_mlp_gradient", "rnnls_mlp_adam", "rnnls_mlp_train_step",
     "rnnls_batch_columns", "rnnls_batch_features", "rnnls_batch_set_model",
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
-    "rnnls_set_tuning", "rnnls_get_tuning",
+    "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
-TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE = 0, 1, 2
+TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ = 0, 1, 2, 3
 
 
 class Opts(ctypes.Structure):
@@ -102,6 +102,8 @@ _SIGS = {
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
     "rnnls_set_tuning": ([_p], ctypes.c_int),
     "rnnls_get_tuning": ([_p], ctypes.c_int),
+    "rnnls_stream_read_blocks": ([], ctypes.c_int),
+    "rnnls_stream_read": ([_p, ctypes.c_int64, _p, _p], ctypes.c_int),
 }
 
 
@@ -501,6 +503,21 @@ def set_tuning(srht_log_tile: int = 0, srht_wgs_per_cu: int = 0) -> None:
     """Launch shape of the sketch kernel (0 = automatic), process-wide."""
     t = Tuning(int(srht_log_tile), int(srht_wgs_per_cu))
     _check(load().rnnls_set_tuning(ctypes.byref(t)), "rnnls_set_tuning")
+
+
+def stream_read(x: torch.Tensor, partials: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Read x (contiguous FP32 on the device) once on the streaming-read
+    reference kernel (rnnls_stream_read); returns the per-workgroup partial sums."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise RnnlsError("stream_read needs a contiguous float32 tensor")
+    nb = load().rnnls_stream_read_blocks()
+    if partials is None:
+        partials = torch.empty(nb, dtype=torch.float32, device=x.device)
+    elif partials.numel() < nb or partials.dtype != torch.float32:
+        raise RnnlsError(f"stream_read needs {nb} float32 partials")
+    _check(load().rnnls_stream_read(_ptr(x), x.numel(), _ptr(partials), _stream(stream)),
+           "rnnls_stream_read")
+    return partials
 
 
 def get_tuning() -> tuple[int, int]:

@@ -95,3 +95,11 @@ def test_rand_nnls_argument_checks(lib):
     assert run(b=None) == -7
     assert run(x=None) == -8
     assert run(SA=1, ldsa=50) == -13
+
+
+def test_stream_read_argument_checks(lib):
+    # rejected before any device work
+    assert lib.rnnls_stream_read(None, -1, 16, None) == -1
+    assert lib.rnnls_stream_read(None, 8, 16, None) == -1          # NULL x with n > 0
+    assert lib.rnnls_stream_read(16, 8, None, None) == -1          # NULL partials
+    assert lib.rnnls_stream_read(20, 8, 16, None) == -1            # x not 16-byte aligned

@@ -321,3 +321,17 @@ def test_workspace_too_small_is_rejected():
     ws = torch.empty(256, dtype=torch.uint8, device="cuda")
     with pytest.raises(rnnls.RnnlsError):
         rnnls.rand_nnls(A, b, 512, 1, ws=ws)
+
+
+@pytest.mark.parametrize("n", [0, 3, 4096 + 2, (1 << 22) + 1])
+def test_stream_read_reference_reads_every_element(n):
+    """The streaming-read reference kernel: its partial sums add up to the
+    buffer's sum (every element read exactly once), tail included."""
+    print(f"stream_read n={n}", flush=True)
+    g = torch.Generator().manual_seed(n)
+    x = torch.rand(max(n, 1), generator=g, dtype=torch.float32)[:n].contiguous()
+    parts = rnnls.stream_read(x.cuda())
+    torch.cuda.synchronize()
+    got = parts.double().sum().item()
+    want = x.double().sum().item()
+    assert abs(got - want) <= 1e-5 * max(1.0, abs(want))
