@@ -3,6 +3,14 @@
 Inputs A (n x d), b (n), a positive integer r < n' and the seed of the random
 streams; output the nonnegative x~ that Lawson-Hanson finds for the sketched
 problem min_{x >= 0} ||H~ D A x - H~ D b||^2 (Algorithm 1, step 5).
+
+Repetition (Theorem 1 holds with probability at least 1/2; its footnote notes
+that a few repetitions raise that): k independent runs with the random streams
+of seeds seed, seed+1, ..., seed+k-1, keeping the x~ whose full residual
+||A x~ - b|| is smallest.  Each run meets the (1+eps) bound with probability
+at least 1/2, so the kept one does with probability at least 1 - 2^-k.
+Readings: candidates whose solve did not finish with status 0 are passed over
+unless none did; ties go to the lowest index.
 """
 from __future__ import annotations
 
@@ -28,3 +36,26 @@ def rand_nnls(A: np.ndarray, b: np.ndarray, r: int, seed: int,
     SA, Sb, R, _ = hadamard.srht_sketch(A, b, r, seed, mode)
     res = nnls.lawson_hanson(SA, Sb, tol=tol, max_iter=max_iter)
     return RandNNLSResult(x=res.x, SA=SA, Sb=Sb, rows=R, solve=res)
+
+
+@dataclass
+class BoostResult:
+    x: np.ndarray            # the kept x~
+    best: int                # its index i (seed + i)
+    residuals: np.ndarray    # ||A x_i - b||_2 of every candidate, FP64
+    statuses: np.ndarray     # Lawson-Hanson status of every candidate
+    candidates: list         # the k RandNNLSResult runs
+
+
+def rand_nnls_boost(A: np.ndarray, b: np.ndarray, r: int, k: int, seed: int,
+                    mode: str = "exact", tol: float | None = None,
+                    max_iter: int | None = None) -> BoostResult:
+    A64 = np.asarray(A, dtype=np.float64)
+    b64 = np.asarray(b, dtype=np.float64)
+    runs = [rand_nnls(A, b, r, seed + i, mode, tol, max_iter) for i in range(k)]
+    res = np.array([np.linalg.norm(A64 @ run.x - b64) for run in runs])
+    st = np.array([run.solve.status for run in runs])
+    ok = st == 0
+    pool = np.flatnonzero(ok) if ok.any() else np.arange(k)
+    best = int(pool[np.argmin(res[pool])])   # argmin takes the lowest index on ties
+    return BoostResult(x=runs[best].x, best=best, residuals=res, statuses=st, candidates=runs)

@@ -105,3 +105,45 @@ def test_padding_ragged_rows():
     b = g.random(n)
     SA, Sb, R, D = hadamard.srht_sketch(A, b, 100, 4)
     assert D.shape[0] == 4096 and R.max() < 4096
+
+
+def test_repetition_single_run_is_algorithm1():
+    p = workloads.uniform_planted(seed=3)
+    one = rand_nnls.rand_nnls(p.A, p.b, 512, 77)
+    rep = rand_nnls.rand_nnls_boost(p.A, p.b, 512, 1, 77)
+    assert rep.best == 0
+    assert np.array_equal(rep.x, one.x)
+
+
+def test_repetition_keeps_the_smallest_full_residual_and_grows_monotone():
+    # the runs of k seeds are a prefix of the runs of k + 1 seeds, so the kept
+    # residual can only fall as k grows; it is the least full residual
+    p = workloads.uniform_planted(seed=4)
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    prev = np.inf
+    for k in range(1, 6):
+        rep = rand_nnls.rand_nnls_boost(p.A, p.b, 40, k, 500)
+        got = float(np.linalg.norm(A64 @ rep.x - b64))
+        per_run = [float(np.linalg.norm(A64 @ rand_nnls.rand_nnls(p.A, p.b, 40, 500 + i).x - b64))
+                   for i in range(k)]
+        assert got == min(per_run)
+        assert got <= prev
+        prev = got
+
+
+def test_repetition_raises_the_success_probability():
+    # Theorem 1's footnote: with the threshold at the median residual of single
+    # runs, one run succeeds about half the time; keeping the best of 4
+    # independent runs fails only if all 4 fail (probability about 1/16)
+    p = workloads.uniform_planted(seed=5)
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    r = 40
+    single = [float(np.linalg.norm(A64 @ rand_nnls.rand_nnls(p.A, p.b, r, 10_000 + s).x - b64))
+              for s in range(60)]
+    thr = float(np.median(single))
+    trials, ok = 50, 0
+    for t in range(trials):
+        rep = rand_nnls.rand_nnls_boost(p.A, p.b, r, 4, 20_000 + 4 * t)
+        ok += float(np.linalg.norm(A64 @ rep.x - b64)) <= thr
+    # expected about 47; a binomial with p = 15/16 falls below 40 with probability < 1e-3
+    assert ok >= 40
