@@ -42,7 +42,8 @@ WORKLOADS = {
 # batching forms: 256 uneven tf-idf-like instances (n log-uniform in
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
-BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64")
+BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64",
+                   "boost_2p20x64_k4")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -440,6 +441,53 @@ def bench_fig1(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_boost(args):
+    """Repetition on the single-instance workload: one step = Algorithm 1 with
+    four seeds on tf-idf-like A 2^20 x 64 (r = 4096) plus the one pass over A
+    that forms the four full residuals and keeps the least."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    n, d, r, k, ds = 1 << 20, 64, 4096, 4, 2
+    p = workloads.tfidf_like(n, d, seed=ds)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    ws = rnnls.boost_workspace(n, d, r, k)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        rnnls.rand_nnls_boost(A, b, r, k, 100 * i, ws=ws)
+    torch.cuda.synchronize()
+    rnnls.timing_enable(True)
+    rnnls.timing_read(rnnls.TIMER_RESIDUAL)
+    it = iter(range(10**9))
+    ms = _timed(lambda: rnnls.rand_nnls_boost(A, b, r, k, 1000 + k * next(it), ws=ws),
+                args.steps, stream)
+    res_ms, res_n = rnnls.timing_read(rnnls.TIMER_RESIDUAL)
+    rnnls.timing_enable(False)
+    res_avg = res_ms / max(res_n, 1)
+    alg = 4 * n * (d + 1)
+    achieved = alg / (res_avg * 1e-3) / 1e9
+    out = rnnls.rand_nnls_boost(A, b, r, k, 7, ws=ws)
+    torch.cuda.synchronize()
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    plain = rnnls.nnls_solve(A, b)
+    res_plain = float(np.linalg.norm(A64 @ plain.x.cpu().numpy() - b64))
+    resid = out.resid.cpu().numpy()[:k]
+    rec = _base_record(args, 1000.0 / ms, ms, {
+        "workload": f"repetition of Algorithm 1: {k} seeds on tf-idf-like A {n}x{d} FP32, "
+                    f"r = {r}, keeping the least full residual",
+        "n": n, "d": d, "r": r, "k": k, "data_seed": ds})
+    rec["roofline"] = _with_read_peak({
+        "kernel": "boost_residual_kernel", "bound": "hbm", "achieved": achieved,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "algorithmic_bytes_per_launch": alg, "avg_launch_ms": res_avg, "launches": res_n})
+    rec["quality"] = {"residual_loss_kept_vs_plain_full_nnls": float(resid.min()) / res_plain - 1.0,
+                      "residual_loss_per_seed": [float(v) / res_plain - 1.0 for v in resid],
+                      "kept": int(out.best.item()), "status": int(out.status.item())}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +536,8 @@ def main():
         return bench_learned(args)
     if args.workload == "fig1_2p20x64":
         return bench_fig1(args)
+    if args.workload == "boost_2p20x64_k4":
+        return bench_boost(args)
 
     n, d, r, ds, ss = WORKLOADS[args.workload]
     planted = args.workload == "single_4096x16"

@@ -187,6 +187,34 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
                     int32_t* r_out, const rnnls_opts* opts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ---- repetition ---------------------------------------------------------
+ * rnnls_rand_nnls_boost -- Theorem 1's guarantee holds with probability at
+ * least 1/2; its footnote notes that a few repetitions raise that.  Runs
+ * Algorithm 1 k times (as rnnls_rand_nnls) with the random streams of seeds
+ * seed, seed+1, ..., seed+k-1, then keeps the x~ whose full residual
+ * ||A x~ - b||_2 is least (one FP64 pass over A for all k candidates), so the
+ * (1+eps) bound holds with probability at least 1 - 2^-k.  Candidates whose
+ * solve did not end with RNNLS_SOLVE_OK are passed over unless none did;
+ * ties go to the lowest index.
+ *
+ *  n, d, r, seed, A, lda, b   as rnnls_rand_nnls
+ *  k           repetitions, 1 <= k <= RNNLS_MAX_BOOST
+ *  x           output double[d]: the kept x~
+ *  resid       output double[k]: ||A x_i - b||_2 of every candidate; may be NULL
+ *  best        output int32[1]: index i of the kept candidate (seed + i); may be NULL
+ *  status      output int32[1]: the kept candidate's solve status; may be NULL
+ * Workspace: rnnls_boost_workspace_bytes(n, d, r, k, opts).  Returns as
+ * rnnls_rand_nnls (argument positions in this signature).
+ */
+#define RNNLS_MAX_BOOST 8
+
+size_t rnnls_boost_workspace_bytes(int64_t n, int32_t d, int32_t r, int32_t k,
+                                   const rnnls_opts* opts);
+int rnnls_rand_nnls_boost(int64_t n, int32_t d, int32_t r, int32_t k, uint64_t seed,
+                          const float* A, int64_t lda, const float* b, double* x,
+                          double* resid, int32_t* best, int32_t* status,
+                          const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- many right-hand sides sharing one A -------------------------------
  * rnnls_rand_nnls_multi -- Algorithm 1 for the k problems min ||A x_j - b_j||,
  * x_j >= 0, j < k, that share A (the extension Section 5 names, e.g. the
@@ -363,7 +391,8 @@ int rnnls_get_tuning(rnnls_tuning* tuning);
 #define RNNLS_TIMER_MOMENTS 1  /* Gram-form moments of the small problem       */
 #define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel                         */
 #define RNNLS_TIMER_STREAM_READ 3  /* the streaming-read reference kernel      */
-#define RNNLS_TIMER_COUNT 4
+#define RNNLS_TIMER_RESIDUAL 4 /* full residuals of the repetition candidates  */
+#define RNNLS_TIMER_COUNT 5
 
 int rnnls_timing_enable(int on);
 int rnnls_timing_read(int32_t which, double* total_ms, int64_t* launches);

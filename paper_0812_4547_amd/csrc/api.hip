@@ -397,6 +397,77 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
       lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm, iters, status), 1, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Repetition workspace: one rand_nnls workspace (the k runs reuse it in
+// stream order), then the k candidates, their statuses and the residual
+// partials.
+struct BoostLayout {
+  size_t rand = 0, X = 0, st = 0, part = 0, total = 0;
+  int grid = 0;
+};
+
+int boost_layout(int64_t n, int32_t d, int32_t r, int32_t k, const Opts& o, BoostLayout* B) {
+  Sizes z;
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 13, &z);
+  if (rc) return rc;
+  if (k < 1 || k > RNNLS_MAX_BOOST) return -4;
+  const int cus = device_cus();
+  if (cus < 0) return cus;
+  z.sp = plan_for(n, d + 1, z.r_cap, cus, o);
+  z.mp = moments_plan(z.r_cap, d, 1, cus);
+  size_t off = 0;
+  B->rand = put(off, layout_sketch(z, o, true, true).total);
+  B->X = put(off, sizeof(double) * (size_t)k * d);
+  B->st = put(off, sizeof(int32_t) * (size_t)k);
+  B->grid = boost_residual_grid(n, cus);
+  B->part = put(off, sizeof(double) * (size_t)B->grid * boost_slots(k));
+  B->total = off;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rnnls_boost_workspace_bytes(int64_t n, int32_t d, int32_t r, int32_t k,
+                                   const rnnls_opts* opts) {
+  BoostLayout B;
+  return boost_layout(n, d, r, k, read_opts(opts), &B) ? 0 : B.total;
+}
+
+int rnnls_rand_nnls_boost(int64_t n, int32_t d, int32_t r, int32_t k, uint64_t seed,
+                          const float* A, int64_t lda, const float* b, double* x,
+                          double* resid, int32_t* best, int32_t* status,
+                          const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  const Opts o = read_opts(opts);
+  Sizes z;
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 13, &z);
+  if (rc) return rc;
+  if (k < 1 || k > RNNLS_MAX_BOOST) return -4;
+  if (!A) return -6;
+  if (lda < n) return -7;
+  if (!b) return -8;
+  if (!x) return -9;
+  BoostLayout B;
+  rc = boost_layout(n, d, r, k, o, &B);
+  if (rc) return rc;
+  if (!ws_ok(ws, ws_bytes, B.total)) return RNNLS_E_WORKSPACE;
+  double* X = at<double>(ws, B.X);
+  int32_t* st = at<int32_t>(ws, B.st);
+  const size_t rand_bytes = B.X - B.rand;
+  for (int i = 0; i < k; ++i) {
+    rc = rnnls_rand_nnls(n, d, r, seed + (uint64_t)i, A, lda, b, X + (size_t)i * d, nullptr,
+                         nullptr, st + i, nullptr, 0, nullptr, nullptr, nullptr, opts,
+                         at<void>(ws, B.rand), rand_bytes, stream);
+    if (rc) return rc;
+  }
+  return launch_boost_select(n, d, k, A, lda, b, X, st, at<double>(ws, B.part), B.grid, x, resid,
+                             best, status, reinterpret_cast<hipStream_t>(stream));
+}
+
 size_t rnnls_multi_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t r,
                                    const rnnls_opts* opts) {
   const Opts o = read_opts(opts);

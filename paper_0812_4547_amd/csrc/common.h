@@ -261,6 +261,16 @@ int launch_passive_flags(const void* jobs, int njobs, uint8_t* flags, hipStream_
 int launch_mlp_forward(int64_t rows, const float* X, const float* theta, const uint16_t* wb,
                        float* prob, uint8_t* flags, float threshold, hipStream_t s);
 
+// Repetition (boost.hip): the residual pass's grid, the residual slots per
+// workgroup for k candidates, and the residual + selection launches.  X holds
+// the k candidates (d doubles each), st their solve statuses; partials holds
+// grid * boost_slots(k) doubles.
+int boost_residual_grid(int64_t n, int cus);
+int boost_slots(int k);
+int launch_boost_select(int64_t n, int d, int k, const float* A, int64_t lda, const float* b,
+                        const double* X, const int32_t* st, double* partials, int grid,
+                        double* x, double* resid, int32_t* best, int32_t* status, hipStream_t s);
+
 int device_cus();
 
 // Event timing (timing.hip): no-ops unless rnnls_timing_enable(1), and while

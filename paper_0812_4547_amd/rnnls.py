@@ -22,7 +22,7 @@ SOLVE_OK, SOLVE_MAX_ITER, SOLVE_KKT_FAIL, SOLVE_NO_ROWS, SOLVE_OVERFLOW = 0, 1, 
 SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
-MAX_D, MAX_R, MAX_K = 128, 32768, 4096
+MAX_D, MAX_R, MAX_K, MAX_BOOST = 128, 32768, 4096, 8
 
 EXPORTS = (
     "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
@@ -34,9 +34,10 @@ EXPORTS = (
     "rnnls_batch_columns", "rnnls_batch_features", "rnnls_batch_set_model",
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
+    "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
-TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ = 0, 1, 2, 3
+TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
 
 
 class Opts(ctypes.Structure):
@@ -76,6 +77,9 @@ _SIGS = {
     "rnnls_rand_nnls": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
                          _p, _p, _p, _sz, _p], ctypes.c_int),
     "rnnls_multi_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
+    "rnnls_boost_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
+    "rnnls_rand_nnls_boost": ([_i64, _i32, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p,
+                               _p, _sz, _p], ctypes.c_int),
     "rnnls_rand_nnls_multi": ([_i64, _i32, _i32, _i32, _u64, _p, _i64, _p, _i64, _p, _i64, _p,
                                _p, _p, _p, _p, _sz, _p], ctypes.c_int),
     "rnnls_batch_workspace_bytes": ([_i32, _p, _p], _sz),
@@ -289,6 +293,43 @@ class MultiSolution:
     rnorm: torch.Tensor   # float64 (k,)
     iters: torch.Tensor   # int32 (k,)
     status: torch.Tensor  # int32 (k,)
+
+
+def boost_workspace(n: int, d: int, r: int, k: int, opts: Opts | None = None, device="cuda"):
+    nbytes = int(load().rnnls_boost_workspace_bytes(n, d, r, k, ctypes.byref(opts or Opts())))
+    if nbytes == 0:
+        raise RnnlsError("invalid sizes for the workspace query")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+@dataclass
+class BoostSolution:
+    x: torch.Tensor       # float64 (d,): the kept x~
+    resid: torch.Tensor   # float64 (k,): ||A x_i - b|| of every candidate
+    best: torch.Tensor    # int32 (1,): index of the kept candidate (seed + i)
+    status: torch.Tensor  # int32 (1,): its solve status
+
+
+def rand_nnls_boost(A: torch.Tensor, b: torch.Tensor, r: int, k: int, seed: int,
+                    opts: Opts | None = None, ws=None, stream=None) -> BoostSolution:
+    """k repetitions of Algorithm 1 (seeds seed .. seed+k-1), keeping the x~
+    with the least full residual (rnnls_rand_nnls_boost)."""
+    opts = opts or Opts()
+    n, d = A.shape
+    lda = _check_colmajor(A, "A")
+    dev = A.device
+    out = BoostSolution(torch.empty(d, dtype=torch.float64, device=dev),
+                        torch.empty(max(k, 1), dtype=torch.float64, device=dev),
+                        torch.empty(1, dtype=torch.int32, device=dev),
+                        torch.empty(1, dtype=torch.int32, device=dev))
+    if ws is None:
+        ws = boost_workspace(n, d, r, k, opts, dev)
+    rc = load().rnnls_rand_nnls_boost(n, d, r, k, seed & (2**64 - 1), _ptr(A), lda, _ptr(b),
+                                      _ptr(out.x), _ptr(out.resid), _ptr(out.best),
+                                      _ptr(out.status), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                      _stream(stream))
+    _check(rc, "rnnls_rand_nnls_boost")
+    return out
 
 
 def multi_workspace(n: int, d: int, k: int, r: int, opts: Opts | None = None, device="cuda"):

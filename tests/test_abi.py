@@ -103,3 +103,20 @@ def test_stream_read_argument_checks(lib):
     assert lib.rnnls_stream_read(None, 8, 16, None) == -1          # NULL x with n > 0
     assert lib.rnnls_stream_read(16, 8, None, None) == -1          # NULL partials
     assert lib.rnnls_stream_read(20, 8, 16, None) == -1            # x not 16-byte aligned
+
+
+def test_rand_nnls_boost_argument_checks(lib):
+    o = rnnls.Opts()
+
+    def run(n=4096, d=4, r=100, k=3, A=1, lda=4096, b=1, x=1):
+        return lib.rnnls_rand_nnls_boost(n, d, r, k, 3, A, lda, b, x, None, None, None,
+                                         ctypes.byref(o), None, 0, None)
+    assert run(n=1) == -1
+    assert run(d=200) == -2
+    assert run(r=4096) == -3
+    assert run(k=0) == -4
+    assert run(k=rnnls.MAX_BOOST + 1) == -4
+    assert run(A=None) == -6
+    assert run(lda=10) == -7
+    assert run(b=None) == -8
+    assert run(x=None) == -9
