@@ -43,7 +43,7 @@ WORKLOADS = {
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
 BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64",
-                   "boost_2p20x64_k4")
+                   "boost_2p20x64_k4", "nmf_2p16x2048_q32")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -488,6 +488,36 @@ def bench_boost(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_nmf(args):
+    """Nonnegative factorisation by alternating NNLS, each half-step Algorithm 1
+    for many right-hand sides: tf-idf-like A 2^16 x 2048, rank 32.  One step =
+    one iteration (an H half-step of 2048 problems on 2^16 rows and a W
+    half-step of 2^16 problems on 2048 rows, in chunks of 4096)."""
+    import torch
+
+    from paper_0812_4547_amd import nmf, rnnls, workloads
+    m, n, q, r_h, r_w = 1 << 16, 2048, 32, 1024, 512
+    p = workloads.tfidf_like(m, n, seed=6)
+    A = rnnls.colmajor(p.A)
+    del p
+    stream = torch.cuda.current_stream()
+    res = nmf.nmf_als(A, q, max(1, args.warmup), r_h, r_w, seed=1)
+    W0 = res.W
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = nmf.nmf_als(A, q, args.steps, r_h, r_w, seed=1, W0=W0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    rec = _base_record(args, (m + n) * 1000.0 / ms, ms, {
+        "workload": f"nonnegative factorisation by alternating NNLS of tf-idf-like A {m}x{n}, "
+                    f"rank {q}, sketch rows {r_h} (H half-step) and {r_w} (W half-step)",
+        "m": m, "n": n, "q": q, "r_h": r_h, "r_w": r_w, "data_seed": 6,
+        "step": "one iteration (m + n NNLS solves)"})
+    rec["sketched_objective_per_half_step"] = res.sketched_objective
+    rec["frobenius_norm_of_A"] = float(torch.linalg.vector_norm(A).item())
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -538,6 +568,8 @@ def main():
         return bench_fig1(args)
     if args.workload == "boost_2p20x64_k4":
         return bench_boost(args)
+    if args.workload == "nmf_2p16x2048_q32":
+        return bench_nmf(args)
 
     n, d, r, ds, ss = WORKLOADS[args.workload]
     planted = args.workload == "single_4096x16"

@@ -1,0 +1,45 @@
+"""Alternating-NNLS factorisation on the device (each half-step Algorithm 1
+for many right-hand sides) against the oracle's exact alternating NNLS."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nmf as onmf
+from paper_0812_4547_amd import nmf, rnnls, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_nmf_recovers_a_planted_factorisation():
+    # A = W* H* exactly: from W0 = W*, the first H half-step's sketched
+    # problems have the exact solutions h*_j, which Lawson-Hanson finds
+    print("nmf planted", flush=True)
+    g = np.random.default_rng(11)
+    m, n, q = 4096, 300, 6
+    W = (g.random((m, q)) * (g.random((m, q)) < 0.5)).astype(np.float32)
+    H = (g.random((q, n)) * (g.random((q, n)) < 0.5)).astype(np.float32)
+    W[:q, :q] += np.eye(q, dtype=np.float32)
+    H[:, :q] += np.eye(q, dtype=np.float32)
+    A = rnnls.colmajor(W @ H)
+    res = nmf.nmf_als(A, q, 1, r_h=512, r_w=128, seed=3, W0=torch.from_numpy(W))
+    H1 = res.H.cpu().numpy()
+    np.testing.assert_allclose(H1, H, atol=2e-4)
+    assert res.sketched_objective[0] <= 1e-3 * float(np.linalg.norm(W @ H))
+
+
+def test_nmf_tracks_exact_alternating_nnls():
+    print("nmf vs oracle anls", flush=True)
+    m, n, q, iters = 2048, 96, 5, 3
+    p = workloads.tfidf_like(m, n, seed=7)
+    A_h = p.A
+    W0 = np.random.default_rng(8).random((m, q)).astype(np.float32)
+    res = nmf.nmf_als(rnnls.colmajor(A_h), q, iters, r_h=512, r_w=64, seed=5,
+                      W0=torch.from_numpy(W0))
+    W, H = res.W.cpu().numpy().astype(np.float64), res.H.cpu().numpy().astype(np.float64)
+    got = onmf.objective(A_h, W, H)
+    _, _, hist = onmf.anls(A_h, W0, iters)
+    # randomized half-steps stay near the exact ones: within 5% of the exact
+    # alternating objective, and below the starting point's first half-step
+    assert got <= hist[-1] * 1.05
+    assert got < hist[0]
+    assert np.all(W >= 0) and np.all(H >= 0)
