@@ -12,6 +12,13 @@
 //              inverse runs the rounds backwards: x ^= x >> ceil(m/2) is its
 //              own inverse on m bits, the odd multiplier is inverted mod 2^m.
 //   BERNOULLI: j is kept iff h(seed, SAMPLE, j) < r * 2^(64-m).
+//
+// Exact mode with r_cap <= 16384 takes one launch instead: the kept rows are
+// the set {pi(k) : k < r}, so workgroup 0 forms those r values, counts them
+// per segment of n'/1024 rows, places them by the segments' offsets and sorts
+// each segment's few values in LDS; the other workgroups write the sign words.
+#include <atomic>
+
 #include "common.h"
 
 namespace rnnls {
@@ -20,6 +27,10 @@ namespace {
 
 constexpr int kScanThreads = 256;  // four threads per word: 64 words per pass
 constexpr int kWriteThreads = 64;  // one wavefront per segment
+constexpr int kExactThreads = 1024;  // single-launch exact mode
+constexpr int kExactSegs = 1024;     // row segments of the placement (one per thread)
+constexpr int kExactWordsPerBlock = kExactThreads / 4;  // sign words per workgroup (one pass)
+constexpr int kExactMaxRows = 16384;
 
 // log2 of the rows of a segment, and the number of segments, for n' = 2^m
 __host__ __device__ inline int seg_log(int m) { return m - 11 > 11 ? m - 11 : 11; }
@@ -84,6 +95,31 @@ __device__ __forceinline__ StreamJob job_of_block(const StreamJob& one, const St
   return j;
 }
 
+// This thread's 8 bits (part 0..3) of sign word w: the sketch kernel's
+// tile-major layout (word tile*(T/32) + tid, bit 4k+e = row tile*T + k*T/8 +
+// 4*tid + e) or the natural one, and the natural bits for an export.
+__device__ __forceinline__ void sign_bits(const StreamJob& J, int64_t w, int part,
+                                          uint64_t sign_key, int64_t n_pad, int64_t nt,
+                                          int kstride, bool export_nat, uint32_t* sbits,
+                                          uint32_t* nat) {
+  const uint64_t base = (uint64_t)w * 32ull;
+  const uint64_t first =
+      J.sign_log_t > 0 ? ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt) : base;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = 8 * part + k;
+    const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
+    if ((int64_t)j < n_pad) *sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
+  }
+  if (export_nat) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t j = base + (uint64_t)(8 * part + k);
+      *nat |= (uint32_t)(mix64(sign_key + j) >> 63) << (8 * part + k);
+    }
+  }
+}
+
 // words [w0, w1) of segment `seg`
 __device__ __forceinline__ void segment_words(int m, int64_t seg, int64_t* w0, int64_t* w1) {
   const int64_t nwords = ((1ll << m) + 31) / 32;
@@ -128,22 +164,7 @@ __global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJ
         const uint64_t j = base + (uint64_t)(8 * part + k);
         if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << (8 * part + k);
       }
-      const uint64_t first =
-          J.sign_log_t > 0 ? ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt)
-                           : base;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int b = 8 * part + k;
-        const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
-        if ((int64_t)j < n_pad) sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
-      }
-      if (export_nat) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint64_t j = base + (uint64_t)(8 * part + k);
-          nat |= (uint32_t)(mix64(sign_key + j) >> 63) << (8 * part + k);
-        }
-      }
+      sign_bits(J, w, part, sign_key, n_pad, nt, kstride, export_nat, &sbits, &nat);
     }
     // the four threads of a word are neighbouring lanes of one wavefront
 #pragma unroll
@@ -218,6 +239,100 @@ __global__ __launch_bounds__(kWriteThreads) void streams_write_rows_kernel(Strea
   }
 }
 
+// Exact mode in one launch.  Workgroup 0: the kept rows; workgroups 1..: the
+// sign words, kExactWordsPerBlock each.  Dynamic LDS: 2 r_cap + 2 kExactSegs
+// uint32.
+__global__ __launch_bounds__(kExactThreads) void streams_exact_kernel(StreamJob J) {
+  extern __shared__ uint32_t ex_smem[];
+  const int t = threadIdx.x;
+  if (blockIdx.x > 0) {
+    const uint64_t sign_key = stream_key(J.seed, kStreamSign);
+    const int64_t n_pad = 1ll << J.m;
+    const int64_t nwords = (n_pad + 31) / 32;
+    const int64_t nt = J.sign_log_t > 0 ? ((1ll << J.sign_log_t) >> 5) : 1;
+    const int kstride = J.sign_log_t > 0 ? (int)((1ll << J.sign_log_t) >> 3) : 4;
+    const bool export_nat = J.sign_export && J.sign_export != J.sign_words && J.sign_log_t > 0;
+    const int part = t & 3;
+    const int64_t w0 = (int64_t)(blockIdx.x - 1) * kExactWordsPerBlock;
+    for (int64_t wb = w0; wb < w0 + kExactWordsPerBlock; wb += kExactThreads / 4) {
+      const int64_t w = wb + (t >> 2);
+      uint32_t sbits = 0, nat = 0;
+      if (w < nwords) sign_bits(J, w, part, sign_key, n_pad, nt, kstride, export_nat, &sbits, &nat);
+#pragma unroll
+      for (int off = 1; off < 4; off <<= 1) {
+        sbits |= (uint32_t)__shfl_xor((int)sbits, off, 64);
+        nat |= (uint32_t)__shfl_xor((int)nat, off, 64);
+      }
+      if (part == 0 && w < nwords) {
+        J.sign_words[w] = sbits;
+        if (J.sign_export && J.sign_export != J.sign_words) J.sign_export[w] = export_nat ? nat : sbits;
+      }
+    }
+    return;
+  }
+  uint32_t* vals = ex_smem;                 // pi(k), k < r
+  uint32_t* out = ex_smem + J.r_cap;        // the same, grouped by segment
+  uint32_t* cnt = ex_smem + 2 * J.r_cap;    // per-segment counts, then cursors (ends)
+  uint32_t* off = cnt + kExactSegs;         // exclusive offsets (starts)
+  __shared__ uint32_t wave_tot[kExactThreads / 64];
+  const PermKeys keys = make_perm_keys(J.seed, J.m);
+  const int shift = J.m > 10 ? J.m - 10 : 0;  // segment of row x: x >> shift
+  const int r = J.r;
+  cnt[t] = 0u;
+  __syncthreads();
+  for (int k = t; k < r; k += kExactThreads) {
+    const uint32_t x = perm_apply(keys, (uint32_t)k);
+    vals[k] = x;
+    atomicAdd(&cnt[x >> shift], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the 1024 counts (one per thread): wavefront scans, then
+  // a scan of the 16 wavefront totals by the first wavefront
+  const uint32_t mine = cnt[t];
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+    if ((t & 63) >= o) incl += v;
+  }
+  if ((t & 63) == 63) wave_tot[t >> 6] = incl;
+  __syncthreads();
+  if (t < 64) {
+    const uint32_t w = t < kExactThreads / 64 ? wave_tot[t] : 0u;
+    uint32_t wi = w;
+#pragma unroll
+    for (int o = 1; o < kExactThreads / 64; o <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)wi, o, 64);
+      if (t >= o) wi += v;
+    }
+    if (t < kExactThreads / 64) wave_tot[t] = wi - w;  // exclusive
+  }
+  __syncthreads();
+  const uint32_t start = wave_tot[t >> 6] + incl - mine;
+  off[t] = start;
+  cnt[t] = start;  // cursor
+  __syncthreads();
+  for (int k = t; k < r; k += kExactThreads) {
+    const uint32_t x = vals[k];
+    out[atomicAdd(&cnt[x >> shift], 1u)] = x;
+  }
+  __syncthreads();
+  // final position of each value: its segment's start plus the number of
+  // smaller values in the segment (distinct values; independent reads)
+  for (int i = t; i < r; i += kExactThreads) {
+    const uint32_t x = out[i];
+    const uint32_t sg = x >> shift;
+    const uint32_t b0 = off[sg], b1 = cnt[sg];
+    uint32_t rank = 0;
+    for (uint32_t p = b0; p < b1; ++p) rank += out[p] < x ? 1u : 0u;
+    J.rows[b0 + rank] = (int32_t)x;
+  }
+  if (t == 0) {
+    *J.count = r;
+    if (J.status) *J.status = RNNLS_SOLVE_OK;
+  }
+}
+
 }  // namespace
 
 size_t streams_scratch_words(int64_t n_pad) {
@@ -230,6 +345,22 @@ size_t streams_scratch_words(int64_t n_pad) {
 int64_t streams_blocks(int m) { return n_segments(m); }
 
 int launch_streams(const StreamJob& j, hipStream_t s) {
+  if (j.mode == RNNLS_SAMPLE_EXACT && j.r_cap <= kExactMaxRows && j.r <= j.r_cap) {
+    const int64_t nwords = ((1ll << j.m) + 31) / 32;
+    const unsigned nb = 1u + (unsigned)((nwords + kExactWordsPerBlock - 1) / kExactWordsPerBlock);
+    const size_t lds = sizeof(uint32_t) * (2 * (size_t)j.r_cap + 2 * kExactSegs);
+    // above 64 KB of dynamic LDS the kernel's limit is raised first (once)
+    static std::atomic<int> lds_limit_set{0};
+    if (lds > 65536 && !lds_limit_set.load()) {
+      const int max_bytes = (int)(sizeof(uint32_t) * (2 * (size_t)kExactMaxRows + 2 * kExactSegs));
+      if (hipFuncSetAttribute((const void*)streams_exact_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes) != hipSuccess)
+        return RNNLS_E_HIP;
+      lds_limit_set.store(1);
+    }
+    hipLaunchKernelGGL(streams_exact_kernel, dim3(nb), dim3(kExactThreads), lds, s, j);
+    return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
+  }
   const unsigned nb = (unsigned)streams_blocks(j.m);
   hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kScanThreads), 0, s, j,
                      (const StreamJob*)nullptr, (const int32_t*)nullptr);

@@ -71,6 +71,22 @@ def test_rows_and_signs_bit_exact_against_golden():
         assert np.array_equal(skb.rows.cpu().numpy()[:cnt], want)
 
 
+@pytest.mark.parametrize("n_pad,r,seed", [(1 << 16, 16384, 31), (1 << 16, 16385, 32),
+                                         (1 << 15, 7000, 33), (1 << 12, 4095, 34)])
+def test_exact_rows_at_the_single_launch_limits(n_pad, r, seed):
+    """Exact rows and signs bit-exact where the single-launch row placement
+    needs more than 64 KB of LDS (r = 16384), just past its limit (two
+    launches) and with every segment nearly full (r = n' - 1)."""
+    print(f"exact rows n'={n_pad} r={r} seed={seed}", flush=True)
+    A = torch.zeros((1, n_pad), dtype=torch.float32, device="cuda").t()
+    sk = rnnls.srht_sketch(A, None, r, seed, export_signs=True)
+    torch.cuda.synchronize()
+    assert int(sk.count.item()) == r
+    assert int(sk.status.item()) == 0
+    assert np.array_equal(sk.rows.cpu().numpy(), rng.rows_exact(seed, n_pad, r))
+    assert np.array_equal(_unpack_signs(sk.sign_bits, n_pad), rng.signs(seed, n_pad))
+
+
 # ------------------------------------------------------------------ sketch
 def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True):
     g = np.random.default_rng(data_seed)
