@@ -43,7 +43,7 @@ WORKLOADS = {
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
 BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64",
-                   "boost_2p20x64_k4", "nmf_2p16x2048_q32")
+                   "boost_2p20x64_k4", "nmf_2p16x2048_q32", "density_sweep_1e4x128")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -518,6 +518,66 @@ def bench_nmf(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_density(args):
+    """The sparse-versus-dense experiment (Section 4.2) with d = 128 (this
+    solver's limit; the paper uses 300): n = 10,000, densities 2..64%, for each
+    density 10 random n x (d+1) matrices (nonzeros uniform in [0, 1]) and 10
+    choices of the column that becomes b (100 problems); r = d, d+50, d+100,
+    d+150 in both sampling modes, against the exact solve on all n rows.
+    Relative error = residual ratio minus one; times are GPU means per solve."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    n, d = 10_000, 128
+    densities = (0.02, 0.04, 0.08, 0.16, 0.32, 0.64)
+    rs = (d, d + 50, d + 100, d + 150)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for di, dens in enumerate(densities):
+        probs = []
+        for mi in range(10):
+            M = workloads.density_matrix(n, d + 1, dens, seed=1000 * di + mi)
+            g = np.random.default_rng(5000 + 10 * di + mi)
+            for col in g.choice(d + 1, size=10, replace=False):
+                p = workloads.density_problem(M, int(col))
+                probs.append((rnnls.colmajor(p.A), torch.from_numpy(p.b).cuda(),
+                              p.A.astype(np.float64), p.b.astype(np.float64)))
+        ws_plain = rnnls.workspace(rnnls.OP_SOLVE, n, d, 0)
+        plain = [rnnls.nnls_solve(A, b, ws=ws_plain) for A, b, _, _ in probs]
+        torch.cuda.synchronize()
+        exact_ms = _timed(lambda: [rnnls.nnls_solve(A, b, ws=ws_plain) for A, b, _, _ in probs],
+                          1, stream) / len(probs)
+        res_plain = [float(np.linalg.norm(A64 @ s.x.cpu().numpy() - b64))
+                     for (_, _, A64, b64), s in zip(probs, plain)]
+        for mode in ("bernoulli", "exact"):
+            opts = rnnls.make_opts(mode)
+            for r in rs:
+                ws = rnnls.workspace(rnnls.OP_RAND_NNLS, n, d, r, opts)
+                sols = [rnnls.rand_nnls(A, b, r, 7 + i, opts=opts, ws=None)
+                        for i, (A, b, _, _) in enumerate(probs)]
+                torch.cuda.synchronize()
+                ms = _timed(lambda: [rnnls.rand_nnls(A, b, r, 7 + i, opts=opts, ws=ws)
+                                     for i, (A, b, _, _) in enumerate(probs)], 1, stream) / len(probs)
+                err = [float(np.linalg.norm(A64 @ s.x.cpu().numpy() - b64)) / rp - 1.0
+                       for (_, _, A64, b64), s, rp in zip(probs, sols, res_plain)]
+                ok = sum(int(s.status.item()) == 0 for s in sols)
+                rows.append({"density": dens, "mode": mode, "r": r, "problems": len(probs),
+                             "relative_error_mean": float(np.mean(err)),
+                             "relative_error_max": float(np.max(err)), "status_ok": ok,
+                             "rand_ms": ms, "exact_full_ms": exact_ms,
+                             "speedup_vs_exact_full": exact_ms / ms})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    last = rows[-1]
+    rec = _base_record(args, 1000.0 / last["rand_ms"], last["rand_ms"], {
+        "workload": "sparse-versus-dense experiment: n = 10,000, d = 128, densities 2..64%, "
+                    "100 problems per density, r = d + 50 i (i = 0..3), both sampling modes",
+        "n": n, "d": d, "densities": list(densities), "r_values": list(rs),
+        "step": "one randomized solve (density 64%, exact mode, r = d + 150)"})
+    rec["sweep"] = rows
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,6 +630,8 @@ def main():
         return bench_boost(args)
     if args.workload == "nmf_2p16x2048_q32":
         return bench_nmf(args)
+    if args.workload == "density_sweep_1e4x128":
+        return bench_density(args)
 
     n, d, r, ds, ss = WORKLOADS[args.workload]
     planted = args.workload == "single_4096x16"

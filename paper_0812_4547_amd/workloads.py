@@ -59,6 +59,23 @@ def uniform_planted(n: int = 4096, d: int = 16, zeros: int = 8, sigma: float = 0
                    name=f"uniform_planted n={n} d={d}")
 
 
+def density_matrix(n: int, cols: int, density: float, seed: int) -> np.ndarray:
+    """n x cols FP32 random matrix of the sparse-versus-dense experiment
+    (Section 4.2): each entry nonzero with probability `density`, nonzero
+    values uniform in [0, 1] (the text's "normally distributed in [0,1]"
+    taken as uniform), stored dense."""
+    g = np.random.default_rng(seed)
+    M = g.random((n, cols)) * (g.random((n, cols)) < density)
+    return M.astype(np.float32)
+
+
+def density_problem(M: np.ndarray, col: int) -> Problem:
+    """b = column `col` of M, A = the remaining columns (Section 4.2)."""
+    keep = [c for c in range(M.shape[1]) if c != col]
+    return Problem(A=np.asfortranarray(M[:, keep]), b=np.ascontiguousarray(M[:, col]),
+                   x_star=None, name=f"density column {col}")
+
+
 def zipf_densities(d: int, mean_density: float, s: float, g) -> np.ndarray:
     """Column densities rho_k = mean * d * k^-s / sum_j j^-s for ranks
     k = 1..d, randomly permuted over the columns."""

@@ -87,6 +87,25 @@ def test_exact_rows_at_the_single_launch_limits(n_pad, r, seed):
     assert np.array_equal(_unpack_signs(sk.sign_bits, n_pad), rng.signs(seed, n_pad))
 
 
+@pytest.mark.parametrize("density,mode,col", [(0.02, "bernoulli", 5), (0.64, "bernoulli", 77),
+                                              (0.02, "exact", 0), (0.64, "exact", 128)])
+def test_rand_nnls_density_sweep_inputs(density, mode, col):
+    """The sparse-versus-dense experiment's inputs (n = 10,000, d = 128 here,
+    r = d + 150) in both sampling modes: rows and x~ against the oracle."""
+    print(f"density sweep density={density} mode={mode} col={col}", flush=True)
+    M = workloads.density_matrix(10_000, 129, density, seed=int(density * 100) + 7)
+    p = workloads.density_problem(M, col)
+    r, seed = 128 + 150, 40 + col
+    opts = rnnls.make_opts(mode)
+    sol = rnnls.rand_nnls(rnnls.colmajor(p.A), torch.from_numpy(p.b).cuda(), r, seed, opts=opts)
+    torch.cuda.synchronize()
+    ref = rand_nnls.rand_nnls(p.A, p.b, r, seed, mode=mode)
+    x = sol.x.cpu().numpy()
+    assert int(sol.status.item()) == 0
+    assert np.all(x >= 0)
+    assert nnls.relative_residual_gap(ref.SA, ref.Sb, x, ref.x) <= GAP_TOL
+
+
 # ------------------------------------------------------------------ sketch
 def _sketch_case(n, d, r, seed, data_seed, mode="exact", lda_pad=0, with_b=True):
     g = np.random.default_rng(data_seed)
