@@ -213,6 +213,32 @@ def test_sketch_full_size_sampled_rows():
         assert np.max(np.abs(got - want) / scale) <= SKETCH_TOL
 
 
+def test_sketch_precision_workload_size_fp32_columns():
+    """2^22 x 128, r = 8192 with the FP32 transform (inputs above twice the
+    last-level cache: the nontemporal tile loads): rows in full, whole sketched
+    columns for a few columns of A and for b against the oracle's FP64
+    transform of those columns, and the solve's x~ against the oracle on the
+    device's own sketch."""
+    n, d, r, seed = 1 << 22, 128, 8192, 3
+    print("fp32 sketch full size 2^22 x 128", flush=True)
+    p = workloads.tfidf_like(n, d, seed=seed)
+    A, b = _dev(p)
+    sk = rnnls.srht_sketch(A, b, r, seed)
+    torch.cuda.synchronize()
+    cols = [0, 5, 64, 127]
+    M = np.column_stack([p.A[:, c] for c in cols] + [p.b]).astype(np.float64)
+    Y, _, R, _ = hadamard.srht_sketch(M, None, r, seed)
+    assert np.array_equal(sk.rows.cpu().numpy(), R)
+    SA = sk.SA.cpu().numpy()
+    got = np.column_stack([SA[:, c] for c in cols] + [sk.Sb.cpu().numpy()])
+    assert _colwise_rel(got, Y) <= SKETCH_TOL
+    sol = rnnls.nnls_solve(sk.SA, sk.Sb)
+    torch.cuda.synchronize()
+    SA64, Sb64 = SA.astype(np.float64), sk.Sb.cpu().numpy().astype(np.float64)
+    ref = nnls.lawson_hanson(SA64, Sb64)
+    assert nnls.relative_residual_gap(SA64, Sb64, sol.x.cpu().numpy(), ref.x) <= GAP_TOL
+
+
 # ------------------------------------------------------------------ solve
 def _solve_case(m, d, seed, planted_zeros=None):
     g = np.random.default_rng(seed)
