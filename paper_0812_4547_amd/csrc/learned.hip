@@ -25,6 +25,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "common.h"
 
 namespace rnnls {
@@ -464,8 +466,8 @@ __global__ void mlp_sync_kernel(const float* __restrict__ theta, uint16_t* __res
 size_t mlp_lds() { return sizeof(MlpShared); }
 
 int mlp_set_lds() {
-  static int done = 0;
-  if (done) return RNNLS_OK;
+  static std::atomic<int> done{0};  // setting the attribute twice is harmless
+  if (done.load()) return RNNLS_OK;
   const int bytes = (int)mlp_lds();
   if (hipFuncSetAttribute((const void*)mlp_kernel<true>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
@@ -473,7 +475,7 @@ int mlp_set_lds() {
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sizeof(InferShared)) != hipSuccess)
     return RNNLS_E_HIP;
-  done = 1;
+  done.store(1);
   return RNNLS_OK;
 }
 

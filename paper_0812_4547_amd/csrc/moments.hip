@@ -208,8 +208,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const M
   const double* src = kind != 3 ? J.part + e : J.part_abs + (e - nblk);
   const int64_t stride = kind != 3 ? nblk : J.d;
   double s = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < J.chunks; ++c) s += src[(int64_t)c * stride];
+  // chunks in order; four loads in flight at a time (same order of additions)
+  int c = 0;
+  for (; c + 4 <= J.chunks; c += 4) {
+    const double a0 = src[(int64_t)c * stride], a1 = src[(int64_t)(c + 1) * stride];
+    const double a2 = src[(int64_t)(c + 2) * stride], a3 = src[(int64_t)(c + 3) * stride];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; c < J.chunks; ++c) s += src[(int64_t)c * stride];
   switch (kind) {
     case 0:
       J.G[(int64_t)i * J.d + j] = s;

@@ -396,8 +396,18 @@ __device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t 
   // the block's threads stride over the kept rows of the column
   for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < count; l += gridDim.x * blockDim.x) {
     const float* p = base + l;
+    // pieces in order; four loads in flight at a time (same order of additions)
     float s = 0.0f;
-    for (int64_t k = 0; k < npieces; ++k) s += p[k * J.r_cap];
+    int64_t k = 0;
+    for (; k + 4 <= npieces; k += 4) {
+      const float a0 = p[k * J.r_cap], a1 = p[(k + 1) * J.r_cap];
+      const float a2 = p[(k + 2) * J.r_cap], a3 = p[(k + 3) * J.r_cap];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; k < npieces; ++k) s += p[k * J.r_cap];
     if (J.rag) s += p[(int64_t)(J.pieces - 1) * J.r_cap];
     store_out(J, col, l, (float)((double)s * J.inv_sqrt_r));
   }
