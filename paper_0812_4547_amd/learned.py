@@ -102,15 +102,20 @@ class Evaluation:
 
 
 def _timed_pass(batch, reps: int):
+    """(ms per pass timed without per-kernel events, Lawson-Hanson ms per pass
+    from a second run of the same passes with the solve's events on)."""
     stream = torch.cuda.current_stream()
-    rnnls.timing_enable(True)
-    rnnls.timing_read(rnnls.TIMER_SOLVE)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
         batch.run()
     e1.record(stream)
+    torch.cuda.synchronize()
+    rnnls.timing_enable(True)
+    rnnls.timing_read(rnnls.TIMER_SOLVE)
+    for _ in range(reps):
+        batch.run()
     torch.cuda.synchronize()
     lh_ms, _ = rnnls.timing_read(rnnls.TIMER_SOLVE)
     rnnls.timing_enable(False)
