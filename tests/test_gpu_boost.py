@@ -75,3 +75,27 @@ def test_boost_single_repetition_equals_rand_nnls():
     torch.cuda.synchronize()
     assert int(out.best.item()) == 0
     assert torch.equal(out.x, one.x)
+
+
+def test_boost_bernoulli_sampling():
+    """Repetition with the paper's Bernoulli row sampling: each candidate is the
+    Bernoulli-mode Algorithm 1 run of its seed."""
+    print("boost bernoulli", flush=True)
+    p = workloads.tfidf_like(40000, 30, seed=17)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    opts = rnnls.make_opts("bernoulli")
+    k, r, seed = 3, 900, 31
+    out = rnnls.rand_nnls_boost(A, b, r, k, seed, opts=opts)
+    torch.cuda.synchronize()
+    runs = [rnnls.rand_nnls(A, b, r, seed + i, opts=opts) for i in range(k)]
+    xs = [run.x.cpu().numpy() for run in runs]
+    st = np.array([int(run.status.item()) for run in runs])
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    res = np.array([np.linalg.norm(A64 @ x - b64) for x in xs])
+    np.testing.assert_allclose(out.resid.cpu().numpy()[:k], res, rtol=1e-10, atol=0)
+    best = int(out.best.item())
+    assert best == _expected_best(res, st)
+    assert np.array_equal(out.x.cpu().numpy(), xs[best])
+    ob = orand.rand_nnls_boost(p.A, p.b, r, k, seed, mode="bernoulli")
+    np.testing.assert_allclose(res, ob.residuals, rtol=1e-6, atol=0)

@@ -43,3 +43,21 @@ def test_nmf_tracks_exact_alternating_nnls():
     assert got <= hist[-1] * 1.05
     assert got < hist[0]
     assert np.all(W >= 0) and np.all(H >= 0)
+
+
+def test_nmf_chunks_more_right_hand_sides_than_one_call_takes():
+    # the W half-step has m = 4096 + 300 right-hand sides: two chunks of the
+    # multi-RHS call sharing one sketch of H^T
+    print("nmf chunked W half-step", flush=True)
+    m, n, q, iters = 4096 + 300, 64, 4, 2
+    p = workloads.tfidf_like(m, n, seed=13)
+    A_h = p.A
+    W0 = np.random.default_rng(14).random((m, q)).astype(np.float32)
+    res = nmf.nmf_als(rnnls.colmajor(A_h), q, iters, r_h=1024, r_w=48, seed=9,
+                      W0=torch.from_numpy(W0))
+    W, H = res.W.cpu().numpy().astype(np.float64), res.H.cpu().numpy().astype(np.float64)
+    assert W.shape == (m, q) and H.shape == (q, n)
+    got = onmf.objective(A_h, W, H)
+    _, _, hist = onmf.anls(A_h, W0, iters)
+    assert got <= hist[-1] * 1.05
+    assert np.all(W >= 0) and np.all(H >= 0)
