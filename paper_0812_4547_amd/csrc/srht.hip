@@ -240,8 +240,16 @@ __device__ __forceinline__ int load_rows(const SketchJob& J, uint32_t (&zidx)[SP
   return count;
 }
 
+// 2^14-row tiles run two workgroups per CU, four wavefronts per SIMD: ask
+// the compiler for that occupancy (at most 128 VGPRs) where the kept rows per
+// thread allow it.
+template <int LOG_T, int SPT, int MODE>
+constexpr int tiled_min_waves() { return (LOG_T == 14 && SPT <= 8 && MODE != 2) ? 4 : 1; }
+
 template <int LOG_T, int SPT, int MODE, bool BATCH, bool RAG, int AUX = kNonTemporal>
-__global__ __launch_bounds__((1 << LOG_T) / kRegs) void srht_tiled_kernel(TiledLaunch L) {
+__global__ __launch_bounds__((1 << LOG_T) / kRegs)
+__attribute__((amdgpu_waves_per_eu(tiled_min_waves<LOG_T, SPT, MODE>())))
+void srht_tiled_kernel(TiledLaunch L) {
   constexpr int T = 1 << LOG_T;
   constexpr int NT = T / kRegs;
   constexpr int LDS_WORDS = T + (T >> 5);
