@@ -606,8 +606,8 @@ def main():
                          "reference kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 (sharding "
+                                   "across GPUs is not implemented)"}))
         sys.exit(2)
 
     import numpy as np
