@@ -112,12 +112,35 @@ __global__ __launch_bounds__(64) void boost_select_kernel(int k, int d, int grid
                                                           int32_t* __restrict__ status, int K) {
   __shared__ double res[RNNLS_MAX_BOOST];
   const int lane = threadIdx.x;
-  for (int i = 0; i < k; ++i) {
-    double v = 0.0;
-    for (int w = lane; w < grid; w += 64) v += partials[(int64_t)w * K + i];
+  // all slots of a workgroup at once (independent loads), workgroups in order
+  double v[RNNLS_MAX_BOOST];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) res[i] = sqrt(v);
+  for (int i = 0; i < RNNLS_MAX_BOOST; ++i) v[i] = 0.0;
+  int w = lane;
+  for (; w + 3 * 64 < grid; w += 4 * 64) {  // four workgroups' loads in flight
+    double q[4][RNNLS_MAX_BOOST];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < RNNLS_MAX_BOOST; ++i)
+        q[u][i] = i < K ? partials[(int64_t)(w + 64 * u) * K + i] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < RNNLS_MAX_BOOST; ++i) v[i] += q[u][i];
+  }
+  for (; w < grid; w += 64) {
+    const double* p = partials + (int64_t)w * K;
+#pragma unroll
+    for (int i = 0; i < RNNLS_MAX_BOOST; ++i)
+      if (i < K) v[i] += p[i];
+  }
+#pragma unroll
+  for (int i = 0; i < RNNLS_MAX_BOOST; ++i) {
+    double t = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0 && i < k) res[i] = sqrt(t);
   }
   __syncthreads();
   int pick = 0;
