@@ -11,6 +11,10 @@ of seeds seed, seed+1, ..., seed+k-1, keeping the x~ whose full residual
 at least 1/2, so the kept one does with probability at least 1 - 2^-k.
 Readings: candidates whose solve did not finish with status 0 are passed over
 unless none did; ties go to the lowest index.
+
+Box constraints on the same sketch (the conclusions' remark that other
+constraint sets can use it): steps 1-4 unchanged, step 5 replaced by the
+bounded-variable solve of min_{lo <= x <= hi} ||H~ D A x - H~ D b||^2.
 """
 from __future__ import annotations
 
@@ -18,7 +22,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import hadamard, nnls
+from . import bvls, hadamard, nnls
 
 
 @dataclass
@@ -59,3 +63,20 @@ def rand_nnls_boost(A: np.ndarray, b: np.ndarray, r: int, k: int, seed: int,
     pool = np.flatnonzero(ok) if ok.any() else np.arange(k)
     best = int(pool[np.argmin(res[pool])])   # argmin takes the lowest index on ties
     return BoostResult(x=runs[best].x, best=best, residuals=res, statuses=st, candidates=runs)
+
+
+@dataclass
+class RandBoxResult:
+    x: np.ndarray            # x~ in the box (FP64)
+    SA: np.ndarray
+    Sb: np.ndarray
+    rows: np.ndarray
+    solve: bvls.BoxResult
+
+
+def rand_box(A: np.ndarray, b: np.ndarray, r: int, seed: int, lo: np.ndarray,
+             hi: np.ndarray, mode: str = "exact", tol: float | None = None,
+             max_iter: int | None = None) -> RandBoxResult:
+    SA, Sb, R, _ = hadamard.srht_sketch(A, b, r, seed, mode)
+    res = bvls.bvls(SA, Sb, lo, hi, tol=tol, max_iter=max_iter)
+    return RandBoxResult(x=res.x, SA=SA, Sb=Sb, rows=R, solve=res)
