@@ -43,7 +43,8 @@ WORKLOADS = {
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
 BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64",
-                   "boost_2p20x64_k4", "nmf_2p16x2048_q32", "density_sweep_1e4x128")
+                   "boost_2p20x64_k4", "nmf_2p16x2048_q32", "density_sweep_1e4x128",
+                   "box_2p20x64")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
 CPU_SAMPLES = {"single_2p20x64": 6, "single_4096x16": 1500, "single_2p22x128": 1}
@@ -495,6 +496,70 @@ def bench_boost(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_box(args):
+    """Box constraints on the same sketch: one step = Algorithm 1 on tf-idf-like
+    A 2^20 x 64 (r = 4096) with 0 <= x <= 0.5 in step 5 (rnnls_rand_box)."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+    n, d, r, ds, ub = 1 << 20, 64, 4096, 2, 0.5
+    p = workloads.tfidf_like(n, d, seed=ds)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    lo = torch.zeros(d, dtype=torch.float64, device="cuda")
+    hi = torch.full((d,), ub, dtype=torch.float64, device="cuda")
+    ws = rnnls.workspace(rnnls.OP_RAND_NNLS, n, d, r)
+    out = rnnls.Solution(torch.empty(d, dtype=torch.float64, device="cuda"), None,
+                         torch.empty(1, dtype=torch.float64, device="cuda"),
+                         torch.empty(1, dtype=torch.int32, device="cuda"),
+                         torch.empty(1, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        rnnls.rand_box(A, b, r, 100 + i, lo, hi, ws=ws, out=out)
+    torch.cuda.synchronize()
+    it = iter(range(10**9))
+    ms = _timed(lambda: rnnls.rand_box(A, b, r, 1000 + next(it), lo, hi, ws=ws, out=out),
+                args.steps, stream)
+    rnnls.timing_enable(True)
+    for t in (rnnls.TIMER_SKETCH, rnnls.TIMER_MOMENTS, rnnls.TIMER_SOLVE):
+        rnnls.timing_read(t)
+    it = iter(range(10**9))
+    _timed(lambda: rnnls.rand_box(A, b, r, 1000 + next(it), lo, hi, ws=ws, out=out),
+           args.steps, stream)
+    sk_ms, sk_n = rnnls.timing_read(rnnls.TIMER_SKETCH)
+    mo_ms, mo_n = rnnls.timing_read(rnnls.TIMER_MOMENTS)
+    so_ms, so_n = rnnls.timing_read(rnnls.TIMER_SOLVE)
+    rnnls.timing_enable(False)
+    sk_avg = sk_ms / max(sk_n, 1)
+    alg = 4 * n * (d + 1) + 4 * r * (d + 1)
+    achieved = alg / (sk_avg * 1e-3) / 1e9
+    rnnls.rand_box(A, b, r, 7, lo, hi, ws=ws, out=out)
+    torch.cuda.synchronize()
+    x = out.x.cpu().numpy()
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    plain = rnnls.rand_nnls(A, b, r, 7)
+    torch.cuda.synchronize()
+    rec = _base_record(args, 1000.0 / ms, ms, {
+        "workload": f"Algorithm 1 with box bounds 0 <= x <= {ub} in step 5 on tf-idf-like A "
+                    f"{n}x{d} FP32, r = {r}", "n": n, "d": d, "r": r, "data_seed": ds})
+    rec["unit"] = "box solves/s"
+    rec["roofline"] = _with_read_peak({
+        "kernel": "srht_tiled_kernel", "bound": "hbm", "achieved": achieved,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sk_avg, "launches": sk_n})
+    rec["breakdown_ms"] = {"sketch": sk_avg, "moments": mo_ms / max(mo_n, 1),
+                           "box_solve": so_ms / max(so_n, 1)}
+    rec["quality"] = {
+        "status": int(out.status.item()), "outer_steps": int(out.iters.item()),
+        "at_lower": int(np.sum(x == 0.0)), "at_upper": int(np.sum(x == ub)),
+        "free": int(np.sum((x > 0.0) & (x < ub))),
+        "full_residual_over_norm_b": float(np.linalg.norm(A64 @ x - b64) / np.linalg.norm(b64)),
+        "unbounded_algorithm1_residual_over_norm_b":
+            float(np.linalg.norm(A64 @ plain.x.cpu().numpy() - b64) / np.linalg.norm(b64))}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_nmf(args):
     """Nonnegative factorisation by alternating NNLS, each half-step Algorithm 1
     for many right-hand sides: tf-idf-like A 2^16 x 2048, rank 32.  One step =
@@ -637,6 +702,8 @@ def main():
         return bench_boost(args)
     if args.workload == "nmf_2p16x2048_q32":
         return bench_nmf(args)
+    if args.workload == "box_2p20x64":
+        return bench_box(args)
     if args.workload == "density_sweep_1e4x128":
         return bench_density(args)
 

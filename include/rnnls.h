@@ -68,6 +68,7 @@ extern "C" {
 #define RNNLS_SOLVE_KKT_FAIL 2      /* finished but the KKT check failed      */
 #define RNNLS_SOLVE_NO_ROWS 3       /* Bernoulli sample kept no row           */
 #define RNNLS_SOLVE_OVERFLOW 4      /* Bernoulli sample exceeded r_cap rows   */
+#define RNNLS_SOLVE_BAD_BOUNDS 5    /* box bounds: some lo not finite or hi < lo */
 
 /* ---- options ----------------------------------------------------------- */
 #define RNNLS_SAMPLE_EXACT 0        /* exactly r distinct rows (default)      */
@@ -186,6 +187,39 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
                     float* SA, int64_t ldsa, float* Sb, int32_t* rows,
                     int32_t* r_out, const rnnls_opts* opts,
                     void* ws, size_t ws_bytes, void* stream);
+
+/* ---- box constraints on the same sketch ---------------------------------
+ * rnnls_rand_box -- the conclusions remark that the sketch of Algorithm 1 does
+ * not depend on the constraint set.  Steps 1-4 as rnnls_rand_nnls, then step 5
+ * with box bounds: x~ = argmin_{lo <= x <= hi} ||H~ D A x - H~ D b||_2^2
+ * (lo = 0, hi = +inf is Algorithm 1 itself).  The small problem is solved by a
+ * bounded-variable active-set method (Stark and Parker's BVLS: Lawson-Hanson's
+ * outer and inner loops with two bounds) in FP64 Gram form, one wavefront,
+ * the free system factored by Cholesky at every step.  Every variable starts
+ * at its lower bound; the entering variable is the bound one whose dual most
+ * violates its condition (lowest index on ties); tau, the dependence test and
+ * the default cap of 3d outer steps are those of rnnls_nnls_solve.
+ *
+ *  n, d, r, seed, A, lda, b   as rnnls_rand_nnls, but 1 <= d <= RNNLS_MAX_BOX_D
+ *  lo, hi      input device double[d]: bounds; every lo finite, hi >= lo, hi may
+ *              be +inf (else status RNNLS_SOLVE_BAD_BOUNDS and x = 0)
+ *  x           output double[d] in the box
+ *  rnorm       output double[1]: ||H~ D (A x - b)||_2; may be NULL
+ *  iters       output int32[1]: outer steps; may be NULL
+ *  status      output int32[1]: RNNLS_SOLVE_OK, _MAX_ITER, _KKT_FAIL (optimality
+ *              conditions w_j <= tau at a lower bound, -w_j <= tau at an upper
+ *              one, |w_j| <= 1e3 tau when free, with w = G (x) dual), _NO_ROWS,
+ *              _OVERFLOW or _BAD_BOUNDS; may be NULL
+ * Workspace: rnnls_workspace_bytes(RNNLS_OP_RAND_NNLS, n, d, r, opts).  Returns
+ * as rnnls_rand_nnls; -8 lo NULL, -9 hi NULL, -10 x NULL (argument positions).
+ * The solve is timed as RNNLS_TIMER_SOLVE.
+ */
+#define RNNLS_MAX_BOX_D 64
+
+int rnnls_rand_box(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A,
+                   int64_t lda, const float* b, const double* lo, const double* hi,
+                   double* x, double* rnorm, int32_t* iters, int32_t* status,
+                   const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- repetition ---------------------------------------------------------
  * rnnls_rand_nnls_boost -- Theorem 1's guarantee holds with probability at
@@ -389,7 +423,7 @@ int rnnls_get_tuning(rnnls_tuning* tuning);
  * a timer's begin/end pairs must not interleave across host threads. */
 #define RNNLS_TIMER_SKETCH 0   /* the sketch transform kernel (steps 1-4)      */
 #define RNNLS_TIMER_MOMENTS 1  /* Gram-form moments of the small problem       */
-#define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel                         */
+#define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel (or the box solver)     */
 #define RNNLS_TIMER_STREAM_READ 3  /* the streaming-read reference kernel      */
 #define RNNLS_TIMER_RESIDUAL 4 /* full residuals of the repetition candidates  */
 #define RNNLS_TIMER_COUNT 5

@@ -397,6 +397,65 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
       lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm, iters, status), 1, s);
 }
 
+int rnnls_rand_box(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A,
+                   int64_t lda, const float* b, const double* lo, const double* hi,
+                   double* x, double* rnorm, int32_t* iters, int32_t* status,
+                   const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  const Opts o = read_opts(opts);
+  Sizes z;
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 14, &z);
+  if (rc) return rc;
+  if (d > RNNLS_MAX_BOX_D) return -2;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!b) return -7;
+  if (!lo) return -8;
+  if (!hi) return -9;
+  if (!x) return -10;
+  const int cus = device_cus();
+  if (cus < 0) return cus;
+  z.sp = plan_for(n, d + 1, z.r_cap, cus, o);
+  z.mp = moments_plan(z.r_cap, d, 1, cus);
+  const Layout L = layout_sketch(z, o, true, true);
+  if (!ws_ok(ws, ws_bytes, L.total)) return RNNLS_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float* sa = at<float>(ws, L.sa);
+  float* sb = at<float>(ws, L.sb);
+  int32_t* cnt = at<int32_t>(ws, L.count);
+  int32_t* st = at<int32_t>(ws, L.status);
+  rc = sketch_core(z, o, seed, A, lda, b, sa, z.r_cap, sb, at<int32_t>(ws, L.rows), cnt,
+                   at<uint32_t>(ws, L.signs), nullptr, st, at<uint32_t>(ws, L.bern),
+                   at<float>(ws, L.partials), s);
+  if (rc) return rc;
+  double* G = at<double>(ws, L.G);
+  double* q = at<double>(ws, L.q);
+  double* cc = at<double>(ws, L.cc);
+  double* colabs = at<double>(ws, L.colabs);
+  rc = launch_moments(
+      z.mp, moment_job(z.mp, sa, z.r_cap, sb, z.r_cap, cnt, at<double>(ws, L.mom), G, q, d, cc,
+                       colabs),
+      s);
+  if (rc) return rc;
+  BoxJob bj{};
+  bj.d = d;
+  bj.max_iter = o.max_iter > 0 ? o.max_iter : 3 * d;
+  bj.m = z.r_cap;
+  bj.tol = o.tol;
+  bj.G = G;
+  bj.q = q;
+  bj.c = cc;
+  bj.colabs = colabs;
+  bj.lo = lo;
+  bj.hi = hi;
+  bj.m_dev = cnt;
+  bj.pre_status = st;
+  bj.x = x;
+  bj.rnorm = rnorm;
+  bj.iters = iters;
+  bj.status = status;
+  return launch_bvls(bj, s);
+}
+
 }  // extern "C"
 
 namespace {

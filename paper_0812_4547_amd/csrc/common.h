@@ -181,6 +181,25 @@ struct LhJob {
   int32_t* warm_used;  // nullable, stride 1: 1 if the warm start was kept
 };
 
+// One box-constrained solve in Gram form (bvls.hip).
+struct BoxJob {
+  int32_t d, max_iter;
+  int64_t m;
+  double tol;
+  const double* G;
+  const double* q;
+  const double* c;
+  const double* colabs;
+  const double* lo;
+  const double* hi;
+  const int32_t* m_dev;       // nullable
+  const int32_t* pre_status;  // nullable: a non-OK value overrides the status
+  double* x;
+  double* rnorm;    // nullable
+  int32_t* iters;   // nullable
+  int32_t* status;  // nullable
+};
+
 // ---------------------------------------------------------------- launchers
 // Each returns RNNLS_OK, RNNLS_E_HIP or RNNLS_E_UNSUPPORTED.  A batch launcher
 // takes the host copy (for sizes) and the device table of the same jobs.
@@ -248,6 +267,7 @@ double* moments_abs_scratch(const MomentsPlan& p, double* scratch);
 
 size_t lh_lds_bytes(int d);
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);
+int launch_bvls(const BoxJob& j, hipStream_t s);
 // every job of a batch has d <= max_d, one problem each
 int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s);
 

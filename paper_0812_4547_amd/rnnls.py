@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librnnls.so
 OK = 0
 E_HIP, E_WORKSPACE, E_UNSUPPORTED = -100, -101, -102
 SOLVE_OK, SOLVE_MAX_ITER, SOLVE_KKT_FAIL, SOLVE_NO_ROWS, SOLVE_OVERFLOW = 0, 1, 2, 3, 4
+SOLVE_BAD_BOUNDS = 5
 SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
-MAX_D, MAX_R, MAX_K, MAX_BOOST = 128, 32768, 4096, 8
+MAX_D, MAX_R, MAX_K, MAX_BOOST, MAX_BOX_D = 128, 32768, 4096, 8, 64
 
 EXPORTS = (
     "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
@@ -34,7 +35,7 @@ EXPORTS = (
     "rnnls_batch_columns", "rnnls_batch_features", "rnnls_batch_set_model",
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
-    "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost",
+    "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost", "rnnls_rand_box",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
@@ -76,6 +77,8 @@ _SIGS = {
                          ctypes.c_int),
     "rnnls_rand_nnls": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
                          _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_rand_box": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                        _sz, _p], ctypes.c_int),
     "rnnls_multi_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
     "rnnls_boost_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
     "rnnls_rand_nnls_boost": ([_i64, _i32, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p,
@@ -293,6 +296,33 @@ class MultiSolution:
     rnorm: torch.Tensor   # float64 (k,)
     iters: torch.Tensor   # int32 (k,)
     status: torch.Tensor  # int32 (k,)
+
+
+def rand_box(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, lo: torch.Tensor,
+             hi: torch.Tensor, opts: Opts | None = None, ws=None, out=None,
+             stream=None) -> Solution:
+    """Algorithm 1 with box bounds lo <= x <= hi in step 5 (rnnls_rand_box);
+    lo, hi are float64 device vectors of length d."""
+    opts = opts or Opts()
+    n, d = A.shape
+    lda = _check_colmajor(A, "A")
+    dev = A.device
+    for name, v in (("lo", lo), ("hi", hi)):
+        if v.dtype != torch.float64 or v.numel() != d or not v.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 vector of length d")
+    if out is None:
+        out = Solution(torch.empty(d, dtype=torch.float64, device=dev), None,
+                       torch.empty(1, dtype=torch.float64, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev))
+    if ws is None:
+        ws = workspace(OP_RAND_NNLS, n, d, r, opts, dev)
+    rc = load().rnnls_rand_box(n, d, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(b), _ptr(lo),
+                               _ptr(hi), _ptr(out.x), _ptr(out.rnorm), _ptr(out.iters),
+                               _ptr(out.status), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                               _stream(stream))
+    _check(rc, "rnnls_rand_box")
+    return out
 
 
 def boost_workspace(n: int, d: int, r: int, k: int, opts: Opts | None = None, device="cuda"):

@@ -120,3 +120,21 @@ def test_rand_nnls_boost_argument_checks(lib):
     assert run(lda=10) == -7
     assert run(b=None) == -8
     assert run(x=None) == -9
+
+
+def test_rand_box_argument_checks(lib):
+    o = rnnls.Opts()
+
+    def run(n=4096, d=4, r=100, A=1, lda=4096, b=1, lo=1, hi=1, x=1):
+        return lib.rnnls_rand_box(n, d, r, 3, A, lda, b, lo, hi, x, None, None, None,
+                                  ctypes.byref(o), None, 0, None)
+    assert run(n=1) == -1
+    assert run(d=0) == -2
+    assert run(d=rnnls.MAX_BOX_D + 1) == -2
+    assert run(r=4096) == -3
+    assert run(A=None) == -5
+    assert run(lda=10) == -6
+    assert run(b=None) == -7
+    assert run(lo=None) == -8
+    assert run(hi=None) == -9
+    assert run(x=None) == -10

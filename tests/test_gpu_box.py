@@ -1,0 +1,122 @@
+"""Box-constrained least squares on the sketch (rnnls_rand_box) against the
+oracle's bounded-variable solve of the oracle's own sketch, and against the
+device's Algorithm 1 on the nonnegative orthant."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import rand_nnls as orand
+from paper_0812_4547_amd import rnnls, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+
+
+def _bounds(d, seed, lo_neg=False, inf_frac=0.0, fixed=()):
+    rng = np.random.default_rng(seed)
+    lo = rng.uniform(-0.3, 0.0, d) if lo_neg else np.zeros(d)
+    hi = lo + rng.uniform(0.2, 0.8, d)
+    hi[rng.random(d) < inf_frac] = np.inf
+    for j in fixed:
+        hi[j] = lo[j]
+    return lo, hi
+
+
+def _check_against_oracle(p, r, seed, lo, hi, gap_bar=1e-6):
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    out = rnnls.rand_box(A, b, r, seed, _dev(lo), _dev(hi))
+    torch.cuda.synchronize()
+    x = out.x.cpu().numpy()
+    ob = orand.rand_box(p.A, p.b, r, seed, lo, hi)
+    assert ob.solve.status == 0
+    assert int(out.status.item()) == rnnls.SOLVE_OK
+    # in the box, exactly on the bounds it reached
+    assert np.all(x >= lo) and np.all(x <= hi)
+    # the sketched objective of the device's x on the oracle's sketch
+    f_dev = np.linalg.norm(ob.SA @ x - ob.Sb)
+    f_orc = np.linalg.norm(ob.SA @ ob.x - ob.Sb)
+    assert f_dev <= f_orc * (1 + gap_bar) + 1e-12
+    assert abs(float(out.rnorm.item()) - f_orc) <= 1e-5 * max(f_orc, 1e-12)
+    return x, ob
+
+
+@pytest.mark.parametrize("n,d,r,seed,lo_neg,inf_frac", [
+    (3 * 16384 + 1234, 24, 600, 7, False, 0.0),   # ragged n, box [0, u]
+    (1 << 15, 40, 1200, 11, True, 0.3),           # negative lower bounds, some hi = +inf
+    ((1 << 14) + 3, 1, 300, 5, False, 0.0),       # d = 1
+    (20000, 64, 900, 21, True, 0.0),              # the largest d of the box solver
+])
+def test_rand_box_against_oracle(n, d, r, seed, lo_neg, inf_frac):
+    print(f"box n={n} d={d} r={r} seed={seed}", flush=True)
+    p = workloads.tfidf_like(n, d, seed=seed + 50)
+    lo, hi = _bounds(d, seed, lo_neg, inf_frac)
+    _check_against_oracle(p, r, seed, lo, hi)
+
+
+def test_rand_box_fixed_variables():
+    print("box fixed variables", flush=True)
+    p = workloads.tfidf_like(30000, 16, seed=3)
+    lo, hi = _bounds(16, 3, lo_neg=True, fixed=(2, 9))
+    x, _ = _check_against_oracle(p, 800, 4, lo, hi)
+    assert x[2] == lo[2] and x[9] == lo[9]
+
+
+def test_rand_box_full_size():
+    """The single-instance workload's size: 2^20 x 64, r = 4096, box [0, 0.5]."""
+    print("box full size", flush=True)
+    p = workloads.tfidf_like(1 << 20, 64, seed=2)
+    lo, hi = np.zeros(64), np.full(64, 0.5)
+    x, ob = _check_against_oracle(p, 4096, 2, lo, hi)
+    # some coefficients end on each bound
+    assert np.any(x == 0.0) and np.any(x == 0.5)
+
+
+def test_rand_box_orthant_is_rand_nnls():
+    """lo = 0, hi = +inf: the box solver and Lawson-Hanson solve the same
+    sketched problem."""
+    print("box orthant", flush=True)
+    p = workloads.tfidf_like(1 << 16, 32, seed=9)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    lo, hi = np.zeros(32), np.full(32, np.inf)
+    box = rnnls.rand_box(A, b, 1500, 123, _dev(lo), _dev(hi))
+    one = rnnls.rand_nnls(A, b, 1500, 123)
+    torch.cuda.synchronize()
+    assert int(box.status.item()) == 0 and int(one.status.item()) == 0
+    np.testing.assert_allclose(box.x.cpu().numpy(), one.x.cpu().numpy(), atol=1e-8)
+    np.testing.assert_allclose(box.rnorm.item(), one.rnorm.item(), rtol=1e-9)
+
+
+def test_rand_box_bad_bounds():
+    print("box bad bounds", flush=True)
+    p = workloads.tfidf_like(20000, 8, seed=1)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    lo = np.zeros(8)
+    hi = np.ones(8)
+    hi[3] = -1.0
+    out = rnnls.rand_box(A, b, 500, 1, _dev(lo), _dev(hi))
+    torch.cuda.synchronize()
+    assert int(out.status.item()) == rnnls.SOLVE_BAD_BOUNDS
+    assert torch.all(out.x == 0)
+
+
+def test_rand_box_bernoulli_sampling():
+    print("box bernoulli", flush=True)
+    p = workloads.tfidf_like(40000, 20, seed=17)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    lo, hi = _bounds(20, 17)
+    opts = rnnls.make_opts("bernoulli")
+    out = rnnls.rand_box(A, b, 900, 31, _dev(lo), _dev(hi), opts=opts)
+    torch.cuda.synchronize()
+    ob = orand.rand_box(p.A, p.b, 900, 31, lo, hi, mode="bernoulli")
+    x = out.x.cpu().numpy()
+    f_dev = np.linalg.norm(ob.SA @ x - ob.Sb)
+    f_orc = np.linalg.norm(ob.SA @ ob.x - ob.Sb)
+    assert int(out.status.item()) == 0
+    assert f_dev <= f_orc * (1 + 1e-6)
