@@ -19,10 +19,16 @@
 //           bound, -w_j <= tau at an upper one, |w_j| <= 1e3 tau when free.
 // tau = 10 eps ||A~||_1 max(m, d) as for Lawson-Hanson.
 //
-// One wavefront per problem, variable j on lane j (d <= 64).  The free system is
-// factored by Cholesky in LDS each time (row i of the factor on lane i, one
-// barrier per elimination step; the workgroup is one wavefront, so a barrier
-// only orders LDS traffic), then forward and back substitution.
+// One wavefront per problem, variable j on lane j (d <= 64).  The free systems go
+// through the symmetric sweep tableau of G in LDS (as in the Lawson-Hanson
+// kernel): a variable that becomes free is one sweep, one that returns to a
+// bound one reverse sweep, and with F swept the block T_FF holds -G_FF^-1, so
+// z_F = -T_FF c_F with c = q - G_{:,B} x_B; the pivot T_tt before t's sweep is
+// its Schur complement with respect to F (the dependence test).  Lane i owns
+// row i of T; the pivot row is copied aside first, so a sweep is d fused
+// multiply-adds per lane between two barriers (the workgroup is one wavefront,
+// so a barrier only orders LDS traffic).  w, c and the closing certificate are
+// computed from G itself.
 #include <float.h>
 #include <math.h>
 
@@ -38,99 +44,121 @@ constexpr int kHigh = 1;
 constexpr int kFree = 2;
 constexpr double kDependence = 1e-14;
 
-// argmax over the wavefront, lowest lane on ties
-__device__ __forceinline__ int wave_argmax(double v, double& best) {
-  int idx = threadIdx.x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, kBoxW);
-    const int oi = __shfl_xor(idx, off, kBoxW);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
-  }
-  best = v;
-  return idx;
+// ---- wave reductions: DPP row shifts 1, 2, 4, 8 (a scan inside each row of 16
+// lanes), then row broadcasts 15 and 31; the result gathers in lane 63 and is
+// read back with readlane, so it is uniform.  (Lane shuffles would go through
+// LDS permutes, a round trip per step.)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp(double old, double v) {
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ double readlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+#define RNNLS_BOX_DPP(STEP) \
+  STEP(0x111, 0xF) STEP(0x112, 0xF) STEP(0x114, 0xF) STEP(0x118, 0xF) STEP(0x142, 0xA) STEP(0x143, 0xC)
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kBoxW));
-  return v;
+template <bool MAX>
+__device__ __forceinline__ double wave_extreme(double v) {
+  const double ident = MAX ? -DBL_MAX : DBL_MAX;
+#define RNNLS_BOX_EXT(C, R)                \
+  {                                        \
+    const double o = dpp<C, R>(ident, v);  \
+    v = MAX ? fmax(v, o) : fmin(v, o);     \
+  }
+  RNNLS_BOX_DPP(RNNLS_BOX_EXT)
+#undef RNNLS_BOX_EXT
+  return readlane(v, kBoxW - 1);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kBoxW);
-  return v;
+#define RNNLS_BOX_SUM(C, R) v += dpp<C, R>(0.0, v);
+  RNNLS_BOX_DPP(RNNLS_BOX_SUM)
+#undef RNNLS_BOX_SUM
+  return readlane(v, kBoxW - 1);
 }
+#undef RNNLS_BOX_DPP
 
 struct BoxLds {
-  double L[kBoxW][kBoxW + 1];  // Cholesky factor of G_FF, row i = free slot i
-  double y[kBoxW];             // right-hand side, then the solution, by slot
+  double T[kBoxW][kBoxW + 1];  // G swept on the free set; row i on lane i
+  double rk[kBoxW];            // pivot row before a sweep
   double xs[kBoxW];            // x by variable (broadcast)
-  double zv[kBoxW];            // free solution by variable
-  int fidx[kBoxW];             // variable of each free slot
-  int bound[kBoxW];            // 1 if the variable is held at a bound in this solve
+  double xb[kBoxW];            // x of the variables held at a bound, 0 for free ones
+  double cf[kBoxW];            // c of the free variables, 0 for bound ones
+  double gdiag[kBoxW];         // diagonal of G
 };
 
-// Solves G_FF z = q_F - G_FB x_B for the m slots in S.fidx (x of the bound
-// variables in S.xs, S.bound marking them).  Returns false if a pivot is not
-// above kDependence times its diagonal of G (the last slot's pivot is its Schur
-// complement with respect to the others).  On return S.zv[fidx[i]] = z_i.
-__device__ bool free_solve(BoxLds& S, const double* __restrict__ G, const double* __restrict__ q,
-                           int d, int m) {
+// Symmetric sweep of T on k (rev = false) or its reverse (rev = true):
+// h = T_kk; T_ij -= T_ik T_kj / h (i, j != k); T_ik = T_ki = +-T_ik / h; T_kk = -1/h.
+// Rows and columns from d up to the next multiple of 8 are zero and stay so,
+// which lets every row loop run in unguarded steps of 8 (independent LDS reads).
+__device__ __forceinline__ void sweep(BoxLds& S, int d, int k, bool rev) {
+  const int lane = threadIdx.x;
+  const int dp = (d + 7) & ~7;
+  __syncthreads();
+  S.rk[lane] = S.T[k][lane];
+  __syncthreads();
+  const double h = S.rk[k];
+  const double inv_h = 1.0 / h;
+  if (lane == k) {
+    const double sg = rev ? -inv_h : inv_h;
+    for (int j0 = 0; j0 < dp; j0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S.T[k][j0 + u] = S.rk[j0 + u] * sg;
+    }
+    S.T[k][k] = -inv_h;
+  } else if (lane < d) {
+    const double ah = S.rk[lane] * inv_h;  // T_ik = T_ki by symmetry
+    for (int j0 = 0; j0 < dp; j0 += 8) {
+      double r[8], t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        r[u] = S.rk[j0 + u];
+        t[u] = S.T[lane][j0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S.T[lane][j0 + u] = fma(-ah, r[u], t[u]);
+    }
+    S.T[lane][k] = rev ? -ah : ah;
+  }
+  __syncthreads();
+}
+
+// z of the free variables (free: this lane's variable is free) from the swept
+// tableau: c = q - G_{:,B} x_B, z_F = -T_FF c_F.  g holds this lane's column
+// of G.  Returns z on free lanes.
+__device__ __forceinline__ double free_solution(BoxLds& S, const double (&g)[kBoxW], double qj,
+                                                int d, bool valid, bool free, double x) {
   const int lane = threadIdx.x;
   __syncthreads();
-  if (lane < m) {
-    const int fi = S.fidx[lane];
-    for (int j = 0; j <= lane; ++j) S.L[lane][j] = G[(int64_t)S.fidx[j] * d + fi];
-    double rhs = q[fi];
-    for (int k = 0; k < d; ++k)
-      if (S.bound[k]) rhs -= G[(int64_t)k * d + fi] * S.xs[k];
-    S.y[lane] = rhs;
-  }
-  bool ok = true;
-  for (int k = 0; k < m; ++k) {
-    __syncthreads();
-    const double piv = S.L[k][k];
-    const double gkk = G[(int64_t)S.fidx[k] * d + S.fidx[k]];
-    if (!(piv > kDependence * gkk)) {
-      ok = false;
-      break;
-    }
-    const double lkk = sqrt(piv);
-    __syncthreads();
-    if (lane == k) S.L[k][k] = lkk;
-    if (lane > k && lane < m) S.L[lane][k] /= lkk;
-    __syncthreads();
-    if (lane > k && lane < m) {
-      const double lik = S.L[lane][k];
-      for (int j = k + 1; j <= lane; ++j) S.L[lane][j] -= lik * S.L[j][k];
+  S.xb[lane] = (valid && !free) ? x : 0.0;
+  __syncthreads();
+  double c = qj;
+#pragma unroll
+  for (int k = 0; k < kBoxW; ++k) c = fma(-g[k], S.xb[k], c);  // g[k] = 0 for k >= d
+  S.cf[lane] = free ? c : 0.0;
+  __syncthreads();
+  double z = 0.0;
+  if (free) {
+    const int dp = (d + 7) & ~7;
+    for (int j0 = 0; j0 < dp; j0 += 8) {
+      double t[8], cj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        t[u] = S.T[lane][j0 + u];
+        cj[u] = S.cf[j0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) z = fma(-t[u], cj[u], z);
     }
   }
-  if (!ok) return false;
-  // L u = rhs
-  for (int k = 0; k < m; ++k) {
-    __syncthreads();
-    const double uk = S.y[k] / S.L[k][k];
-    __syncthreads();
-    if (lane == k) S.y[k] = uk;
-    if (lane > k && lane < m) S.y[lane] -= S.L[lane][k] * uk;
-  }
-  // L^T z = u
-  for (int k = m - 1; k >= 0; --k) {
-    __syncthreads();
-    const double zk = S.y[k] / S.L[k][k];
-    __syncthreads();
-    if (lane == k) S.y[k] = zk;
-    if (lane < k) S.y[lane] -= S.L[k][lane] * zk;
-  }
-  __syncthreads();
-  if (lane < m) S.zv[S.fidx[lane]] = S.y[lane];
-  __syncthreads();
-  return true;
+  return z;
 }
 
 __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
@@ -144,8 +172,7 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
   const double hi = valid ? J.hi[lane] : 0.0;
   const double qj = valid ? q[lane] : 0.0;
 
-  double amax = valid ? J.colabs[lane] : 0.0;
-  amax = -wave_min(-amax);
+  const double amax = wave_extreme<true>(valid ? J.colabs[lane] : 0.0);
   const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
   const double tau =
       J.tol > 0.0 ? J.tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d);
@@ -161,6 +188,14 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
     return;
   }
 
+  // column `lane` of G in registers (G is symmetric: row k, element lane), and
+  // T = G (nothing swept)
+  double g[kBoxW];
+#pragma unroll
+  for (int k = 0; k < kBoxW; ++k) g[k] = (valid && k < d) ? G[(int64_t)k * d + lane] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kBoxW; ++k) S.T[k][lane] = g[k];  // zero outside d x d
+  S.gdiag[lane] = valid ? G[(int64_t)lane * d + lane] : 0.0;
   double x = lo;
   int st = kLow;
   bool refused = false;
@@ -172,37 +207,34 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
     S.xs[lane] = valid ? x : 0.0;
     __syncthreads();
     w = qj;
-    if (valid)
-      for (int k = 0; k < d; ++k) w -= G[(int64_t)k * d + lane] * S.xs[k];
+#pragma unroll
+    for (int k = 0; k < kBoxW; ++k) w = fma(-g[k], S.xs[k], w);
     double score = -INFINITY;
     if (valid && !refused) {
       if (st == kLow && hi > lo) score = w;
       else if (st == kHigh) score = -w;
     }
-    double best;
-    const int t = wave_argmax(score, best);
+    const double best = wave_extreme<true>(score);
     if (!(best > tau)) break;
+    const int t = (int)__builtin_ctzll(__ballot(score == best));  // lowest index on ties
     if (iters >= J.max_iter) {
       status = RNNLS_SOLVE_MAX_ITER;
       break;
     }
     ++iters;
-    const int from = __shfl(st, t, kBoxW);
-    const double xt = __shfl(x, t, kBoxW);
-    // trial free set: the free variables in ascending order, then t
-    const bool isf = valid && st == kFree;
-    const uint64_t fmask = __ballot(isf);
-    const int m0 = __popcll(fmask);
-    if (isf) S.fidx[__popcll(fmask & ((1ull << lane) - 1ull))] = lane;
-    if (lane == 0) S.fidx[m0] = t;
-    S.bound[lane] = (valid && !isf && lane != t) ? 1 : 0;
-    if (!free_solve(S, G, q, d, m0 + 1)) {
+    const int from = __builtin_amdgcn_readlane(st, t);
+    const double xt = readlane(x, t);
+    // t's Schur complement with respect to the free set
+    if (!(S.T[t][t] > kDependence * S.gdiag[t])) {
       if (lane == t) refused = true;
       continue;
     }
-    const double zt = S.zv[t];
+    sweep(S, d, t, false);
+    double z = free_solution(S, g, qj, d, valid, valid && (st == kFree || lane == t), x);
+    const double zt = readlane(z, t);
     const bool moves_in = (from == kLow) ? (zt > xt) : (zt < xt);
     if (!moves_in) {
+      sweep(S, d, t, true);
       if (lane == t) refused = true;
       continue;
     }
@@ -210,7 +242,6 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
     if (lane == t) st = kFree;
     for (int inner = 0; inner <= d; ++inner) {
       const bool fr = valid && st == kFree;
-      const double z = fr ? S.zv[lane] : 0.0;
       const bool below = fr && z <= lo + tau;
       const bool above = fr && z >= hi - tau;
       if (!__any(below || above)) {
@@ -220,13 +251,12 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
       double a = INFINITY;
       if (below && x > z) a = (x - lo) / (x - z);
       else if (above && z > x) a = (hi - x) / (z - x);
-      const double amin = wave_min(a);
+      const double amin = wave_extreme<false>(a);
       double alpha = 1.0;
       int arg = -1;
       if (amin < 1.0) {
         alpha = amin;
-        double dummy;
-        arg = wave_argmax(a == amin ? 1.0 : 0.0, dummy);
+        arg = (int)__builtin_ctzll(__ballot(a == amin));
       }
       alpha = fmin(fmax(alpha, 0.0), 1.0);
       if (fr) {
@@ -241,20 +271,16 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
           st = kHigh;
         }
       }
-      const bool still = valid && st == kFree;
-      const uint64_t mask = __ballot(still);
-      const int m = __popcll(mask);
-      if (m == 0) break;
-      __syncthreads();
-      if (still) S.fidx[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
-      S.bound[lane] = (valid && !still) ? 1 : 0;
-      S.xs[lane] = valid ? x : 0.0;
-      if (!free_solve(S, G, q, d, m)) {  // a subset of an independent set: rounding only
-        status = RNNLS_SOLVE_KKT_FAIL;
-        break;
+      // the variables that reached a bound leave the tableau, lowest first
+      uint64_t leave = __ballot(fr && st != kFree);
+      while (leave) {
+        sweep(S, d, (int)__builtin_ctzll(leave), true);
+        leave &= leave - 1ull;
       }
+      const bool still = valid && st == kFree;
+      if (!__any(still)) break;
+      z = free_solution(S, g, qj, d, valid, still, x);
     }
-    if (status != RNNLS_SOLVE_OK) break;
   }
 
   // certificate from w = q - G x
@@ -262,8 +288,8 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
   S.xs[lane] = valid ? x : 0.0;
   __syncthreads();
   w = qj;
-  if (valid)
-    for (int k = 0; k < d; ++k) w -= G[(int64_t)k * d + lane] * S.xs[k];
+#pragma unroll
+  for (int k = 0; k < kBoxW; ++k) w = fma(-g[k], S.xs[k], w);
   bool ok = true;
   if (valid) {
     if (x < lo - tau || x > hi + tau) {
