@@ -20,7 +20,11 @@ hadamard     Walsh-Hadamard matrix in Sylvester (natural) order, its fast
              transform, and the sketch [H~ D A | H~ D b] of Algorithm 1.
 nnls         Lawson-Hanson active-set NNLS (Definition 1), KKT certificate,
              brute force over supports, unconstrained least squares.
-rand_nnls    Algorithm 1 end to end.
+rand_nnls    Algorithm 1 end to end; its repetition over seeds; the box-bounded
+             form of step 5.
+bvls         least squares with box bounds lo <= x <= hi (bounded-variable
+             active set), brute force over bound/free assignments.
+nmf          alternating NNLS for a nonnegative factorisation.
 diagnostics  realised subspace-embedding distortion (Lemma 1) and the
              row-norm flattening of Lemma 2, plus the proof chain of Theorem 1.
 learned      per-column features, the passive-set perceptron (forward, loss,

@@ -111,3 +111,39 @@ def test_dropped_interpolation_step_is_caught(monkeypatch):
                                iters=1, status=0, passive=np.nonzero(x)[0])
     monkeypatch.setattr(nnls, "lawson_hanson", bad_lh)
     assert not _lh_matches_brute_force()
+
+
+def _bvls_matches_brute_force():
+    from oracle import bvls
+    g = np.random.default_rng(12)
+    for _ in range(6):
+        A = g.standard_normal((20, 4))
+        b = 2.0 * g.standard_normal(20)
+        lo = g.uniform(-1.0, 0.2, 4)
+        hi = lo + g.uniform(0.1, 1.0, 4)
+        res = bvls.bvls(A, b, lo, hi)
+        _, fb = bvls.brute_force(A, b, lo, hi)
+        f = float(np.sum((A @ res.x - b) ** 2))
+        if f > fb * (1 + 1e-9) + 1e-12:
+            return False
+    return True
+
+
+def test_box_pin_passes_on_the_real_oracle():
+    assert _bvls_matches_brute_force()
+
+
+def test_free_solve_without_bound_terms_is_caught(monkeypatch):
+    """The free least-squares problem forgets that the bound variables sit at
+    nonzero values (right-hand side b instead of b - A_B x_B)."""
+    from oracle import bvls
+
+    def plain_free(A, b, x, F):
+        return np.linalg.lstsq(A[:, F], b, rcond=None)[0]
+
+    def free_solve(A, b, x, F):
+        return plain_free(A, b, x, F), True
+
+    monkeypatch.setattr(bvls, "_plain_free", plain_free)
+    monkeypatch.setattr(bvls, "_free_solve", free_solve)
+    assert not _bvls_matches_brute_force()
