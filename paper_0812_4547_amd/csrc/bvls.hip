@@ -85,6 +85,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 #undef RNNLS_BOX_DPP
 
+// sum_k g[k] v[k] over the register column g (zero past d) and an LDS vector,
+// in four interleaved partial sums (short dependency chains)
+__device__ __forceinline__ double col_dot(const double (&g)[kBoxW], const double* v) {
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kBoxW; ++k) p[k & 3] = fma(g[k], v[k], p[k & 3]);
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
 struct BoxLds {
   double T[kBoxW][kBoxW + 1];  // G swept on the free set; row i on lane i
   double rk[kBoxW];            // pivot row before a sweep
@@ -106,15 +115,12 @@ __device__ __forceinline__ void sweep(BoxLds& S, int d, int k, bool rev) {
   __syncthreads();
   const double h = S.rk[k];
   const double inv_h = 1.0 / h;
-  if (lane == k) {
-    const double sg = rev ? -inv_h : inv_h;
-    for (int j0 = 0; j0 < dp; j0 += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) S.T[k][j0 + u] = S.rk[j0 + u] * sg;
-    }
-    S.T[k][k] = -inv_h;
-  } else if (lane < d) {
+  if (lane < d) {
+    // one loop for every row: row k becomes +-rk / h, the others T_ij - T_ik rk_j / h
+    const bool piv = lane == k;
     const double ah = S.rk[lane] * inv_h;  // T_ik = T_ki by symmetry
+    const double keep = piv ? 0.0 : 1.0;
+    const double coef = piv ? (rev ? -inv_h : inv_h) : -ah;
     for (int j0 = 0; j0 < dp; j0 += 8) {
       double r[8], t[8];
 #pragma unroll
@@ -123,9 +129,9 @@ __device__ __forceinline__ void sweep(BoxLds& S, int d, int k, bool rev) {
         t[u] = S.T[lane][j0 + u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) S.T[lane][j0 + u] = fma(-ah, r[u], t[u]);
+      for (int u = 0; u < 8; ++u) S.T[lane][j0 + u] = fma(coef, r[u], keep * t[u]);
     }
-    S.T[lane][k] = rev ? -ah : ah;
+    S.T[lane][k] = piv ? -inv_h : (rev ? -ah : ah);
   }
   __syncthreads();
 }
@@ -139,12 +145,10 @@ __device__ __forceinline__ double free_solution(BoxLds& S, const double (&g)[kBo
   __syncthreads();
   S.xb[lane] = (valid && !free) ? x : 0.0;
   __syncthreads();
-  double c = qj;
-#pragma unroll
-  for (int k = 0; k < kBoxW; ++k) c = fma(-g[k], S.xb[k], c);  // g[k] = 0 for k >= d
+  const double c = qj - col_dot(g, S.xb);
   S.cf[lane] = free ? c : 0.0;
   __syncthreads();
-  double z = 0.0;
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
   if (free) {
     const int dp = (d + 7) & ~7;
     for (int j0 = 0; j0 < dp; j0 += 8) {
@@ -155,10 +159,10 @@ __device__ __forceinline__ double free_solution(BoxLds& S, const double (&g)[kBo
         cj[u] = S.cf[j0 + u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) z = fma(-t[u], cj[u], z);
+      for (int u = 0; u < 8; ++u) p[u & 3] = fma(t[u], cj[u], p[u & 3]);
     }
   }
-  return z;
+  return -((p[0] + p[1]) + (p[2] + p[3]));
 }
 
 __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
@@ -206,9 +210,7 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
     __syncthreads();
     S.xs[lane] = valid ? x : 0.0;
     __syncthreads();
-    w = qj;
-#pragma unroll
-    for (int k = 0; k < kBoxW; ++k) w = fma(-g[k], S.xs[k], w);
+    w = qj - col_dot(g, S.xs);
     double score = -INFINITY;
     if (valid && !refused) {
       if (st == kLow && hi > lo) score = w;
@@ -287,9 +289,7 @@ __global__ __launch_bounds__(kBoxW) void bvls_kernel(BoxJob J) {
   __syncthreads();
   S.xs[lane] = valid ? x : 0.0;
   __syncthreads();
-  w = qj;
-#pragma unroll
-  for (int k = 0; k < kBoxW; ++k) w = fma(-g[k], S.xs[k], w);
+  w = qj - col_dot(g, S.xs);
   bool ok = true;
   if (valid) {
     if (x < lo - tau || x > hi + tau) {
