@@ -105,11 +105,11 @@ struct BoxLds {
 
 // Symmetric sweep of T on k (rev = false) or its reverse (rev = true):
 // h = T_kk; T_ij -= T_ik T_kj / h (i, j != k); T_ik = T_ki = +-T_ik / h; T_kk = -1/h.
-// Rows and columns from d up to the next multiple of 8 are zero and stay so,
-// which lets every row loop run in unguarded steps of 8 (independent LDS reads).
+// Rows and columns from d up to the next multiple of 16 are zero and stay so,
+// which lets every row loop run in unguarded steps of 16 (independent LDS reads).
 __device__ __forceinline__ void sweep(BoxLds& S, int d, int k, bool rev) {
   const int lane = threadIdx.x;
-  const int dp = (d + 7) & ~7;
+  const int dp = (d + 15) & ~15;
   __syncthreads();
   S.rk[lane] = S.T[k][lane];
   __syncthreads();
@@ -121,15 +121,15 @@ __device__ __forceinline__ void sweep(BoxLds& S, int d, int k, bool rev) {
     const double ah = S.rk[lane] * inv_h;  // T_ik = T_ki by symmetry
     const double keep = piv ? 0.0 : 1.0;
     const double coef = piv ? (rev ? -inv_h : inv_h) : -ah;
-    for (int j0 = 0; j0 < dp; j0 += 8) {
-      double r[8], t[8];
+    for (int j0 = 0; j0 < dp; j0 += 16) {
+      double r[16], t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         r[u] = S.rk[j0 + u];
         t[u] = S.T[lane][j0 + u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) S.T[lane][j0 + u] = fma(coef, r[u], keep * t[u]);
+      for (int u = 0; u < 16; ++u) S.T[lane][j0 + u] = fma(coef, r[u], keep * t[u]);
     }
     S.T[lane][k] = piv ? -inv_h : (rev ? -ah : ah);
   }
@@ -150,16 +150,16 @@ __device__ __forceinline__ double free_solution(BoxLds& S, const double (&g)[kBo
   __syncthreads();
   double p[4] = {0.0, 0.0, 0.0, 0.0};
   if (free) {
-    const int dp = (d + 7) & ~7;
-    for (int j0 = 0; j0 < dp; j0 += 8) {
-      double t[8], cj[8];
+    const int dp = (d + 15) & ~15;
+    for (int j0 = 0; j0 < dp; j0 += 16) {
+      double t[16], cj[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         t[u] = S.T[lane][j0 + u];
         cj[u] = S.cf[j0 + u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) p[u & 3] = fma(t[u], cj[u], p[u & 3]);
+      for (int u = 0; u < 16; ++u) p[u & 3] = fma(t[u], cj[u], p[u & 3]);
     }
   }
   return -((p[0] + p[1]) + (p[2] + p[3]));
