@@ -195,7 +195,9 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
  * (lo = 0, hi = +inf is Algorithm 1 itself).  The small problem is solved by a
  * bounded-variable active-set method (Stark and Parker's BVLS: Lawson-Hanson's
  * outer and inner loops with two bounds) in FP64 Gram form, one wavefront,
- * the free system factored by Cholesky at every step.  Every variable starts
+ * the free systems through a symmetric sweep tableau of G (one sweep when a
+ * variable leaves its bound, one reverse sweep when it returns to one); the
+ * closing certificate is computed from G itself.  Every variable starts
  * at its lower bound; the entering variable is the bound one whose dual most
  * violates its condition (lowest index on ties); tau, the dependence test and
  * the default cap of 3d outer steps are those of rnnls_nnls_solve.
@@ -208,8 +210,10 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
  *  iters       output int32[1]: outer steps; may be NULL
  *  status      output int32[1]: RNNLS_SOLVE_OK, _MAX_ITER, _KKT_FAIL (optimality
  *              conditions w_j <= tau at a lower bound, -w_j <= tau at an upper
- *              one, |w_j| <= 1e3 tau when free, with w = G (x) dual), _NO_ROWS,
- *              _OVERFLOW or _BAD_BOUNDS; may be NULL
+ *              one, |w_j| <= 1e3 tau when free, with the dual w = q - G x of
+ *              G = (H~DA)^T H~DA, q = (H~DA)^T H~Db), _NO_ROWS, _OVERFLOW or
+ *              _BAD_BOUNDS; may be NULL
+ * All pointers are device memory owned by the caller; lo and hi are only read.
  * Workspace: rnnls_workspace_bytes(RNNLS_OP_RAND_NNLS, n, d, r, opts).  Returns
  * as rnnls_rand_nnls; -8 lo NULL, -9 hi NULL, -10 x NULL (argument positions).
  * The solve is timed as RNNLS_TIMER_SOLVE.
