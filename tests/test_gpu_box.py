@@ -120,3 +120,38 @@ def test_rand_box_bernoulli_sampling():
     f_orc = np.linalg.norm(ob.SA @ ob.x - ob.Sb)
     assert int(out.status.item()) == 0
     assert f_dev <= f_orc * (1 + 1e-6)
+
+
+def test_rand_box_outer_step_cap():
+    """max_iter = 2: the solve stops after two entries with status MAX_ITER and
+    an x that still lies in the box."""
+    print("box max_iter", flush=True)
+    p = workloads.tfidf_like(30000, 24, seed=8)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    lo, hi = _bounds(24, 8)
+    out = rnnls.rand_box(A, b, 700, 3, _dev(lo), _dev(hi), opts=rnnls.make_opts(max_iter=2))
+    torch.cuda.synchronize()
+    x = out.x.cpu().numpy()
+    assert int(out.status.item()) == rnnls.SOLVE_MAX_ITER
+    assert int(out.iters.item()) == 2
+    assert np.all(x >= lo) and np.all(x <= hi)
+
+
+def test_rand_box_wide_box_is_sketched_least_squares():
+    """Bounds far outside the unconstrained solution of the sketched problem:
+    every variable ends free and x~ is that least-squares solution (checked
+    against the oracle's sketch solved by LAPACK)."""
+    print("box wide", flush=True)
+    p = workloads.tfidf_like(1 << 15, 20, seed=13)
+    A = rnnls.colmajor(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    r, seed = 1000, 5
+    ob = orand.rand_box(p.A, p.b, r, seed, np.full(20, -1e3), np.full(20, 1e3))
+    x_ls = np.linalg.lstsq(ob.SA, ob.Sb, rcond=None)[0]
+    out = rnnls.rand_box(A, b, r, seed, _dev(np.full(20, -1e3)), _dev(np.full(20, 1e3)))
+    torch.cuda.synchronize()
+    x = out.x.cpu().numpy()
+    assert int(out.status.item()) == 0
+    assert np.all(np.abs(x) < 1e3)
+    np.testing.assert_allclose(x, x_ls, rtol=0, atol=1e-5 * np.abs(x_ls).max())
