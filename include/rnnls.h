@@ -405,8 +405,9 @@ int rnnls_batch_warm_used(rnnls_batch* plan, int32_t* out, void* stream);
 
 /* ---- launch tuning ------------------------------------------------------
  * Process-wide launch shape of the sketch kernel (all fields 0 = automatic:
- * 2^14-row tiles with two workgroups per CU when r_cap <= 4096, else 2^15-row
- * tiles with one; tiles are widened when r_cap needs more than 32 kept rows
+ * 2^13-row tiles with three workgroups per CU when r_cap <= 4096 and fewer than
+ * 16 tiles fall on each workgroup, 2^14-row tiles with two when more, else
+ * 2^15-row tiles with one; tiles are widened when r_cap needs more than 32 kept rows
  * per thread).
  *  srht_log_tile   log2 of the rows one workgroup transforms at a time:
  *                  12..15 (capped at log2 n'); workgroups have 2^(tile-5) threads

@@ -757,7 +757,7 @@ int srht_wgs_per_cu(int log_t) {
   switch (log_t) {
     case 15: return 1;
     case 14: return 2;
-    case 13: return 4;
+    case 13: return 3;  // three 256-thread workgroups: three wavefronts per SIMD
     default: return 8;
   }
 }
@@ -786,9 +786,11 @@ int get_tuning(rnnls_tuning* t) {
 int srht_pref_log_t(int m, int r_cap, int log_t_cap) {
   if (m <= 11) return 0;
   int cap = log_t_cap > 0 ? log_t_cap : g_log_tile.load();
-  // untuned: 2^14-row tiles (two workgroups per CU, whose barrier phases
-  // interleave) while 8 kept rows per thread hold r_cap, else 2^15
-  if (cap <= 0) cap = (r_cap <= 8 * ((1 << 14) / kRegs)) ? 14 : 15;
+  // untuned: 2^13-row tiles (three workgroups per CU, whose barrier phases
+  // interleave) while 16 kept rows per thread hold r_cap, else 2^15.  The
+  // 768 slots spread a few items per workgroup more evenly than 512 (at
+  // 2^20 x 65: 10.8 items each against 8.1, where every ninth item is a tail).
+  if (cap <= 0) cap = (r_cap <= 16 * ((1 << 13) / kRegs)) ? 13 : 15;
   int lt = cap;
   if (lt > m) lt = m;
   while (((1 << lt) / kRegs) * 32 < r_cap && lt < 15 && lt < m) ++lt;
@@ -851,6 +853,12 @@ SrhtPlan srht_plan(int64_t n, int ncols, int r_cap, int cus) {
   const int m = ilog2_exact((uint64_t)p.n_pad);
   p.log_t = srht_pref_log_t(m, r_cap, 0);
   if (p.log_t == 0) return p;  // direct kernel
+  // The untuned 2^13-row tiles pay off through balance when each workgroup
+  // gets few items; with 16 or more per workgroup the 2^14-row tiles (two
+  // workgroups per CU) are the more efficient per item.
+  if (g_log_tile.load() == 0 && g_wgs_per_cu.load() == 0 && p.log_t == 13 && m >= 14 &&
+      (int64_t)ncols * (n >> 13) >= 16ll * cus * srht_wgs_per_cu(13))
+    p.log_t = 14;
   p.spt = srht_spt(p.log_t, r_cap);
   p.tiles = n >> p.log_t;                       // full tiles per column
   p.rag = (n & ((1ll << p.log_t) - 1)) ? 1 : 0;  // one straddling tile

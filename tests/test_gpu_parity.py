@@ -149,7 +149,7 @@ def test_sketch_matches_oracle(n, d, r, seed):
 @pytest.mark.parametrize("log_tile,wgs", [(15, 1), (14, 2), (13, 4)])
 def test_sketch_with_tuned_tiles(log_tile, wgs):
     """Tuned tile sizes and workgroups per CU (the automatic choice here is
-    2^14 rows, two workgroups per CU): same outputs."""
+    2^13 rows, three workgroups per CU): same outputs."""
     rnnls.set_tuning(log_tile, wgs)
     try:
         _sketch_case((1 << 18) + 777, 64, 4096, 21, data_seed=5)
