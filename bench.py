@@ -1,18 +1,23 @@
 """Benchmark of the RandomizedNNLS hot path on one MI355X.
 
-One step = one pass of the whole path over one instance resident in HBM:
-random streams, sketch transform, reduce, FP64 moments, Lawson-Hanson and its
-KKT certificate (rnnls_rand_nnls).  Default workload: the single instance at
-scale, tf-idf-like A of 2^20 x 64 (1% mean density, Zipf(1.1) column
-densities, lognormal values, L2-normalised columns, stored dense FP32),
-b = A x* + 5% noise, r = 4096.
+Default workload (the metric's configuration): batched, warm-started solves.
+A passive-set perceptron is trained on the device from 100k problems of the
+batch generator solved cold by the method itself; 4096 held-out problems of
+the same generator (n log-uniform in [2^14, 2^18], d uniform in [8, 96],
+r = max(32 d, 1024), tf-idf-like entries), all resident in HBM, run as 16
+batch plans of 256 problems replayed as HIP graphs.  One step = one pass over
+all 4096 problems.  `value` = warm-started solves/s; beside it the plain
+cold-start rate of the same plans, the relative residual gap of every
+warm-started solution against the cold one on the same sketch (max, mean),
+the fallback rate and the outer iterations.  The `roofline` is the sketch
+kernel's over the pass, stated for the transform kernel alone and for the
+whole sketch (random streams + transform + reduce); `single_2p20x64` adds the
+single instance at scale (tf-idf-like 2^20 x 64, r = 4096) with warm- and
+cold-cache medians of the sketch over 50 repetitions.  `cpu_baseline` is the
+FP64 oracle on a bounded sample of the held-out problems, on all host cores.
 
-Prints one JSON line (metric, value = solves/s, roofline of the sketch kernel
-from HIP events recorded on its launch stream, and the CPU oracle timed on a
-bounded sample as a reported baseline).
-
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu-baseline]
-                    [--workload single_2p20x64|single_4096x16|single_2p22x128]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+                    [--workload warm_batch_4096|single_2p20x64|...]
     python bench.py --copy-mib 1024   # plain copies only, to scale byte counters
 """
 from __future__ import annotations
@@ -21,8 +26,11 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import shutil
 import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -151,6 +159,89 @@ def _run_cpu_sample(code, what):
                       f"{res['seconds']:.1f} s"}
 
 
+CPU_ORACLE_WORKER = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, {root!r})
+from oracle import rand_nnls
+secs = 0.0
+files = {files!r}
+for f in files:
+    z = np.load(f)
+    A, b, r, seed = z["A"], z["b"], int(z["r"]), int(z["seed"])
+    t0 = time.perf_counter()
+    rand_nnls.rand_nnls(A, b, r, seed)
+    secs += time.perf_counter() - t0
+print(json.dumps({{"seconds": secs, "instances": len(files)}}))
+"""
+
+
+def host_cpus() -> int:
+    """Host cores this process may use, at most 16 (a one-GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_all_cores(problems, what):
+    """The FP64 oracle (Algorithm 1 as written, oracle.rand_nnls) over
+    `problems` = [(A (n, d) float32, b, r, sketch seed)], one single-threaded
+    worker process per host core (longest problems first).  Rate = problems
+    over the slowest worker's compute time; the one-core rate = problems over
+    the summed compute time."""
+    import numpy as np
+    workers = min(host_cpus(), len(problems))
+    tmp = tempfile.mkdtemp(prefix="rnnls_oracle_")
+    try:
+        files = []
+        for i, (A, b, r, seed) in enumerate(problems):
+            f = os.path.join(tmp, f"p{i}.npz")
+            np.savez(f, A=A, b=b, r=np.int64(r), seed=np.int64(seed))
+            files.append(f)
+        order = sorted(range(len(problems)), key=lambda i: -problems[i][0].size)
+        buckets, loads = [[] for _ in range(workers)], [0] * workers
+        for i in order:
+            w = loads.index(min(loads))
+            buckets[w].append(files[i])
+            loads[w] += problems[i][0].size
+        env = dict(os.environ)
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[k] = "1"
+        procs = [subprocess.Popen([sys.executable, "-c",
+                                   CPU_ORACLE_WORKER.format(root=ROOT, files=bk)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                                  env=env) for bk in buckets]
+        res = []
+        for pr in procs:
+            out, err = pr.communicate(timeout=900)
+            if pr.returncode != 0:
+                raise RuntimeError("cpu baseline worker failed: " + err[-2000:])
+            res.append(json.loads(out.strip().splitlines()[-1]))
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    makespan = max(r["seconds"] for r in res)
+    total = sum(r["seconds"] for r in res)
+    return {"value": len(problems) / makespan, "unit": "solves/s", "cores": workers,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "single_core_value": len(problems) / total,
+            "sample": f"{what}: {len(problems)} solves (FP64 numpy oracle of Algorithm 1, "
+                      f"exact-r rows), {workers} single-threaded worker processes, "
+                      f"{total:.1f} s of CPU work, slowest worker {makespan:.1f} s"}
+
+
 def _timed(fn, steps, stream):
     import torch
     start = torch.cuda.Event(enable_timing=True)
@@ -195,6 +286,17 @@ def _with_read_peak(roof):
     roof["read_stream_peak"] = peak
     roof["frac_of_read_stream"] = roof["achieved"] / peak
     return roof
+
+
+ALL_TIMERS = (0, 1, 2, 5, 6)  # sketch, moments, solve, streams, reduce
+
+
+def _whole(alg, ms):
+    """Roofline of steps 1-4 as a whole: random streams + transform + reduce
+    (their summed kernel durations `ms` per unit of `alg` bytes)."""
+    ach = alg / (ms * 1e-3) / 1e9
+    return {"kernels": "streams + srht transform + srht reduce", "ms": ms, "achieved": ach,
+            "frac": ach / HBM_PEAK_GBS}
 
 
 def _base_record(args, value, ms, config, dtype="f32"):
@@ -650,65 +752,227 @@ def bench_density(args):
     print(json.dumps(rec), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="single_2p20x64",
-                    choices=sorted(WORKLOADS) + list(BATCH_WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=0,
-                    help="instances the oracle times (default: about 10-30 s of CPU work)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
-                    help="sketch transform: FP32 vector units, or BF16 matrix cores with "
-                         "split hi + lo operands and FP32 accumulation")
-    ap.add_argument("--train-instances", type=int, default=100_000)
-    ap.add_argument("--heldout", type=int, default=4096)
-    ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="only run 5 plain device copies of this many MiB (the "
-                         "reference kernel that scales the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 (sharding "
-                                   "across GPUs is not implemented)"}))
-        sys.exit(2)
+def bench_warm_batch(args):
+    """The metric's configuration: batched, warm-started solves/s against the
+    plain cold-start path on the same plans (see the module docstring)."""
+    import numpy as np
+    import torch
 
+    from paper_0812_4547_amd import learned, rnnls
+    stream = torch.cuda.current_stream()
+    # 1. training set: problems of the batch generator solved cold on the device
+    t0 = time.perf_counter()
+    Xs, ys, labels_ok = [], [], True
+    chunk = 1024
+    for c0 in range(0, args.train_instances, chunk):
+        X, y, o = learned.collect(min(chunk, args.train_instances - c0), seed=100 + c0 // chunk)
+        Xs.append(X)
+        ys.append(y)
+        labels_ok = labels_ok and o
+        if (c0 // chunk) % 20 == 0:
+            print(f"collected {min(c0 + chunk, args.train_instances)} / {args.train_instances} "
+                  f"training problems ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+                  flush=True)
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    del Xs, ys
+    collect_s = time.perf_counter() - t0
+    mlp = rnnls.Mlp(learned.init_params(1))
+    t1 = time.perf_counter()
+    hist = learned.train(mlp, X, y, epochs=args.epochs, batch_rows=8192, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    prob, _ = mlp.forward(X)
+    acc = float(((prob > 0.5).to(torch.uint8) == y).double().mean().item())
+    train_rows = int(X.shape[0])
+    del X, y, prob
+    print(f"trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, accuracy {acc:.4f} "
+          f"({train_s:.1f} s)", file=sys.stderr, flush=True)
+
+    # 2. held-out problems, all resident in HBM, as plans of `plan_size`
+    count, per, hseed = args.heldout, args.plan_size, 2_000_000
+    shp = learned.shapes(count, seed=hseed)
+    alg = sum(4 * n * (d + 1) + 4 * r * (d + 1) for n, d, r in shp)
+    plans, sample = [], []
+    for c0 in range(0, count, per):
+        probs = learned.device_problems(shp[c0:c0 + per], hseed * 1_000_003 + c0)
+        if c0 == 0 and not args.no_cpu_baseline:
+            for A, b, r, sd in probs[:args.cpu_samples or 64]:
+                sample.append((A.t().contiguous().cpu().numpy().T, b.cpu().numpy(), r, sd))
+        plans.append(rnnls.Batch(probs))
+        del probs
+    torch.cuda.synchronize()
+    tiles = [P.autotune() for P in plans]
+    print(f"{len(plans)} plans of {per} held-out problems resident "
+          f"({alg / 1e9:.1f} GB of [A | b]), autotuned", file=sys.stderr, flush=True)
+
+    def one_pass():
+        for P in plans:
+            P.launch()
+
+    def phase(model):
+        for P in plans:
+            P.set_model(model)
+            P.run()
+        torch.cuda.synchronize()
+        for P in plans:
+            P.capture()
+        for _ in range(args.warmup):
+            one_pass()
+        ms = _timed(one_pass, args.steps, stream)
+        res = {"ms": ms,
+               "rnorm": torch.cat([P.rnorm for P in plans]).clone(),
+               "iters": torch.cat([P.iters for P in plans]).clone(),
+               "status": torch.cat([P.status for P in plans]).clone(),
+               "warm_used": (torch.cat([P.warm_used() for P in plans])
+                             if model is not None else None)}
+        # per-kernel durations from eager passes with the library's events on
+        rnnls.timing_enable(True)
+        for t in ALL_TIMERS:
+            rnnls.timing_read(t)
+        reps = 3
+        for _ in range(reps):
+            for P in plans:
+                P.run()
+        torch.cuda.synchronize()
+        names = ("sketch", "moments", "lawson_hanson", "streams", "reduce")
+        res["kernels_ms"] = {nm: rnnls.timing_read(t)[0] / reps
+                             for nm, t in zip(names, ALL_TIMERS)}
+        rnnls.timing_enable(False)
+        return res
+
+    cold = [phase(None)]
+    warm = [phase(mlp)]
+    cold.append(phase(None))
+    warm.append(phase(mlp))
+    cold_ms = float(np.mean([c["ms"] for c in cold]))
+    warm_ms = float(np.mean([w["ms"] for w in warm]))
+    rn_c, rn_w = cold[-1]["rnorm"], warm[-1]["rnorm"]
+    gap = (rn_w / rn_c.clamp_min(1e-300) - 1.0).cpu().numpy()
+    st_c = cold[-1]["status"].cpu().numpy()
+    st_w = warm[-1]["status"].cpu().numpy()
+    used = warm[-1]["warm_used"].double().cpu().numpy()
+    kc, kw = cold[-1]["kernels_ms"], warm[-1]["kernels_ms"]
+    sk_ms = kw["sketch"]
+    achieved = alg / (sk_ms * 1e-3) / 1e9
+    rec = _base_record(args, count * 1000.0 / warm_ms, warm_ms, {
+        "workload": f"batched warm-started RandomizedNNLS: {count} held-out problems of the "
+                    "batch generator (n log-uniform in [2^14, 2^18], d uniform in [8, 96], "
+                    "r = max(32 d, 1024); tf-idf-like entries generated on the device) in "
+                    f"{len(plans)} batch plans of {per}, HIP graph replay, autotuned tiles; "
+                    "Lawson-Hanson warm-started from the learned passive-set proposal, "
+                    "KKT-judged with cold fallback",
+        "problems": count, "plan_size": per, "heldout_seed": hseed,
+        "algorithmic_bytes_per_pass": alg, "autotuned_tiles": sorted(set(tiles)),
+        "network": "8-128-128-1 perceptron, BF16 weights, FP32 accumulation",
+        "step": f"one pass over all {count} problems"})
+    rec["vs_cold"] = {
+        "warm_solves_per_s": count * 1000.0 / warm_ms,
+        "cold_solves_per_s": count * 1000.0 / cold_ms,
+        "speedup": cold_ms / warm_ms,
+        "ms_per_pass_cold": [c["ms"] for c in cold], "ms_per_pass_warm": [w["ms"] for w in warm],
+        "max_rel_residual_gap_vs_cold": float(gap.max()),
+        "max_abs_rel_residual_gap_vs_cold": float(np.abs(gap).max()),
+        "mean_rel_residual_gap_vs_cold": float(gap.mean()),
+        "gap_bar": 1e-2, "within_bar": bool(np.abs(gap).max() <= 1e-2),
+        "fallback_rate": float(1.0 - used.mean()),
+        "status_ok_cold": int((st_c == 0).sum()), "status_ok_warm": int((st_w == 0).sum()),
+        "outer_iterations_cold_mean": float(cold[-1]["iters"].double().mean().item()),
+        "outer_iterations_warm_mean": float(warm[-1]["iters"].double().mean().item()),
+        "kernels_ms_per_pass_cold": kc, "kernels_ms_per_pass_warm": kw,
+        "gap_definition": "||S(Ax_warm - b)|| / ||S(Ax_cold - b)|| - 1 on the same sketch"}
+    rec["roofline"] = _with_read_peak({
+        "kernel": "srht_tiled_kernel (every sketch launch of the pass)", "bound": "hbm",
+        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sk_ms,
+        "whole_sketch": _whole(alg, kw["streams"] + sk_ms + kw["reduce"])})
+    rec["training"] = {"problems": args.train_instances, "rows": train_rows,
+                       "epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1],
+                       "train_accuracy": acc, "collect_s": collect_s, "train_s": train_s,
+                       "labels_all_ok": labels_ok}
+    for P in plans:
+        P.close()
+    del plans
+    torch.cuda.empty_cache()
+    single = run_single(args, "single_2p20x64", with_extras=False)
+    rec["single_2p20x64"] = {k: single[k] for k in ("value", "ms_per_step", "config", "roofline",
+                                                    "breakdown_ms_per_step", "quality",
+                                                    "srht_medians")}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = oracle_all_cores(sample, "the first held-out problems")
+    print(json.dumps(rec), flush=True)
+
+
+def srht_medians(A, b, r, seed, n, d, reps=50, warmups=5):
+    """Steps 1-4 of Algorithm 1 (rnnls_srht_sketch: random streams, transform,
+    reduce) timed one call at a time, `reps` times after `warmups`, with the
+    last-level cache warm (calls back to back) and cold (a 1 GiB read between
+    calls; also a 1 GiB write, which leaves dirty lines).  Medians of the
+    transform kernel alone and of the three kernels
+    together (their event-timed durations), and of the call bracketed by two
+    events (launch gaps included); HBM fractions of the algorithmic bytes
+    4 n (d+1) + 4 r (d+1)."""
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls
+    stream = torch.cuda.current_stream()
+    ws = rnnls.workspace(rnnls.OP_SKETCH, n, d, r)
+    flush = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    parts = rnnls.stream_read(flush)
+    alg = 4 * n * (d + 1) + 4 * r * (d + 1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    timers = (rnnls.TIMER_STREAMS, rnnls.TIMER_SKETCH, rnnls.TIMER_REDUCE)
+    out = {}
+    for mode in ("warm", "cold", "cold_dirty"):
+        for i in range(warmups):
+            rnnls.srht_sketch(A, b, r, seed + i, ws=ws)
+        torch.cuda.synchronize()
+        rnnls.timing_enable(True)
+        for t in timers:
+            rnnls.timing_read(t)
+        tiled, whole, call = [], [], []
+        for i in range(reps):
+            if mode == "cold":        # evict [A | b] with clean lines
+                rnnls.stream_read(flush, parts)
+            elif mode == "cold_dirty":  # evict it with dirty lines
+                flush.fill_(float(i))
+            e0.record(stream)
+            rnnls.srht_sketch(A, b, r, seed + i, ws=ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st, sk, rd = (rnnls.timing_read(t)[0] for t in timers)
+            tiled.append(sk)
+            whole.append(st + sk + rd)
+            call.append(e0.elapsed_time(e1))
+        rnnls.timing_enable(False)
+        t_ms, w_ms, c_ms = (float(np.median(v)) for v in (tiled, whole, call))
+        out[mode] = {"transform_kernel_us": t_ms * 1e3,
+                     "transform_frac": alg / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "streams_transform_reduce_us": w_ms * 1e3,
+                     "streams_transform_reduce_frac": alg / (w_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "call_us": c_ms * 1e3,
+                     "call_frac": alg / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del flush
+    out["reps"] = reps
+    out["algorithmic_bytes"] = alg
+    out["cold"]["flush"] = ("1 GiB device read between calls (the last-level cache holds 256 MB), "
+                            "so no line of [A | b] stays cached")
+    out["cold_dirty"]["flush"] = ("1 GiB device write between calls: the cache then holds dirty "
+                                  "lines whose write-back lands inside the timed call")
+    return out
+
+
+def run_single(args, name, with_extras=True):
+    """One step = rnnls_rand_nnls on one instance resident in HBM."""
     import numpy as np
     import torch
 
     from paper_0812_4547_amd import rnnls, workloads
-
-    if args.copy_mib > 0:
-        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written":
-                          dst.numel() * 4, "launches": 5}), flush=True)
-        return
-
-    if args.workload == "batch_256":
-        return bench_batch(args)
-    if args.workload == "multi_2p20x64_k512":
-        return bench_multi(args)
-    if args.workload == "learned_4096":
-        return bench_learned(args)
-    if args.workload == "fig1_2p20x64":
-        return bench_fig1(args)
-    if args.workload == "boost_2p20x64_k4":
-        return bench_boost(args)
-    if args.workload == "nmf_2p16x2048_q32":
-        return bench_nmf(args)
-    if args.workload == "box_2p20x64":
-        return bench_box(args)
-    if args.workload == "density_sweep_1e4x128":
-        return bench_density(args)
-
-    n, d, r, ds, ss = WORKLOADS[args.workload]
-    planted = args.workload == "single_4096x16"
+    n, d, r, ds, ss = WORKLOADS[name]
+    planted = name == "single_4096x16"
     p = workloads.uniform_planted(n=n, d=d, seed=ds) if planted else workloads.tfidf_like(n, d, seed=ds)
     A = rnnls.colmajor(p.A)
     b = torch.from_numpy(p.b).cuda()
@@ -740,7 +1004,7 @@ def main():
     # the same steps again with every launch of the sketch, moments and solve
     # bracketed by HIP events on its stream: per-kernel durations
     rnnls.timing_enable(True)
-    for t in (rnnls.TIMER_SKETCH, rnnls.TIMER_MOMENTS, rnnls.TIMER_SOLVE):
+    for t in ALL_TIMERS:
         rnnls.timing_read(t)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -753,6 +1017,8 @@ def main():
     sk_ms, sk_n = rnnls.timing_read(rnnls.TIMER_SKETCH)
     mo_ms, mo_n = rnnls.timing_read(rnnls.TIMER_MOMENTS)
     lh_ms, lh_n = rnnls.timing_read(rnnls.TIMER_SOLVE)
+    st_ms, _ = rnnls.timing_read(rnnls.TIMER_STREAMS)
+    rd_ms, _ = rnnls.timing_read(rnnls.TIMER_REDUCE)
     rnnls.timing_enable(False)
     status = int(out.status.item())
 
@@ -760,7 +1026,7 @@ def main():
     sk_avg = sk_ms / max(sk_n, 1)
     alg_bytes = 4 * n * (d + 1) + 4 * r * (d + 1)
     achieved = alg_bytes / (sk_avg * 1e-3) / 1e9
-    traffic = load_traffic() if (args.precision == "fp32" and args.workload == "single_2p20x64") else None
+    traffic = load_traffic() if (args.precision == "fp32" and name == "single_2p20x64") else None
 
     # quality of x~ (untimed): the paper's residual loss against the exact NNLS
     # of the whole problem, both solved on the GPU (nnls_solve on all n rows is
@@ -808,12 +1074,16 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": sk_avg,
             "launches": sk_n,
+            "whole_sketch": _whole(alg_bytes, (st_ms + sk_ms + rd_ms) / args.steps),
         },
         "breakdown_ms_per_step": {
+            "streams": st_ms / args.steps,
             "sketch_kernel": sk_ms / args.steps,
+            "reduce": rd_ms / args.steps,
             "moments": mo_ms / args.steps,
             "lawson_hanson": lh_ms / args.steps,
-            "other": ms_timed_total / args.steps - (sk_ms + mo_ms + lh_ms) / args.steps,
+            "other": ms_timed_total / args.steps
+                     - (st_ms + sk_ms + rd_ms + mo_ms + lh_ms) / args.steps,
             "note": "from a second run of the same steps with per-kernel events "
                     f"({ms_timed_total / args.steps:.4f} ms per step there)",
         },
@@ -825,11 +1095,80 @@ def main():
             "plain_status": int(plain.status.item()),
         },
     }
-    _with_read_peak(rec["roofline"])
-    if not args.no_cpu_baseline:
-        ns = args.cpu_samples or CPU_SAMPLES[args.workload]
-        rec["cpu_baseline"] = cpu_baseline(n, d, r, ds, planted, ns)
-    print(json.dumps(rec), flush=True)
+    if args.precision == "fp32":
+        rec["srht_medians"] = srht_medians(A, b, r, ss, n, d)
+    if with_extras:
+        _with_read_peak(rec["roofline"])
+        if not args.no_cpu_baseline:
+            ns = args.cpu_samples or CPU_SAMPLES[name]
+            rec["cpu_baseline"] = cpu_baseline(n, d, r, ds, planted, ns)
+    return rec
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="warm_batch_4096",
+                    choices=["warm_batch_4096"] + sorted(WORKLOADS) + list(BATCH_WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=0,
+                    help="instances the oracle times (default: about 10-30 s of CPU work)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
+                    help="sketch transform: FP32 vector units, or BF16 matrix cores with "
+                         "split hi + lo operands and FP32 accumulation")
+    ap.add_argument("--train-instances", type=int, default=100_000)
+    ap.add_argument("--heldout", type=int, default=4096)
+    ap.add_argument("--plan-size", type=int, default=256,
+                    help="problems per batch plan of the default workload")
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 5 plain device copies of this many MiB (the "
+                         "reference kernel that scales the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 (sharding "
+                                   "across GPUs is not implemented)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0812_4547_amd import rnnls, workloads
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written":
+                          dst.numel() * 4, "launches": 5}), flush=True)
+        return
+
+    if args.workload == "batch_256":
+        return bench_batch(args)
+    if args.workload == "multi_2p20x64_k512":
+        return bench_multi(args)
+    if args.workload == "learned_4096":
+        return bench_learned(args)
+    if args.workload == "fig1_2p20x64":
+        return bench_fig1(args)
+    if args.workload == "boost_2p20x64_k4":
+        return bench_boost(args)
+    if args.workload == "nmf_2p16x2048_q32":
+        return bench_nmf(args)
+    if args.workload == "box_2p20x64":
+        return bench_box(args)
+    if args.workload == "density_sweep_1e4x128":
+        return bench_density(args)
+
+    if args.workload == "warm_batch_4096":
+        return bench_warm_batch(args)
+    print(json.dumps(run_single(args, args.workload)), flush=True)
 
 
 if __name__ == "__main__":

@@ -431,7 +431,11 @@ int rnnls_get_tuning(rnnls_tuning* tuning);
 #define RNNLS_TIMER_SOLVE 2    /* Lawson-Hanson kernel (or the box solver)     */
 #define RNNLS_TIMER_STREAM_READ 3  /* the streaming-read reference kernel      */
 #define RNNLS_TIMER_RESIDUAL 4 /* full residuals of the repetition candidates  */
-#define RNNLS_TIMER_COUNT 5
+#define RNNLS_TIMER_STREAMS 5  /* random streams: sign words and kept rows     */
+#define RNNLS_TIMER_REDUCE 6   /* fixed-order sum of the sketch partials and the
+                                  1/sqrt(r) scale (steps 1-4 are STREAMS +
+                                  SKETCH + REDUCE)                             */
+#define RNNLS_TIMER_COUNT 7
 
 int rnnls_timing_enable(int on);
 int rnnls_timing_read(int32_t which, double* total_ms, int64_t* launches);

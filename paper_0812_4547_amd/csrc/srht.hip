@@ -920,9 +920,11 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
+  timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
   hipLaunchKernelGGL(srht_reduce_kernel<false>, rgrid, dim3(threads), 0, s, j,
                      (const SketchJob*)nullptr, (const int32_t*)nullptr, main_items,
                      (int64_t)(p.grid > 0 ? p.grid : 1));
+  timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
@@ -957,8 +959,10 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
   }
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
+  timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
   hipLaunchKernelGGL(srht_reduce_kernel<true>, rgrid, dim3(threads), 0, s, none, dev,
                      col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1));
+  timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

@@ -358,14 +358,20 @@ int launch_streams(const StreamJob& j, hipStream_t s) {
         return RNNLS_E_HIP;
       lds_limit_set.store(1);
     }
+    void* tok = nullptr;
+    timer_begin(RNNLS_TIMER_STREAMS, s, &tok);
     hipLaunchKernelGGL(streams_exact_kernel, dim3(nb), dim3(kExactThreads), lds, s, j);
+    timer_end(RNNLS_TIMER_STREAMS, s, tok);
     return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
   }
   const unsigned nb = (unsigned)streams_blocks(j.m);
+  void* tok = nullptr;
+  timer_begin(RNNLS_TIMER_STREAMS, s, &tok);
   hipLaunchKernelGGL(streams_scan_rows_kernel<false>, dim3(nb), dim3(kScanThreads), 0, s, j,
                      (const StreamJob*)nullptr, (const int32_t*)nullptr);
   hipLaunchKernelGGL(streams_write_rows_kernel<false>, dim3(nb), dim3(kWriteThreads), 0, s, j,
                      (const StreamJob*)nullptr, (const int32_t*)nullptr);
+  timer_end(RNNLS_TIMER_STREAMS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
@@ -375,10 +381,13 @@ int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs,
   const StreamJob& last = host[njobs - 1];
   const unsigned nb = (unsigned)(last.blk0 + streams_blocks(last.m));
   StreamJob none{};
+  void* tok = nullptr;
+  timer_begin(RNNLS_TIMER_STREAMS, s, &tok);
   hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kScanThreads), 0, s, none,
                      dev, blk_job);
   hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kWriteThreads), 0, s, none,
                      dev, blk_job);
+  timer_end(RNNLS_TIMER_STREAMS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 

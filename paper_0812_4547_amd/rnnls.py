@@ -39,6 +39,7 @@ EXPORTS = (
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
+TIMER_STREAMS, TIMER_REDUCE = 5, 6
 
 
 class Opts(ctypes.Structure):
