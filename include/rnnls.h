@@ -96,7 +96,9 @@ typedef struct rnnls_opts {
   int32_t precision;   /* RNNLS_PREC_*                                        */
   int32_t max_iter;    /* Lawson-Hanson outer-iteration cap; <= 0: 3*d        */
   int32_t r_cap;       /* Bernoulli: rows the sketch buffers hold; <= 0: the
-                          default r + 8*ceil(sqrt(r)) + 64 (EXACT: ignored)   */
+                          default r + 8*ceil(sqrt(r)) + 64; either is clamped
+                          to n' (a sample keeps at most n' rows) (EXACT:
+                          ignored)                                            */
   double tol;          /* dual tolerance tau; <= 0: 10*eps*||M||_1*max(m,d),
                           ||M||_1 the largest column 1-norm (lsqnonneg's rule) */
 } rnnls_opts;          /* NULL opts = all defaults                            */
@@ -129,7 +131,7 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
  *  A, lda      input, column-major, lda >= n
  *  b           input right-hand side of length n, or NULL (then Sb is unused)
  *  SA, ldsa    output, column-major R x d with ldsa >= R_cap where R_cap = r
- *              (EXACT) or opts->r_cap (BERNOULLI); rows beyond the kept
+ *              (EXACT) or the clamped opts->r_cap (BERNOULLI); rows beyond the kept
  *              count are left untouched
  *  Sb          output of length R_cap (ignored when b is NULL)
  *  rows        output int32[R_cap]: kept rows of H_n', ascending; may be NULL

@@ -53,10 +53,13 @@ bool opts_valid(const Opts& o) {
 }
 
 // Rows the sketch buffers hold.
-int row_capacity(int r, const Opts& o) {
+// Rows the sketch buffers hold.  A Bernoulli sample never keeps more than
+// n' rows, so the capacity is clamped to n' (beyond it a tile could not hold
+// the kept rows of one column).
+int row_capacity(int r, const Opts& o, int64_t n_pad) {
   if (o.sample_mode == RNNLS_SAMPLE_EXACT) return r;
-  if (o.r_cap > 0) return o.r_cap;
-  return r + 8 * (int)ceil(sqrt((double)r)) + 64;
+  const int64_t want = o.r_cap > 0 ? o.r_cap : r + 8 * (int64_t)ceil(sqrt((double)r)) + 64;
+  return (int)(want < n_pad ? want : n_pad);
 }
 
 // Workspace layout; every region 256-byte aligned.
@@ -141,7 +144,7 @@ int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n
   const int64_t n_pad = (int64_t)next_pow2((uint64_t)n);
   if (r < 1 || (int64_t)r >= n_pad || r > RNNLS_MAX_R) return -pos_r;
   if (!opts_valid(o)) return -pos_opts;
-  const int r_cap = row_capacity(r, o);
+  const int r_cap = row_capacity(r, o, n_pad);
   if (r_cap < 1 || r_cap > RNNLS_MAX_R) return -pos_opts;
   z->n = n;
   z->n_pad = n_pad;

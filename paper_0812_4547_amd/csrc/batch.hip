@@ -39,10 +39,12 @@ struct Settings {
   double tol = 0.0;
 };
 
-int row_cap(int r, const Settings& o) {
+// Rows the sketch buffers of one problem hold (a Bernoulli sample keeps at
+// most n' rows, so the capacity is clamped to n').
+int row_cap(int r, const Settings& o, int64_t n_pad) {
   if (o.sample_mode == RNNLS_SAMPLE_EXACT) return r;
-  if (o.r_cap > 0) return o.r_cap;
-  return r + 8 * (int)ceil(sqrt((double)r)) + 64;
+  const int64_t want = o.r_cap > 0 ? o.r_cap : r + 8 * (int64_t)ceil(sqrt((double)r)) + 64;
+  return (int)(want < n_pad ? want : n_pad);
 }
 
 int check_problem(const rnnls_problem& p, const Settings& o) {
@@ -50,7 +52,7 @@ int check_problem(const rnnls_problem& p, const Settings& o) {
   if (p.d < 1 || p.d > RNNLS_MAX_D) return -1;
   const int64_t n_pad = (int64_t)next_pow2((uint64_t)p.n);
   if (p.r < 1 || (int64_t)p.r >= n_pad || p.r > RNNLS_MAX_R) return -1;
-  const int rc = row_cap(p.r, o);
+  const int rc = row_cap(p.r, o, n_pad);
   if (rc < 1 || rc > RNNLS_MAX_R) return -1;
   if (!p.A || p.lda < p.n || !p.b || !p.x) return -1;
   return 0;
@@ -143,7 +145,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
     m[i] = ilog2_exact(next_pow2((uint64_t)p.n));
-    rcap[i] = row_cap(p.r, o);
+    rcap[i] = row_cap(p.r, o, 1ll << m[i]);
     log_t[i] = srht_pref_log_t(m[i], rcap[i], c.log_t_cap);
   }
   const int group_keys[] = {15, 14, 13, 12, 0};

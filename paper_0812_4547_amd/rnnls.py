@@ -153,12 +153,13 @@ def make_opts(sample_mode: str = "exact", precision: str = "fp32", max_iter: int
                 int(max_iter), int(r_cap), float(tol))
 
 
-def row_capacity(r: int, opts: Opts) -> int:
+def row_capacity(r: int, opts: Opts, n: int) -> int:
+    """Rows the sketch buffers hold: r (exact), else opts.r_cap or
+    r + 8 ceil(sqrt r) + 64, clamped to n' (the library's rule)."""
     if opts.sample_mode == SAMPLE_EXACT:
         return r
-    if opts.r_cap > 0:
-        return opts.r_cap
-    return r + 8 * int(np.ceil(np.sqrt(r))) + 64
+    want = opts.r_cap if opts.r_cap > 0 else r + 8 * int(np.ceil(np.sqrt(r))) + 64
+    return min(want, 1 << max(0, (n - 1).bit_length()))
 
 
 def colmajor(M: np.ndarray, device="cuda") -> torch.Tensor:
@@ -210,7 +211,7 @@ def srht_sketch(A: torch.Tensor, b: torch.Tensor | None, r: int, seed: int,
     n, d = A.shape
     lda = _check_colmajor(A, "A")
     dev = A.device
-    rc_ = row_capacity(r, opts)
+    rc_ = row_capacity(r, opts, n)
     SA = torch.empty((d, rc_), dtype=torch.float32, device=dev).t()
     Sb = torch.empty(rc_, dtype=torch.float32, device=dev) if b is not None else None
     rows = torch.empty(rc_, dtype=torch.int32, device=dev)
@@ -272,7 +273,7 @@ def rand_nnls(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, opts: Opts | 
                        torch.empty(1, dtype=torch.int32, device=dev))
     sk = None
     if keep_sketch:
-        rc_ = row_capacity(r, opts)
+        rc_ = row_capacity(r, opts, n)
         sk = Sketch(torch.empty((d, rc_), dtype=torch.float32, device=dev).t(),
                     torch.empty(rc_, dtype=torch.float32, device=dev),
                     torch.empty(rc_, dtype=torch.int32, device=dev),
@@ -282,7 +283,7 @@ def rand_nnls(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, opts: Opts | 
     rc = load().rnnls_rand_nnls(
         n, d, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(b), _ptr(out.x), _ptr(out.rnorm),
         _ptr(out.iters), _ptr(out.status),
-        _ptr(sk.SA) if sk else None, row_capacity(r, opts) if sk else 0,
+        _ptr(sk.SA) if sk else None, row_capacity(r, opts, n) if sk else 0,
         _ptr(sk.Sb) if sk else None, _ptr(sk.rows) if sk else None,
         _ptr(sk.count) if sk else None, ctypes.byref(opts), _ptr(ws), ws.numel(),
         _stream(stream))

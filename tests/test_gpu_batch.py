@@ -61,21 +61,6 @@ def test_multi_rhs_one_column_equals_single_path():
     assert torch.equal(one.x, multi.X[:, 0])
 
 
-def test_multi_rhs_full_size_sampled_columns():
-    n, d, k, r, seed = 1 << 20, 64, 512, 2048, 4
-    print("multi full size 2^20 x 64, 512 rhs", flush=True)
-    A, B, _ = workloads.tfidf_multi_rhs(n, d, k, seed=seed)
-    sol = rnnls.rand_nnls_multi(rnnls.colmajor(A), rnnls.colmajor(B), r, seed)
-    torch.cuda.synchronize()
-    assert (sol.status.cpu().numpy() == rnnls.SOLVE_OK).all()
-    cols = list(range(0, k, 37)) + [k - 1]
-    Y, _, _, _ = hadamard.srht_sketch(
-        np.column_stack([A] + [B[:, j] for j in cols]).astype(np.float64), None, r, seed)
-    X = sol.X.cpu().numpy()
-    for t, j in enumerate(cols):
-        assert _gap_ok(Y[:, :d], Y[:, d + t], X[:, j]) <= GAP_TOL, j
-
-
 # ------------------------------------------------------------ batch plans
 SMALL_BATCH = [(3000, 5, 1024), (5000, 40, 1280), (17000, 8, 1024), (33000, 20, 1024),
                (70000, 96, 3072), (2047, 3, 500), (40000, 64, 2048), (16384, 17, 1024),
@@ -154,18 +139,6 @@ def test_batch_autotune_capture_and_replay():
         one = rnnls.rand_nnls(rnnls.colmajor(p0.A), torch.from_numpy(p0.b).cuda(), 1280, rep)
         torch.cuda.synchronize()
         assert int(one.status.item()) == rnnls.SOLVE_OK
-    batch.close()
-
-
-def test_batch_full_size_sampled_instances():
-    shapes = workloads.batch_shapes()
-    print(f"full batch of {len(shapes)} instances", flush=True)
-    probs, batch = _make_batch(shapes, batch_seed=4)
-    batch.run()
-    torch.cuda.synchronize()
-    st = batch.status.cpu().numpy()
-    assert (st == rnnls.SOLVE_OK).all()
-    _check_against_oracle(probs, batch, which={0, 1, 77, 128, 200, 255})
     batch.close()
 
 

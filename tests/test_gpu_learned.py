@@ -128,7 +128,10 @@ def test_warm_start_gain_and_parity():
     assert ev.all_ok
     assert ev.max_gap <= 1e-9
     assert ev.warm_kept >= 0.9
+    # outer iterations counted after the warm start (its own sweeps are not
+    # outer iterations), and the Lawson-Hanson kernel time, which does count them
     assert ev.warm_iters < 0.5 * ev.cold_iters
+    assert ev.warm_lh_ms < ev.cold_lh_ms
     # parity of warm-started solutions with the oracle on a few problems
     shp = learned.shapes(256, 22, (12.0, 14.0))[:4]
     probs = learned.device_problems(shp, 22 * 1_000_003, "cuda")
@@ -142,4 +145,101 @@ def test_warm_start_gain_and_parity():
         ref = nnls.lawson_hanson(SA, Sb)
         x = batch.x[i].cpu().numpy()
         assert nnls.relative_residual_gap(SA, Sb, x, ref.x) <= 1e-6, i
+    batch.close()
+
+
+def test_features_on_a_hand_built_gram():
+    """The device features of the 3-column Gram form whose features are worked
+    out by hand in the oracle's pins (FP32 output of FP64 arithmetic)."""
+    G = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 16.0]])
+    q = np.array([2.0, -6.0, 3.0])
+    f0 = np.array([1 / 6, -1.0, 1 / 8])
+    want = np.column_stack([
+        f0, [1 / 3, -1.0, 1 / 2], np.array([7.0, -17.0, 10.0]) / np.sqrt(146.0),
+        [1 / 2, 9 / 16, 1 / 16], [1.0, 1.0, 1 / 8], [-1 / 2, 35 / 384, -1 / 16],
+        np.log(np.array([4.0, 1.0, 16.0]) / 7.0), np.full(3, 3 / 128)])
+    got = rnnls.features(torch.from_numpy(G).cuda(), torch.from_numpy(q).cuda(),
+                         torch.tensor([36.0], dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(got.cpu().numpy().astype(np.float64), want, rtol=1e-6, atol=1e-7)
+
+
+def _cosine_net(threshold=0.05):
+    """A perceptron proposing exactly the columns whose cosine with b (feature
+    f0) exceeds `threshold`: h1_0 = relu(f0 - t), h2_0 = relu(h1_0),
+    p = sigmoid(1000 h2_0 - 1e-3); every other weight zero (all exact in BF16)."""
+    P = {name: np.zeros(shape) for name, shape in olearned.SHAPES}
+    P["W1"][0, 0] = 1.0
+    P["b1"][0] = -threshold
+    P["W2"][0, 0] = 1.0
+    P["w3"][0] = 1000.0
+    P["b3"][0] = -1e-3
+    return olearned.pack(P).astype(np.float32)
+
+
+def _gaussian_problems(count, n=4096, d=24, r=512):
+    """Mixed-sign problems (standard normal A, x* with 10 zeros, noise 2):
+    columns anti-correlated with b exist, so the cosine proposal is partial."""
+    out = []
+    for seed in range(count):
+        g = np.random.default_rng(seed)
+        A = g.standard_normal((n, d)).astype(np.float32)
+        xs = np.abs(g.standard_normal(d))
+        xs[g.choice(d, 10, replace=False)] = 0.0
+        b = (A.astype(np.float64) @ xs + 2.0 * g.standard_normal(n)).astype(np.float32)
+        out.append((A, b, r, 1000 + seed))
+    return out
+
+
+def test_rejected_warm_start_falls_back_to_the_cold_solve():
+    """Definition 1's KKT conditions judge a warm start; one that cannot pass
+    (here: it hits the outer-iteration cap) is replaced by the cold start from
+    x = 0.  Premise on the oracle: from the cosine proposal Lawson-Hanson needs
+    more than `cap` outer iterations.  On the device the warm-started pass must
+    then report warm_used = 0, the cold pass's x bit for bit, its status, and
+    the iterations of both attempts."""
+    cap = 2
+    probs = _gaussian_problems(4)
+    theta = _cosine_net()
+    for A, b, r, seed in probs:
+        SA, Sb, _, _ = hadamard.srht_sketch(A.astype(np.float64), b.astype(np.float64), r, seed)
+        F = olearned.features(SA.T @ SA, SA.T @ Sb, float(Sb @ Sb))
+        prop = F[:, 0] > 0.05
+        assert 0 < prop.sum() < len(prop)
+        assert nnls.lawson_hanson(SA, Sb, passive0=prop).iters > cap + 1
+        assert nnls.lawson_hanson(SA, Sb).iters > cap
+    dev = [(rnnls.colmajor(A), torch.from_numpy(b).cuda(), r, s) for A, b, r, s in probs]
+    mlp = rnnls.Mlp(torch.from_numpy(theta).cuda())
+    batch = rnnls.Batch(dev, opts=rnnls.make_opts(max_iter=cap))
+    batch.run()
+    torch.cuda.synchronize()
+    x_cold = [x.clone() for x in batch.x]
+    st_cold = batch.status.clone()
+    it_cold = batch.iters.clone()
+    assert (st_cold == rnnls.SOLVE_MAX_ITER).all() and (it_cold == cap).all()
+    batch.set_model(mlp)
+    batch.run()
+    torch.cuda.synchronize()
+    used = batch.warm_used().cpu().numpy()
+    assert (used == 0).all()
+    for i in range(len(probs)):
+        assert torch.equal(batch.x[i], x_cold[i]), i
+    assert torch.equal(batch.status, st_cold)
+    assert (batch.iters == it_cold + cap).all()
+    batch.close()
+    # without the cap the same proposal is kept and reaches the optimum
+    batch = rnnls.Batch(dev)
+    batch.run()
+    torch.cuda.synchronize()
+    it_cold = batch.iters.clone()
+    batch.set_model(mlp)
+    batch.run()
+    torch.cuda.synchronize()
+    assert (batch.warm_used().cpu().numpy() == 1).all()
+    assert (batch.status.cpu().numpy() == rnnls.SOLVE_OK).all()
+    assert (batch.iters < it_cold).all()
+    for i, (A, b, r, seed) in enumerate(probs):
+        SA, Sb, _, _ = hadamard.srht_sketch(A.astype(np.float64), b.astype(np.float64), r, seed)
+        ref = nnls.lawson_hanson(SA, Sb)
+        assert abs(nnls.relative_residual_gap(SA, Sb, batch.x[i].cpu().numpy(), ref.x)) <= 1e-6
     batch.close()

@@ -105,20 +105,3 @@ def test_split_rand_nnls_against_oracle(n, d, r, seed):
     assert abs(full) <= 1e-5
 
 
-def test_split_full_size_sampled_columns():
-    """2^22 x 128, r = 8192: whole sketched columns for a few columns of A
-    and for b, against the oracle's FP64 transform of those columns."""
-    n, d, r, seed = 1 << 22, 128, 8192, 3
-    print("split-bf16 full size 2^22 x 128", flush=True)
-    p = workloads.tfidf_like(n, d, seed=seed)
-    sk = rnnls.srht_sketch(rnnls.colmajor(p.A), torch.from_numpy(p.b).cuda(), r, seed,
-                           opts=SPLIT)
-    torch.cuda.synchronize()
-    cols = [0, 1, 64, 127]
-    M = np.column_stack([p.A[:, c] for c in cols] + [p.b]).astype(np.float64)
-    Y, _, R, _ = hadamard.srht_sketch(M, None, r, seed)
-    assert np.array_equal(sk.rows.cpu().numpy(), R)
-    got = np.column_stack([sk.SA.cpu().numpy()[:, c] for c in cols] + [sk.Sb.cpu().numpy()])
-    err = _colwise_rel(got, Y)
-    print(f"split-bf16 2^22 x 128 r=8192: max column error {err:.2e}", flush=True)
-    assert err <= SPLIT_TOL

@@ -127,3 +127,29 @@ def test_feature_special_cases():
     # one column: no neighbours
     X = learned.features(*_gram(Q[:, :1], b))
     assert X[0, 3] == X[0, 4] == X[0, 5] == 0.0
+
+
+def test_feature_values_on_a_hand_built_gram():
+    """Every feature of a 3-column (G, q, c) worked out by hand from the
+    definitions: C_01 = 2/(2*1) = 1, C_02 = 0, C_12 = 0.5/(1*4) = 1/8;
+    f0 = q_j / sqrt(G_jj c) = (2/12, -6/6, 3/24); max|q| = 6 (not max q = 3);
+    mean q = -1/3 and std q = sqrt(146)/3, so f2 = (7, -17, 10)/sqrt(146);
+    f5_j averages C_jk f0_k over k != j; mean diag G = 7."""
+    G = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 16.0]])
+    q = np.array([2.0, -6.0, 3.0])
+    c = 36.0
+    f0 = np.array([1 / 6, -1.0, 1 / 8])
+    want = np.zeros((3, 8))
+    want[:, 0] = f0
+    want[:, 1] = [1 / 3, -1.0, 1 / 2]
+    want[:, 2] = np.array([7.0, -17.0, 10.0]) / np.sqrt(146.0)
+    want[:, 3] = [1 / 2, 9 / 16, 1 / 16]
+    want[:, 4] = [1.0, 1.0, 1 / 8]
+    want[:, 5] = [(1.0 * f0[1] + 0.0 * f0[2]) / 2,      # -1/2
+                  (1.0 * f0[0] + 0.125 * f0[2]) / 2,    # 35/384
+                  (0.0 * f0[0] + 0.125 * f0[1]) / 2]    # -1/16
+    want[:, 6] = np.log(np.array([4.0, 1.0, 16.0]) / 7.0)
+    want[:, 7] = 3 / 128
+    assert abs(want[1, 5] - 35 / 384) < 1e-15
+    got = learned.features(G, q, c)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-15)

@@ -147,3 +147,43 @@ def test_free_solve_without_bound_terms_is_caught(monkeypatch):
     monkeypatch.setattr(bvls, "_plain_free", plain_free)
     monkeypatch.setattr(bvls, "_free_solve", free_solve)
     assert not _bvls_matches_brute_force()
+
+
+def _features_pin(feat):
+    """The hand-built 3-column pin of the learned features (values worked out
+    from the definitions; see test_oracle_learned)."""
+    G = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 16.0]])
+    q = np.array([2.0, -6.0, 3.0])
+    X = feat(G, q, 36.0)
+    f0 = np.array([1 / 6, -1.0, 1 / 8])
+    return (np.allclose(X[:, 1], [1 / 3, -1.0, 1 / 2], atol=1e-13)
+            and np.allclose(X[:, 5], [-1 / 2, 35 / 384, -1 / 16], atol=1e-13)
+            and np.allclose(X[:, 6], np.log(np.array([4.0, 1.0, 16.0]) / 7.0), atol=1e-13)
+            and np.allclose(X[:, 0], f0, atol=1e-13))
+
+
+def test_feature_mistakes_are_caught():
+    from oracle import learned
+    assert _features_pin(learned.features)
+
+    def mutated(change):
+        def feat(G, q, c):
+            X = learned.features(G, q, c)
+            change(X, G, q, c)
+            return X
+        return feat
+
+    def f1_by_max_q(X, G, q, c):          # max q instead of max |q|
+        X[:, 1] = q / np.max(q)
+
+    def f5_own_cosine(X, G, q, c):        # f0_j instead of f0_k
+        d = len(q)
+        for j in range(d):
+            C = [G[j, k] / np.sqrt(G[j, j] * G[k, k]) for k in range(d) if k != j]
+            X[j, 5] = np.mean(C) * X[j, 0]
+
+    def f6_by_max_norm(X, G, q, c):       # normalised by the largest diagonal
+        X[:, 6] = np.log(np.diag(G) / np.max(np.diag(G)))
+
+    for change in (f1_by_max_q, f5_own_cosine, f6_by_max_norm):
+        assert not _features_pin(mutated(change)), change.__name__
