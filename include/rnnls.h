@@ -190,6 +190,33 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed,
                     int32_t* r_out, const rnnls_opts* opts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ---- without a workspace ------------------------------------------------
+ * rnnls_rand_nnls_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): rnnls_rand_nnls with the same arguments and results, minus
+ * ws and ws_bytes.  Its scratch is a fixed array of
+ * RNNLS_NOALLOC_SCRATCH_BYTES in the library's device memory, one per device,
+ * held until the process ends; the call allocates nothing (no hipMalloc, no
+ * library allocation) and frees nothing.
+ *  - Sizes whose workspace (rnnls_workspace_bytes(RNNLS_OP_RAND_NNLS, ...))
+ *    exceeds RNNLS_NOALLOC_SCRATCH_BYTES return RNNLS_E_WORKSPACE before
+ *    anything is launched (2^20 x 64 at r = 4096 needs about 15 MB, 2^22 x 128
+ *    at r = 8192 about 14 MB).  Invalid arguments return as rnnls_rand_nnls.
+ *  - Every call on a device shares that device's array, which keeps the last
+ *    call's contents; nothing in it has to start at zero.  Calls that
+ *    overlap on one device (other streams, other host threads) race on it:
+ *    order them on one stream.
+ *  - The array's device address is read with hipGetSymbolAddress on the
+ *    first call made with each device current (RNNLS_E_HIP if that fails).
+ */
+#define RNNLS_NOALLOC_SCRATCH_BYTES (64 << 20)
+
+int rnnls_rand_nnls_noalloc(int64_t n, int32_t d, int32_t r, uint64_t seed,
+                            const float* A, int64_t lda, const float* b,
+                            double* x, double* rnorm, int32_t* iters, int32_t* status,
+                            float* SA, int64_t ldsa, float* Sb, int32_t* rows,
+                            int32_t* r_out, const rnnls_opts* opts, void* stream);
+
 /* ---- box constraints on the same sketch ---------------------------------
  * rnnls_rand_box -- the conclusions remark that the sketch of Algorithm 1 does
  * not depend on the constraint set.  Steps 1-4 as rnnls_rand_nnls, then step 5

@@ -24,6 +24,7 @@ SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
 MAX_D, MAX_R, MAX_K, MAX_BOOST, MAX_BOX_D = 128, 32768, 4096, 8, 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = (
     "rnnls_version", "rnnls_device_cus", "rnnls_workspace_bytes", "rnnls_srht_sketch",
@@ -36,6 +37,7 @@ EXPORTS = (
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
     "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost", "rnnls_rand_box",
+    "rnnls_rand_nnls_noalloc",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
@@ -78,6 +80,8 @@ _SIGS = {
                          ctypes.c_int),
     "rnnls_rand_nnls": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
                          _p, _p, _p, _sz, _p], ctypes.c_int),
+    "rnnls_rand_nnls_noalloc": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _i64,
+                                 _p, _p, _p, _p, _p], ctypes.c_int),
     "rnnls_rand_box": ([_i64, _i32, _i32, _u64, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                         _sz, _p], ctypes.c_int),
     "rnnls_multi_workspace_bytes": ([_i64, _i32, _i32, _i32, _p], _sz),
@@ -288,6 +292,38 @@ def rand_nnls(A: torch.Tensor, b: torch.Tensor, r: int, seed: int, opts: Opts | 
         _ptr(sk.count) if sk else None, ctypes.byref(opts), _ptr(ws), ws.numel(),
         _stream(stream))
     _check(rc, "rnnls_rand_nnls")
+    out.sketch = sk
+    return out
+
+
+def rand_nnls_noalloc(A: torch.Tensor, b: torch.Tensor, r: int, seed: int,
+                      opts: Opts | None = None, keep_sketch: bool = False, out=None,
+                      stream=None) -> Solution:
+    """Algorithm 1 end to end without a workspace (rnnls_rand_nnls_noalloc):
+    the library's fixed per-device scratch array takes its place."""
+    opts = opts or Opts()
+    n, d = A.shape
+    lda = _check_colmajor(A, "A")
+    dev = A.device
+    if out is None:
+        out = Solution(torch.empty(d, dtype=torch.float64, device=dev), None,
+                       torch.empty(1, dtype=torch.float64, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev))
+    sk = None
+    rc_ = row_capacity(r, opts, n)
+    if keep_sketch:
+        sk = Sketch(torch.empty((d, rc_), dtype=torch.float32, device=dev).t(),
+                    torch.empty(rc_, dtype=torch.float32, device=dev),
+                    torch.empty(rc_, dtype=torch.int32, device=dev),
+                    torch.empty(1, dtype=torch.int32, device=dev), out.status, None)
+    rc = load().rnnls_rand_nnls_noalloc(
+        n, d, r, seed & (2**64 - 1), _ptr(A), lda, _ptr(b), _ptr(out.x), _ptr(out.rnorm),
+        _ptr(out.iters), _ptr(out.status),
+        _ptr(sk.SA) if sk else None, rc_ if sk else 0,
+        _ptr(sk.Sb) if sk else None, _ptr(sk.rows) if sk else None,
+        _ptr(sk.count) if sk else None, ctypes.byref(opts), _stream(stream))
+    _check(rc, "rnnls_rand_nnls_noalloc")
     out.sketch = sk
     return out
 
