@@ -77,7 +77,8 @@ extern "C" {
 #define RNNLS_PREC_FP32 0           /* FP32 transform                         */
 #define RNNLS_PREC_SPLIT_BF16 1     /* split-BF16 matrix-core transform (below) */
 
-/* Limits of this version: 1 <= d <= RNNLS_MAX_D; 1 <= r < n'; r (or r_cap)
+/* Limits of this version: 1 <= d <= RNNLS_MAX_D (RNNLS_MAX_D_SOLVE for the
+ * single-problem calls, below); 1 <= r < n'; r (or r_cap)
  * <= RNNLS_MAX_R; n' <= 2^30.
  *
  * RNNLS_PREC_SPLIT_BF16: the in-tile Hadamard transform runs two of its three
@@ -90,6 +91,13 @@ extern "C" {
  * launched); problems with n' < 2^14 run the FP32 transform. */
 #define RNNLS_MAX_D 128
 #define RNNLS_MAX_R 32768
+/* rnnls_srht_sketch, rnnls_nnls_solve, rnnls_rand_nnls (and its
+ * allocation-free variant) take 1 <= d <= RNNLS_MAX_D_SOLVE: problems with
+ * d > RNNLS_MAX_D are solved by a Lawson-Hanson kernel whose sweep tableau
+ * (d x d FP64, upper triangle) lives in the workspace; batches, many
+ * right-hand sides, repetition, box bounds and the learned proposal keep
+ * d <= RNNLS_MAX_D. */
+#define RNNLS_MAX_D_SOLVE 512
 
 typedef struct rnnls_opts {
   int32_t sample_mode; /* RNNLS_SAMPLE_*                                      */
@@ -125,7 +133,7 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
  *
  *   [SA | Sb] = (1/sqrt r) * (H_n' D [A | b])[rows, :]
  *
- *  n, d        A is n x d (n >= 2, 1 <= d <= RNNLS_MAX_D)
+ *  n, d        A is n x d (n >= 2, 1 <= d <= RNNLS_MAX_D_SOLVE)
  *  r           target row count, 1 <= r < n' (n' = 2^ceil(log2 n))
  *  seed        seed of the random streams (see above)
  *  A, lda      input, column-major, lda >= n
@@ -151,7 +159,7 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed,
 /* rnnls_nnls_solve -- Definition 1 solved exactly (Lawson-Hanson, LH74 ch. 23)
  * for a problem already on the device:  x = argmin_{x >= 0} ||M x - f||_2.
  *
- *  m, d        M is m x d (m >= 1, 1 <= d <= RNNLS_MAX_D)
+ *  m, d        M is m x d (m >= 1, 1 <= d <= RNNLS_MAX_D_SOLVE)
  *  M, ldm      input, column-major, ldm >= m
  *  f           input right-hand side of length m
  *  m_dev       optional device int32[1] holding the row count actually used
@@ -323,8 +331,12 @@ int rnnls_rand_nnls_multi(int64_t n, int32_t d, int32_t k, int32_t r, uint64_t s
  *              *bad_index, if not NULL, receives its index), plans the
  *              launches and binds `ws` (device, 256-byte aligned, caller
  *              owned, kept until destroy).  Allocates the plan's device-side
- *              descriptor tables (hipMalloc) and uploads them synchronously.
- * rnnls_batch_run     enqueues one pass over all problems on `stream`.
+ *              descriptor tables (hipMalloc) and uploads them synchronously,
+ *              and creates one stream and two events of its own.
+ * rnnls_batch_run     enqueues one pass over all problems on `stream`; the
+ *              solves of problems with d <= 64 run on the plan's own stream,
+ *              forked from `stream` and joined back into it, beside those
+ *              with d > 64 (so later work on `stream` sees every result).
  * rnnls_batch_autotune  times every candidate tile shape of the sketch on
  *              the plan's own problems (synchronising `stream`), keeps the
  *              fastest for this plan and reports it in *chosen (may be NULL).
@@ -421,16 +433,22 @@ int rnnls_mlp_train_step(int64_t rows, const float* X, const uint8_t* y, float* 
  * rnnls_batch_columns    total columns (sum of d) of the plan's problems
  * rnnls_batch_features   X (columns x 8, problems in order) of the last pass
  *                        and, if passive != NULL, its solutions' flags x_j > 0
- * rnnls_batch_set_model  theta/wb (device, kept by the caller) warm-start
- *                        every later pass from flags prob > threshold; NULL
- *                        theta turns the warm start off
+ * rnnls_batch_set_model  theta/wb (device, kept by the caller; wb 4-byte
+ *                        aligned, else -3) warm-start every later pass from
+ *                        the proposal prob > threshold; NULL theta turns the
+ *                        warm start off.  Each Lawson-Hanson workgroup computes
+ *                        its problem's features and runs the perceptron
+ *                        itself (no separate launches) before solving.
  * rnnls_batch_warm_used  int32[count]: 1 where the last pass kept the warm start
+ * rnnls_batch_proposal   uint8[columns]: the last warm-started pass's proposal
+ *                        (1 = proposed passive), problems in order
  */
 int rnnls_batch_columns(const rnnls_batch* plan, int64_t* columns);
 int rnnls_batch_features(rnnls_batch* plan, float* X, uint8_t* passive, void* stream);
 int rnnls_batch_set_model(rnnls_batch* plan, const float* theta, const uint16_t* wb,
                           float threshold);
 int rnnls_batch_warm_used(rnnls_batch* plan, int32_t* out, void* stream);
+int rnnls_batch_proposal(rnnls_batch* plan, uint8_t* out, void* stream);
 
 /* ---- launch tuning ------------------------------------------------------
  * Process-wide launch shape of the sketch kernel (all fields 0 = automatic:

@@ -65,7 +65,7 @@ int row_capacity(int r, const Opts& o, int64_t n_pad) {
 // Workspace layout; every region 256-byte aligned.
 struct Layout {
   size_t rows = 0, count = 0, status = 0, signs = 0, bern = 0, partials = 0, sa = 0, sb = 0,
-         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, total = 0;
+         mom = 0, G = 0, q = 0, cc = 0, colabs = 0, tab = 0, total = 0;
 };
 
 size_t put(size_t& off, size_t bytes) {
@@ -98,6 +98,7 @@ Layout layout_sketch(const Sizes& z, const Opts& o, bool with_solve, bool with_b
     L.q = put(off, sizeof(double) * (size_t)z.d);
     L.cc = put(off, sizeof(double));
     L.colabs = put(off, sizeof(double) * (size_t)z.d);
+    L.tab = put(off, lh_large_tableau_bytes(z.d));
   }
   L.total = off;
   return L;
@@ -132,15 +133,16 @@ Layout layout_solve(const Sizes& z) {
   L.q = put(off, sizeof(double) * (size_t)z.d);
   L.cc = put(off, sizeof(double));
   L.colabs = put(off, sizeof(double) * (size_t)z.d);
+  L.tab = put(off, lh_large_tableau_bytes(z.d));
   L.total = off;
   return L;
 }
 
 // Validate sketch sizes; returns 0 or -(argument position).
 int check_sketch_sizes(int64_t n, int32_t d, int32_t r, const Opts& o, int pos_n, int pos_d,
-                       int pos_r, int pos_opts, Sizes* z) {
+                       int pos_r, int pos_opts, Sizes* z, int max_d = RNNLS_MAX_D) {
   if (n < 2 || n > (1ll << 30)) return -pos_n;
-  if (d < 1 || d > RNNLS_MAX_D) return -pos_d;
+  if (d < 1 || d > max_d) return -pos_d;
   const int64_t n_pad = (int64_t)next_pow2((uint64_t)n);
   if (r < 1 || (int64_t)r >= n_pad || r > RNNLS_MAX_R) return -pos_r;
   if (!opts_valid(o)) return -pos_opts;
@@ -286,13 +288,13 @@ size_t rnnls_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t r,
   const int cus = device_cus();
   if (cus < 0) return 0;
   if (op == RNNLS_OP_SOLVE) {
-    if (n < 1 || d < 1 || d > RNNLS_MAX_D) return 0;
+    if (n < 1 || d < 1 || d > RNNLS_MAX_D_SOLVE) return 0;
     z.d = d;
     z.mp = moments_plan(n, d, 1, cus);
     return layout_solve(z).total;
   }
   if (op != RNNLS_OP_SKETCH && op != RNNLS_OP_RAND_NNLS) return 0;
-  if (check_sketch_sizes(n, d, r, o, 1, 2, 3, 4, &z)) return 0;
+  if (check_sketch_sizes(n, d, r, o, 1, 2, 3, 4, &z, RNNLS_MAX_D_SOLVE)) return 0;
   z.mp = moments_plan(z.r_cap, d, 1, cus);
   if (op == RNNLS_OP_RAND_NNLS) {
     z.sp = plan_for(n, d + 1, z.r_cap, cus, o);
@@ -307,7 +309,7 @@ int rnnls_srht_sketch(int64_t n, int32_t d, int32_t r, uint64_t seed, const floa
                       const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream) {
   const Opts o = read_opts(opts);
   Sizes z;
-  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 15, &z);
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 15, &z, RNNLS_MAX_D_SOLVE);
   if (rc) return rc;
   if (!A) return -5;
   if (lda < n) return -6;
@@ -334,7 +336,7 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
                      void* stream) {
   const Opts o = read_opts(opts);
   if (m < 1) return -1;
-  if (d < 1 || d > RNNLS_MAX_D) return -2;
+  if (d < 1 || d > RNNLS_MAX_D_SOLVE) return -2;
   if (!M) return -3;
   if (ldm < m) return -4;
   if (!f) return -5;
@@ -355,8 +357,9 @@ int rnnls_nnls_solve(int64_t m, int32_t d, const float* M, int64_t ldm, const fl
   int rc = launch_moments(
       z.mp, moment_job(z.mp, M, ldm, f, m, m_dev, at<double>(ws, L.mom), G, q, d, cc, colabs), s);
   if (rc) return rc;
-  return launch_lawson_hanson(
-      lh_job(d, m, m_dev, o, G, q, cc, colabs, nullptr, x, w, rnorm, iters, status), 1, s);
+  LhJob lj = lh_job(d, m, m_dev, o, G, q, cc, colabs, nullptr, x, w, rnorm, iters, status);
+  lj.tab = at<double>(ws, L.tab);
+  return launch_lawson_hanson(lj, 1, s);
 }
 
 int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A, int64_t lda,
@@ -365,7 +368,7 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
                     const rnnls_opts* opts, void* ws, size_t ws_bytes, void* stream) {
   const Opts o = read_opts(opts);
   Sizes z;
-  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 17, &z);
+  int rc = check_sketch_sizes(n, d, r, o, 1, 2, 3, 17, &z, RNNLS_MAX_D_SOLVE);
   if (rc) return rc;
   if (!A) return -5;
   if (lda < n) return -6;
@@ -396,8 +399,9 @@ int rnnls_rand_nnls(int64_t n, int32_t d, int32_t r, uint64_t seed, const float*
       z.mp, moment_job(z.mp, sa, ld, sb, z.r_cap, cnt, at<double>(ws, L.mom), G, q, d, cc, colabs),
       s);
   if (rc) return rc;
-  return launch_lawson_hanson(
-      lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm, iters, status), 1, s);
+  LhJob lj = lh_job(d, z.r_cap, cnt, o, G, q, cc, colabs, st, x, nullptr, rnorm, iters, status);
+  lj.tab = at<double>(ws, L.tab);
+  return launch_lawson_hanson(lj, 1, s);
 }
 
 int rnnls_rand_box(int64_t n, int32_t d, int32_t r, uint64_t seed, const float* A,

@@ -31,6 +31,8 @@ struct Candidate {
 };
 // LDS bounds the occupancy: 2^15-row tiles use 132 KB of the 160 KB per CU.
 const Candidate kCandidates[] = {{15, 1}, {14, 1}, {14, 2}, {13, 2}, {13, 4}, {12, 4}, {12, 8}};
+// row segments of a problem's moments at most (each at least 256 rows)
+constexpr int kMomentSegments = 8;
 
 struct Settings {
   int sample_mode = RNNLS_SAMPLE_EXACT;
@@ -81,9 +83,10 @@ struct rnnls_batch {
   void* dev_tables = nullptr;
   std::vector<StreamJob> sjobs;
   StreamJob* sdev = nullptr;
-  std::vector<int32_t> blk_map, chunk_map;  // block -> job
+  std::vector<int32_t> blk_map, chunk_map, ent_map;  // block -> job
   int32_t* blk_map_dev = nullptr;
   int32_t* chunk_map_dev = nullptr;
+  int32_t* ent_map_dev = nullptr;
   std::vector<Group> groups;
   std::vector<MomentJob> mjobs;
   MomentJob* mdev = nullptr;
@@ -94,6 +97,9 @@ struct rnnls_batch {
   int l_max_d[2] = {0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the d <= 64 solves run on a second stream beside the d > 64 ones
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   // learned proposal
   int64_t columns = 0;
   std::vector<char> fjobs;  // FeatJob records
@@ -215,8 +221,9 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
-    // chunks of 256 rows: short workgroups, few partials per entry
-    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, 1);  // one chunk: no partials
+    // row segments of at least 256 rows, at most 8 per problem (many
+    // problems fill the device together)
+    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, kMomentSegments);
     o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
     o_cnt[i] = put(off, sizeof(int32_t));
     o_st[i] = put(off, sizeof(int32_t));
@@ -248,6 +255,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   int64_t blk0 = 0, chunk0 = 0, row0 = 0;
   B.blk_map.clear();
   B.chunk_map.clear();
+  B.ent_map.clear();
   int max_pairs = 0;
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
@@ -282,9 +290,11 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     mj.nb = mp[i].nb;
     mj.pairs = mp[i].pairs;
     mj.chunk0 = chunk0;
-    mj.ent0 = 0;
     chunk0 += mp[i].chunks;
     B.chunk_map.insert(B.chunk_map.end(), (size_t)mp[i].chunks, i);
+    mj.ent0 = (int64_t)B.ent_map.size() * 256;
+    if (mp[i].chunks > 1)  // blocks of 256 reduce entries of this problem
+      B.ent_map.insert(B.ent_map.end(), (size_t)((moments_entries(mp[i]) + 255) / 256), i);
     max_pairs = std::max(max_pairs, mp[i].pairs);
     double* scr = at<double>(ws, o_mom[i]);
     mj.part = scr;
@@ -310,7 +320,10 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     lj.rnorm = p.rnorm;
     lj.iters = p.iters;
     lj.status = p.status;
-    lj.p0 = B.theta ? B.flags + row0 : nullptr;
+    lj.theta = B.theta;
+    lj.wb = B.wb;
+    lj.threshold = B.threshold;
+    lj.flags = B.theta ? B.flags + row0 : nullptr;
     lj.warm_used = B.warm_used + i;
     make_feat_job(B.fjobs.data() + (size_t)i * feat_job_bytes(), mj.G, mj.Q, mj.c, p.x, p.d,
                   row0);
@@ -344,6 +357,14 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     }
   }
   return total;
+}
+
+void free_streams(rnnls_batch& B) {
+  if (B.fork) (void)hipEventDestroy(B.fork);
+  if (B.join) (void)hipEventDestroy(B.join);
+  if (B.side) (void)hipStreamDestroy(B.side);
+  B.fork = B.join = nullptr;
+  B.side = nullptr;
 }
 
 void free_tables(rnnls_batch& B) {
@@ -383,6 +404,8 @@ int plan(rnnls_batch& B, const Candidate& c) {
   bytes += map_bytes(B.blk_map);
   const size_t o_cm = bytes;
   bytes += map_bytes(B.chunk_map);
+  const size_t o_em = bytes;
+  bytes += map_bytes(B.ent_map);
   std::vector<size_t> o_gm;
   for (Group& G : B.groups) {
     o_gm.push_back(bytes);
@@ -404,6 +427,7 @@ int plan(rnnls_batch& B, const Candidate& c) {
   copy(o_f, B.fjobs.data(), B.fjobs.size());
   copy(o_bm, B.blk_map.data(), sizeof(int32_t) * B.blk_map.size());
   copy(o_cm, B.chunk_map.data(), sizeof(int32_t) * B.chunk_map.size());
+  copy(o_em, B.ent_map.data(), sizeof(int32_t) * B.ent_map.size());
   for (size_t g = 0; g < B.groups.size(); ++g)
     copy(o_gm[g], B.groups[g].col_map.data(), sizeof(int32_t) * B.groups[g].col_map.size());
   if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -417,6 +441,7 @@ int plan(rnnls_batch& B, const Candidate& c) {
   B.fdev = base + o_f;
   B.blk_map_dev = reinterpret_cast<int32_t*>(base + o_bm);
   B.chunk_map_dev = reinterpret_cast<int32_t*>(base + o_cm);
+  B.ent_map_dev = reinterpret_cast<int32_t*>(base + o_em);
   for (size_t g = 0; g < B.groups.size(); ++g)
     B.groups[g].col_map_dev = reinterpret_cast<int32_t*>(base + o_gm[g]);
   B.tune = c;
@@ -436,16 +461,29 @@ int run_all(rnnls_batch& B, hipStream_t s) {
   if (rc) return rc;
   rc = run_sketch(B, s);
   if (rc) return rc;
-  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.m_max_pairs, B.chunk_map_dev, s);
+  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.chunk_map_dev,
+                            (int64_t)B.ent_map.size(), B.ent_map_dev, s);
   if (rc) return rc;
-  if (B.theta) {  // learned proposal -> warm-start flags
-    rc = launch_features_batch(B.fdev, B.count, B.X, s);
+  // with a model, each Lawson-Hanson workgroup first computes its problem's
+  // learned proposal (features and perceptron) and warm-starts from it.  The
+  // two solve launches (d <= 64, d > 64) are independent: the smaller one
+  // runs on the plan's second stream, forked from and joined back into `s`
+  // (also inside a captured graph, as two branches).
+  const bool model = B.theta != nullptr;
+  const bool both = !B.ljobs[0].empty() && !B.ljobs[1].empty();
+  if (both) {
+    if (hipEventRecord(B.fork, s) != hipSuccess || hipStreamWaitEvent(B.side, B.fork, 0) != hipSuccess)
+      return RNNLS_E_HIP;
+    rc = launch_lawson_hanson_batch(B.ldev[0], (int)B.ljobs[0].size(), B.l_max_d[0], model,
+                                    B.side);
     if (rc) return rc;
-    rc = launch_mlp_forward(B.columns, B.X, B.theta, B.wb, nullptr, B.flags, B.threshold, s);
+    if (hipEventRecord(B.join, B.side) != hipSuccess) return RNNLS_E_HIP;
+    rc = launch_lawson_hanson_batch(B.ldev[1], (int)B.ljobs[1].size(), B.l_max_d[1], model, s);
     if (rc) return rc;
+    return hipStreamWaitEvent(s, B.join, 0) == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
   }
   for (int h = 0; h < 2; ++h) {
-    rc = launch_lawson_hanson_batch(B.ldev[h], (int)B.ljobs[h].size(), B.l_max_d[h], s);
+    rc = launch_lawson_hanson_batch(B.ldev[h], (int)B.ljobs[h].size(), B.l_max_d[h], model, s);
     if (rc) return rc;
   }
   return RNNLS_OK;
@@ -518,9 +556,15 @@ int rnnls_batch_create(rnnls_batch** out, int32_t count, const rnnls_problem* pr
   }
   B->ws = ws;
   B->ws_bytes = ws_bytes;
-  const int rc = plan(*B, Candidate{0, 0});
+  int rc = RNNLS_OK;
+  if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess)
+    rc = RNNLS_E_HIP;
+  if (rc == RNNLS_OK) rc = plan(*B, Candidate{0, 0});
   if (rc) {
     free_tables(*B);
+    free_streams(*B);
     delete B;
     return rc;
   }
@@ -637,11 +681,12 @@ int rnnls_batch_set_model(rnnls_batch* B, const float* theta, const uint16_t* wb
                           float threshold) {
   if (!B) return -1;
   if (theta && !wb) return -3;
+  if (wb && (uintptr_t)wb % 4 != 0) return -3;
   if (!(threshold > 0.0f && threshold < 1.0f)) return -4;
   B->theta = theta;
   B->wb = wb;
   B->threshold = threshold;
-  return plan(*B, B->tune);  // the Lawson-Hanson descriptors gain or lose p0
+  return plan(*B, B->tune);  // the Lawson-Hanson descriptors gain or lose the model
 }
 
 int rnnls_batch_warm_used(rnnls_batch* B, int32_t* out, void* stream) {
@@ -653,10 +698,21 @@ int rnnls_batch_warm_used(rnnls_batch* B, int32_t* out, void* stream) {
              : RNNLS_E_HIP;
 }
 
+int rnnls_batch_proposal(rnnls_batch* B, uint8_t* out, void* stream) {
+  if (!B) return -1;
+  if (!out) return -2;
+  if (B->columns < 1) return RNNLS_OK;
+  return hipMemcpyAsync(out, B->flags, (size_t)B->columns, hipMemcpyDeviceToDevice,
+                        reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? RNNLS_OK
+             : RNNLS_E_HIP;
+}
+
 int rnnls_batch_destroy(rnnls_batch* B) {
   if (!B) return RNNLS_OK;
   const bool ok = hipDeviceSynchronize() == hipSuccess;
   free_tables(*B);
+  free_streams(*B);
   delete B;
   return ok ? RNNLS_OK : RNNLS_E_HIP;
 }

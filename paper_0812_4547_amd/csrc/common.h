@@ -176,10 +176,31 @@ struct LhJob {
   double* rnorm;    // nullable, stride 1
   int32_t* iters;   // nullable, stride 1
   int32_t* status;  // nullable, stride 1
-  const uint8_t* p0;  // nullable: proposed passive set (d flags) for a warm start
-  int64_t p0_stride;
+  // learned warm start (nullable theta = cold start only): the perceptron's
+  // FP32 parameters and BF16 weights (4-byte aligned), the probability
+  // threshold, and where the proposal (d flags) is written (nullable)
+  const float* theta;
+  const uint16_t* wb;
+  float threshold;
+  uint8_t* flags;
   int32_t* warm_used;  // nullable, stride 1: 1 if the warm start was kept
+  double* tab;  // d > RNNLS_MAX_D: the sweep tableau's scratch (lh_large_tableau_bytes)
 };
+
+// Parameter layout of the passive-set perceptron (8 -> 128 -> 128 -> 1): FP32
+// master vector W1 (128 x 8, row-major), b1, W2 (128 x 128), b2, w3, b3; BF16
+// copy of W1, W2, w3 in that order.
+namespace mlp {
+constexpr int kF = RNNLS_MLP_FEATURES;
+constexpr int kH = RNNLS_MLP_WIDTH;
+constexpr int oW1 = 0, ob1 = kH * kF, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH,
+              ob3 = ow3 + kH;
+constexpr int kParams = ob3 + 1;
+constexpr int bW1 = 0, bW2 = kH * kF, bw3 = bW2 + kH * kH;
+constexpr int kBf16 = bw3 + kH;
+static_assert(kParams == RNNLS_MLP_PARAMS, "parameter layout");
+static_assert(kBf16 == RNNLS_MLP_BF16_WEIGHTS, "bf16 layout");
+}  // namespace mlp
 
 // One box-constrained solve in Gram form (bvls.hip).
 struct BoxJob {
@@ -253,23 +274,32 @@ struct MomentsPlan {
   int64_t m;
   int d, k;
   int chunks, nbA, nb, pairs;
+  int lds;  // one right-hand side: all block pairs from each row chunk in LDS
 };
 // max_chunks > 0 caps the row chunks (batches spread over problems instead)
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);
 size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
-// one chunk per job (max_chunks = 1 plans); chunk_job: job of every block
-// column of the launch
-int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         const int32_t* chunk_job, hipStream_t s);
+// one right-hand side per job; chunk_job: job of every row segment of the
+// launch; ent_job: job of every block of 256 reduce entries (jobs with more
+// than one segment only)
+int launch_moments_batch(const MomentJob* dev, int njobs, int64_t segments,
+                         const int32_t* chunk_job, int64_t ent_blocks, const int32_t* ent_job,
+                         hipStream_t s);
+int64_t moments_entries(const MomentsPlan& p);
 // start of the column 1-norm partials inside a moments scratch of plan p
 double* moments_abs_scratch(const MomentsPlan& p, double* scratch);
 
-size_t lh_lds_bytes(int d);
+size_t lh_lds_bytes(int d, bool model);
+// wide problems (RNNLS_MAX_D < d <= RNNLS_MAX_D_SOLVE): tableau scratch bytes
+// (0 for d <= RNNLS_MAX_D) and the one-problem launch
+size_t lh_large_tableau_bytes(int d);
+int launch_lawson_hanson_large(const LhJob& j, hipStream_t s);
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s);
 int launch_bvls(const BoxJob& j, hipStream_t s);
 // every job of a batch has d <= max_d, one problem each
-int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s);
+int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, bool model,
+                               hipStream_t s);
 
 // Learned proposals (learned.hip).  Feature jobs are opaque records of
 // feat_job_bytes() bytes built by make_feat_job.

@@ -33,15 +33,19 @@ namespace rnnls {
 
 namespace {
 
-constexpr int kF = RNNLS_MLP_FEATURES;
-constexpr int kH = RNNLS_MLP_WIDTH;
-constexpr int oW1 = 0, ob1 = kH * kF, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH,
-              ob3 = ow3 + kH;
-constexpr int kParams = ob3 + 1;
-static_assert(kParams == RNNLS_MLP_PARAMS, "parameter layout");
-constexpr int bW1 = 0, bW2 = kH * kF, bw3 = bW2 + kH * kH;
-constexpr int kBf16 = bw3 + kH;
-static_assert(kBf16 == RNNLS_MLP_BF16_WEIGHTS, "bf16 layout");
+using mlp::kF;
+using mlp::kH;
+using mlp::oW1;
+using mlp::ob1;
+using mlp::oW2;
+using mlp::ob2;
+using mlp::ow3;
+using mlp::ob3;
+using mlp::kParams;
+using mlp::bW1;
+using mlp::bW2;
+using mlp::bw3;
+using mlp::kBf16;
 constexpr int kRows = 64;  // rows per workgroup
 constexpr int kT = 256;
 constexpr int kLd = kH + 1;

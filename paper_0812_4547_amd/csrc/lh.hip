@@ -181,10 +181,223 @@ __host__ __device__ constexpr int lh_threads(int) { return 256; }
 __host__ __device__ constexpr int lh_waves(int dp) { return lh_threads(dp) / kW; }
 inline int padded_order(int d) { return d <= kW ? kW : 2 * kW; }
 
+// Scratch of the learned proposal (before Q is staged, in Q's place):
+// the features (128 x 8 FP32); the first hidden layer of a chunk of 32
+// columns (32 rows of 128 FP32, row stride 132), whose space first holds
+// 1/sqrt(G_jj) and the cosines (FP64, 128 each); W2 (128 x 128 BF16,
+// [unit][input], row stride 132); W1 (128 x 8 BF16); output partials
+// (4 wavefronts x 32 FP32); flags.
+constexpr int kPropCols = 32;
+constexpr int kH1Ld = 132;
+constexpr int kW2Ld = 132;
+constexpr size_t kPropF = 0, kPropH1 = kPropF + 128 * 8 * 4,
+                 kPropIsd = kPropH1, kPropCos = kPropIsd + 128 * 8,
+                 kPropW2 = kPropH1 + kPropCols * kH1Ld * 4, kPropW1 = kPropW2 + 128 * kW2Ld * 2,
+                 kPropZ = kPropW1 + 128 * 8 * 2, kPropFl = kPropZ + 4 * kPropCols * 4,
+                 kPropBytes = kPropFl + 128;
+static_assert(kPropCos + 128 * 8 <= kPropW2, "cosines fit in the hidden-layer space");
+
 // partial sums (one row of 2*kW per wavefront), two pivot-row buffers
-// (2 x 128), Q (d x ld)
-inline size_t lds_words(int d) {
-  return (size_t)lh_waves(padded_order(d)) * 2 * kW + 2 * 128 + (size_t)d * lds_ld(d);
+// (2 x 128), Q (d x ld) -- or the proposal's scratch before Q, if larger
+inline size_t lds_words(int d, bool model) {
+  const size_t q = (size_t)d * lds_ld(d);
+  const size_t prop = model ? (kPropBytes + 7) / 8 : 0;
+  return (size_t)lh_waves(padded_order(d)) * 2 * kW + 2 * 128 + (q > prop ? q : prop);
+}
+
+__device__ __forceinline__ float bf16f(uint32_t h16) { return __uint_as_float(h16 << 16); }
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kW);
+  return v;
+}
+
+// The learned passive-set proposal of one problem, by the whole workgroup
+// (256 threads), from its Gram form: the per-column features f0..f7 (FP64,
+// stored FP32; definitions in learned.hip) and the perceptron
+// p = sigmoid(w3 . relu(W2 relu(W1 f + b1) + b2) + b3) with BF16 weights and
+// FP32 accumulation.  The first layer runs on the vector units (thread t: the
+// eight units 8 (t % 16) .. of column t / 16 of a 32-column chunk); the second
+// on the FP32 matrix cores (v_mfma_f32_16x16x4f32, products of FP32 values
+// accumulated in FP32): wavefront w forms columns 16 (w % 2) .. + 15 of the
+// chunk against units 64 (w / 2) .. + 63, four 16 x 16 output tiles over the
+// 128 inputs.  qv / dq hold q and diag(G) replicated in every wavefront
+// (entry lane + 64 h).  Returns the proposal as ballot masks (every wavefront
+// the same) and writes the flags to J.flags when given.  `scr` is LDS
+// scratch of kPropBytes; the caller synchronises before reusing it.
+template <int H>
+__device__ void propose(const LhJob& J, const double* __restrict__ G,
+                        const double* __restrict__ q, int d, double c,
+                        const double (&qv)[H], const double (&dq)[H], const bool (&valid)[H],
+                        char* scr, uint64_t (&prop)[H]) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int t = threadIdx.x;
+  const int lane = t & (kW - 1);
+  const int wv = t / kW;
+  float* F = reinterpret_cast<float*>(scr + kPropF);
+  double* isd = reinterpret_cast<double*>(scr + kPropIsd);
+  double* cosv = reinterpret_cast<double*>(scr + kPropCos);
+  float* h1 = reinterpret_cast<float*>(scr + kPropH1);
+  uint16_t* w2s = reinterpret_cast<uint16_t*>(scr + kPropW2);
+  uint16_t* w1s = reinterpret_cast<uint16_t*>(scr + kPropW1);
+  float* zp = reinterpret_cast<float*>(scr + kPropZ);
+  uint8_t* fl = reinterpret_cast<uint8_t*>(scr + kPropFl);
+
+  // weights into LDS, row by row as stored (32-bit reads: wb is 4-byte aligned)
+  const uint32_t* wb32 = reinterpret_cast<const uint32_t*>(J.wb);
+  for (int e = t; e < 128 * 64; e += 256) {
+    const int u = e >> 6, v2 = e & 63;
+    *reinterpret_cast<uint32_t*>(w2s + u * kW2Ld + 2 * v2) = wb32[(mlp::bW2 >> 1) + e];
+  }
+  for (int e = t; e < 128 * 4; e += 256)
+    reinterpret_cast<uint32_t*>(w1s)[e] = wb32[(mlp::bW1 >> 1) + e];
+
+  // column statistics over the replicated registers (the same in every wave)
+  double qa = 0.0, qs = 0.0, ds = 0.0;
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+    if (valid[h]) {
+      qa = fmax(qa, fabs(qv[h]));
+      qs += qv[h];
+      ds += dq[h];
+    }
+  const double qmax = wave_extreme<true>(qa);
+  const double qmean = wave_sum(qs) / d;
+  const double dmean = wave_sum(ds) / d;
+  double qq = 0.0;
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+    if (valid[h]) qq += (qv[h] - qmean) * (qv[h] - qmean);
+  const double qstd = sqrt(wave_sum(qq) / d);
+  if (wv == 0) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if (valid[h]) {
+        const int j = lane + h * kW;
+        isd[j] = dq[h] > 0.0 ? 1.0 / sqrt(dq[h]) : 0.0;
+        cosv[j] = (dq[h] > 0.0 && c > 0.0) ? qv[h] / sqrt(dq[h] * c) : 0.0;
+      }
+  }
+  __syncthreads();
+  if (t < d) {  // features of column j = t; row k of G holds G[k][j] (coalesced)
+    const int j = t;
+    const double isdj = isd[j];
+    double csum = 0.0, cmax = -1.0, cw = 0.0;
+    // sixteen rows of G in flight at a time; the terms are added in k order
+    for (int k0 = 0; k0 < d; k0 += 16) {
+      double g[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) g[e] = k0 + e < d ? G[(int64_t)(k0 + e) * d + j] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int k = k0 + e;
+        if (k < d && k != j) {
+          const double ck = g[e] * isdj * isd[k];
+          csum += ck;
+          cmax = fmax(cmax, ck);
+          cw += ck * cosv[k];
+        }
+      }
+    }
+    const double qj = q[j];
+    const double gd = G[(int64_t)j * d + j];
+    const double inv = d > 1 ? 1.0 / (d - 1) : 0.0;
+    double lg = (gd > 0.0 && dmean > 0.0) ? log(gd / dmean) : -30.0;
+    lg = fmin(30.0, fmax(-30.0, lg));
+    float* f = F + j * 8;
+    f[0] = (float)cosv[j];
+    f[1] = (float)(qmax > 0.0 ? qj / qmax : 0.0);
+    f[2] = (float)(qstd > 0.0 ? (qj - qmean) / qstd : 0.0);
+    f[3] = (float)(csum * inv);
+    f[4] = (float)(d > 1 ? cmax : 0.0);
+    f[5] = (float)(cw * inv);
+    f[6] = (float)lg;
+    f[7] = (float)d / 128.0f;
+  }
+  // first layer: this thread's column of the chunk and eight units
+  const int c1 = t >> 4;
+  const int u1 = 8 * (t & 15);
+  float b1u[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) b1u[b] = J.theta[mlp::ob1 + u1 + b];
+  // second layer: this wavefront's column block and units; its lane's unit
+  // (column of the output tiles) in each of the four tiles
+  const int cb = 16 * (wv & 1);
+  const int ub = 64 * (wv >> 1);
+  const int kq = lane >> 4;
+  float b2u[4], w3u[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const int u = ub + 16 * tt + (lane & 15);
+    b2u[tt] = J.theta[mlp::ob2 + u];
+    w3u[tt] = bf16f(J.wb[mlp::bw3 + u]);
+  }
+  const float b3 = J.theta[mlp::ob3];
+  __syncthreads();  // features, weights in place; isd / cosv are dead from here
+  for (int c0 = 0; c0 < d; c0 += kPropCols) {
+    {
+      const int col = c0 + 2 * c1;
+      // two columns per thread: 2 c1 and 2 c1 + 1 of the chunk
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const bool in = col + cc < d;
+        float x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = in ? F[(col + cc) * 8 + i] : 0.0f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          float h = b1u[b];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) h = fmaf(bf16f(w1s[(u1 + b) * 8 + i]), x[i], h);
+          h1[(2 * c1 + cc) * kH1Ld + u1 + b] = in ? fmaxf(h, 0.0f) : 0.0f;
+        }
+      }
+    }
+    __syncthreads();
+    // second layer on the matrix cores: D[i][j] = sum_k h1[cb + i][k] W2[u][k]
+    // (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of each
+    // 16 x 16 x 4 step; D[4 (l / 16) + v][l % 16] returns in accumulator v)
+    v4f acc[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) acc[tt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < 128; k0 += 4) {
+      const float a = h1[(cb + (lane & 15)) * kH1Ld + k0 + kq];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        const float bw = bf16f(w2s[(ub + 16 * tt + (lane & 15)) * kW2Ld + k0 + kq]);
+        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw, acc[tt], 0, 0, 0);
+      }
+    }
+    // output partials: rows 4 kq + v of the block are columns cb + 4 kq + v
+    float zr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float z = 0.0f;
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) z = fmaf(w3u[tt], fmaxf(acc[tt][v] + b2u[tt], 0.0f), z);
+      // sum over the 16 units of each tile row held by lanes 16 kq .. 16 kq + 15
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) z += __shfl_xor(z, off, kW);
+      zr[v] = z;
+    }
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zp[wv * kPropCols + cb + 4 * kq + v] = zr[v];
+    }
+    __syncthreads();
+    if (t < kPropCols && c0 + t < d) {
+      const int w0 = (t >> 4) & 1;  // the two wavefronts holding column block t / 16
+      const float zz = zp[w0 * kPropCols + t] + zp[(w0 + 2) * kPropCols + t] + b3;
+      const float p = 1.0f / (1.0f + expf(-zz));
+      fl[c0 + t] = p > J.threshold ? 1 : 0;
+    }
+    __syncthreads();  // h1 and zp are rewritten by the next chunk
+  }
+#pragma unroll
+  for (int h = 0; h < H; ++h) prop[h] = __ballot(valid[h] && fl[lane + h * kW] != 0);
+  if (J.flags && t < d) J.flags[t] = fl[t];
 }
 
 // u[h] += sum_{i0 <= i < i1} M[i][col[h]] x_i (x_i a scalar read from the
@@ -218,7 +431,7 @@ __device__ __forceinline__ void mv_rows(const double* M, int ld, int i0, int i1,
 
 }  // namespace
 
-size_t lh_lds_bytes(int d) { return lds_words(d) * sizeof(double); }
+size_t lh_lds_bytes(int d, bool model) { return lds_words(d, model) * sizeof(double); }
 
 template <bool BATCH>
 __device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jobs) {
@@ -229,7 +442,7 @@ __device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jo
 // The problem of workgroup blockIdx.x: job blockIdx.x of a batch table
 // (BATCH), or sub-problem blockIdx.x of the job `one`, whose inputs sit at the
 // job's strides.  Q (= G) is d x d row-major (symmetric), d <= DP.
-template <int DP, bool BATCH>
+template <int DP, bool BATCH, bool MODEL>
 __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one,
                                                                      const LhJob* jobs) {
   constexpr int H = DP / kW;      // column-indexed entries per lane
@@ -267,9 +480,9 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
         v[e][h] = (i0 + e < r1 && valid[h]) ? Qg[(int64_t)(i0 + e) * d + lane + h * kW] : 0.0;
   };
   // this wavefront's first rows of Q are requested before anything else, so
-  // their latency overlaps the set-up
+  // their latency overlaps the set-up (after the proposal, with a model)
   double v0[kBlock][H];
-  fetch(r0, v0);
+  if (!MODEL) fetch(r0, v0);
 
   const int max_iter = J.max_iter;
   const double* qg = J.q + sub * J.q_stride;
@@ -294,6 +507,16 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   for (int off = 1; off < kW; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, kW));
   const double c = J.c[sub * J.c_stride];
   const int64_t m_eff = J.m_dev ? (int64_t)J.m_dev[sub * J.m_dev_stride] : J.m;
+  // the learned proposal, computed before Q is staged (its scratch is Q's place)
+  uint64_t prop0[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) prop0[h] = 0ull;
+  if constexpr (MODEL) {
+    propose<H>(J, Qg, qg, d, c, qv, dq, valid,
+               reinterpret_cast<char*>(lh_lds + kNW * 2 * kW + 2 * 128), prop0);
+    __syncthreads();
+    fetch(r0, v0);
+  }
   const double tau =
       uni(J.tol > 0.0 ? J.tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
 
@@ -424,8 +647,7 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
 
   // A proposed passive set (warm start) is tried first; its result must pass
   // the KKT certificate, else a cold start from x = 0 replaces it.
-  const uint8_t* p0 = J.p0 ? J.p0 + sub * J.p0_stride : nullptr;
-  int warm = p0 ? 1 : 0;
+  int warm = MODEL ? 1 : 0;
   int total_iters = 0;
   bool ok = true;
   double xq = 0.0, xw = 0.0;
@@ -438,7 +660,7 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
       // skipped), then reverse-sweep nonpositive coefficients until z > 0
       uint64_t prop[H];
 #pragma unroll
-      for (int h = 0; h < H; ++h) prop[h] = __ballot(valid[h] && p0[lane + h * kW] != 0);
+      for (int h = 0; h < H; ++h) prop[h] = prop0[h];
       for (int k = pop_lowest(prop); k >= 0; k = pop_lowest(prop)) {
         const double s = uni(bcast(dg, k));
         const double qkk = uni(bcast(dq, k));
@@ -600,38 +822,49 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   }
 }
 
-template <int DP, bool BATCH>
+template <int DP, bool BATCH, bool MODEL>
 int launch_lh_t(const LhJob& one, const LhJob* jobs, int nblocks, size_t lds, hipStream_t s) {
-  const void* fn = (const void*)lawson_hanson_kernel<DP, BATCH>;
+  const void* fn = (const void*)lawson_hanson_kernel<DP, BATCH, MODEL>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess)
     return RNNLS_E_HIP;
-  hipLaunchKernelGGL((lawson_hanson_kernel<DP, BATCH>), dim3(nblocks), dim3(lh_threads(DP)), lds,
-                     s, one, jobs);
+  hipLaunchKernelGGL((lawson_hanson_kernel<DP, BATCH, MODEL>), dim3(nblocks),
+                     dim3(lh_threads(DP)), lds, s, one, jobs);
   return RNNLS_OK;
 }
 
 template <bool BATCH>
-int launch_lh(const LhJob& one, const LhJob* jobs, int nblocks, int d, hipStream_t s) {
-  const size_t lds = lh_lds_bytes(d);
+int launch_lh(const LhJob& one, const LhJob* jobs, int nblocks, int d, bool model,
+              hipStream_t s) {
+  const size_t lds = lh_lds_bytes(d, model);
   if (lds > kMaxLdsBytes) return RNNLS_E_UNSUPPORTED;
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_SOLVE, s, &tok);
-  const int rc = d <= kW ? launch_lh_t<64, BATCH>(one, jobs, nblocks, lds, s)
-                         : launch_lh_t<128, BATCH>(one, jobs, nblocks, lds, s);
+  // the warm-started kernels are separate instances: the proposal's registers
+  // and LDS stay out of the cold solves
+  int rc;
+  if (model)
+    rc = d <= kW ? launch_lh_t<64, BATCH, true>(one, jobs, nblocks, lds, s)
+                 : launch_lh_t<128, BATCH, true>(one, jobs, nblocks, lds, s);
+  else
+    rc = d <= kW ? launch_lh_t<64, BATCH, false>(one, jobs, nblocks, lds, s)
+                 : launch_lh_t<128, BATCH, false>(one, jobs, nblocks, lds, s);
   timer_end(RNNLS_TIMER_SOLVE, s, tok);
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
 int launch_lawson_hanson(const LhJob& j, int nsub, hipStream_t s) {
-  return launch_lh<false>(j, nullptr, nsub, j.d, s);
+  if (j.d > RNNLS_MAX_D)  // wide problems: tableau in memory (lh_large.hip)
+    return nsub == 1 ? launch_lawson_hanson_large(j, s) : RNNLS_E_UNSUPPORTED;
+  return launch_lh<false>(j, nullptr, nsub, j.d, j.theta != nullptr, s);
 }
 
-int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, hipStream_t s) {
+int launch_lawson_hanson_batch(const LhJob* dev, int njobs, int max_d, bool model,
+                               hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   LhJob none{};
-  return launch_lh<true>(none, dev, njobs, max_d, s);
+  return launch_lh<true>(none, dev, njobs, max_d, model, s);
 }
 
 }  // namespace rnnls

@@ -21,6 +21,15 @@
 // into chunks whose partial blocks a second kernel adds in a fixed order
 // (one thread per output entry: deterministic).
 //
+// With a single right-hand side (d + k <= 129 columns) a second kernel reads
+// every row once: the rows of a segment go through LDS in chunks of 64 rows
+// of all d + k columns (double-buffered: the next chunk's loads are in flight
+// while the current one is multiplied), and the workgroup's eight wavefronts
+// form every block pair of the problem from each chunk, each wavefront its
+// own pairs in its own accumulators.  Row segments (enough to fill the device,
+// at least 256 rows each) write partial blocks that the reduce kernel adds in
+// a fixed order, as the chunks of the first kernel.
+//
 // One problem travels by value in the kernel arguments; a batch of problems
 // (different m, d) reads its descriptors from a device table.
 #include <algorithm>
@@ -178,6 +187,134 @@ __global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const
   }
 }
 
+// ---- every block pair of a problem from one pass over its rows
+constexpr int kLdsCols = 129;   // d + k
+constexpr int kLdsRows = 64;    // rows per chunk
+constexpr int kLdsCs = kLdsRows + 4;  // column stride in LDS (padded against bank conflicts)
+constexpr int kLdsNW = 8;       // wavefronts per workgroup
+constexpr int kLdsMaxPairs = 45;  // 9 blocks of 16: 8 * 9 / 2 + 9
+constexpr int kLdsPW = (kLdsMaxPairs + kLdsNW - 1) / kLdsNW;  // pairs per wavefront
+constexpr int kLdsLoads = (kLdsCols * (kLdsRows / 4) + kLdsNW * 64 - 1) / (kLdsNW * 64);
+
+// Segment `seg` of the job: rows [m seg / S, m (seg+1) / S) (S = J.chunks).
+template <bool BATCH>
+__global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
+                                                               const MomentJob* jobs,
+                                                               const int32_t* jmap) {
+  __shared__ __attribute__((aligned(16))) float xs[2][kLdsCols * kLdsCs];
+  int64_t seg64;
+  const MomentJob J =
+      mjob<BATCH>(one, jobs, jmap, blockIdx.x, blockIdx.x, &MomentJob::chunk0, seg64);
+  const int seg = (int)seg64;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = t >> 6;
+  const int kq = lane >> 4;
+  const int D1 = J.d + J.k;
+  const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
+  const int64_t r0 = (J.m * seg) / J.chunks;
+  const int64_t r1 = (J.m * (seg + 1)) / J.chunks;
+  const int64_t hi = r1 < m_eff ? r1 : m_eff;
+  const bool vec = ((uintptr_t)J.M % 16 == 0) && (J.ldm % 4 == 0) &&
+                   (J.k == 0 || (((uintptr_t)J.F % 16 == 0) && (J.ldf % 4 == 0)));
+
+  // this thread's share of a chunk's loads: float4 e = column e / 16, rows 4 (e % 16) ..
+  auto fetch = [&](int64_t c0, float4 (&v)[kLdsLoads]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kLdsLoads; ++u) {
+      const int e = t + u * kLdsNW * 64;
+      const int col = e >> 4;
+      v[u] = (col < D1) ? load_rows4(col_ptr(J, col), c0 + 4 * (e & 15), hi, vec)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&](float* buf, const float4 (&v)[kLdsLoads]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kLdsLoads; ++u) {
+      const int e = t + u * kLdsNW * 64;
+      const int col = e >> 4;
+      if (col < D1) *reinterpret_cast<float4*>(buf + col * kLdsCs + 4 * (e & 15)) = v[u];
+    }
+  };
+
+  // this wavefront's block pairs: p = wv, wv + 8, ...
+  int pbi[kLdsPW], pbj[kLdsPW];
+#pragma unroll
+  for (int s = 0; s < kLdsPW; ++s) {
+    const int p = wv + s * kLdsNW;
+    if (p < J.pairs) pair_blocks(p, J.nbA, J.nb, pbi[s], pbj[s]);
+    else pbi[s] = pbj[s] = 0;
+  }
+  v4d acc[kLdsPW];
+#pragma unroll
+  for (int s = 0; s < kLdsPW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
+  double aabs = 0.0;  // column t's 1-norm share (t < d)
+
+  float4 nxt[kLdsLoads];
+  int b = 0;
+  if (r0 < hi) {
+    fetch(r0, nxt);
+    stash(xs[0], nxt);
+  }
+  for (int64_t c0 = r0; c0 < hi; c0 += kLdsRows) {
+    const bool more = c0 + kLdsRows < hi;
+    if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
+    __syncthreads();
+    const float* X = xs[b];
+    if (t < J.d) {
+#pragma unroll 8
+      for (int r = 0; r < kLdsRows; ++r) aabs += fabs((double)X[t * kLdsCs + r]);
+    }
+#pragma unroll
+    for (int g = 0; g < kLdsRows / 16; ++g) {
+#pragma unroll
+      for (int s = 0; s < kLdsPW; ++s) {
+        if (wv + s * kLdsNW >= J.pairs) continue;
+        const float4 xa = *reinterpret_cast<const float4*>(
+            X + (pbi[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+        const float4 xb = *reinterpret_cast<const float4*>(
+            X + (pbj[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.x, (double)xb.x, acc[s], 0, 0, 0);
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.y, (double)xb.y, acc[s], 0, 0, 0);
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.z, (double)xb.z, acc[s], 0, 0, 0);
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.w, (double)xb.w, acc[s], 0, 0, 0);
+      }
+    }
+    if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
+    b ^= 1;
+  }
+  // results: partial blocks of the segment, or the final G, Q, c and 1-norms
+#pragma unroll
+  for (int s = 0; s < kLdsPW; ++s) {
+    const int p = wv + s * kLdsNW;
+    if (p >= J.pairs) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 4 * v + kq;  // row of the block
+      const double val = acc[s][v];
+      if (J.chunks > 1) {
+        J.part[((int64_t)seg * J.pairs + p) * (kBlk * kBlk) + a * kBlk + (lane & 15)] = val;
+        continue;
+      }
+      const int i = pbi[s] * kBlk + a;
+      const int j = pbj[s] * kBlk + (lane & 15);
+      if (i > j || j >= D1) continue;
+      if (j < J.d) {
+        J.G[(int64_t)i * J.d + j] = val;
+        J.G[(int64_t)j * J.d + i] = val;
+      } else if (i < J.d) {
+        J.Q[(int64_t)(j - J.d) * J.ldq + i] = val;
+      } else if (i == j) {
+        J.c[i - J.d] = val;
+      }
+    }
+  }
+  if (t < J.d) {
+    if (J.chunks > 1) J.part_abs[(int64_t)seg * J.d + t] = aabs;
+    else J.colabs[t] = aabs;
+  }
+}
+
 // One thread per output entry, summing the chunks in order (deterministic;
 // consecutive threads read consecutive entries of each chunk).  Entry
 // e < pairs*256 is element (e/16 % 16, e % 16) of block pair e/256; the next
@@ -240,6 +377,16 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   p.nbA = (d + kBlk - 1) / kBlk;
   p.nb = (d + k + kBlk - 1) / kBlk;
   p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
+  p.lds = d + k <= kLdsCols ? 1 : 0;
+  if (p.lds) {
+    // segments of at least 256 rows, at most two workgroups per CU (batches
+    // cap them per problem: many problems fill the device together)
+    int64_t segs = (m + 255) / 256;
+    int64_t cap = 2 * (int64_t)cus;
+    if (max_chunks > 0 && max_chunks < cap) cap = max_chunks;
+    p.chunks = (int)std::max<int64_t>(1, std::min(segs, cap));
+    return p;
+  }
   // at most kRowsPerChunk rows per chunk, and enough chunks (of at least 512
   // rows) that the blocks fill about two workgroups per CU
   int64_t want = (m + kRowsPerChunk - 1) / kRowsPerChunk;
@@ -274,7 +421,10 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   const dim3 grid(p.chunks, p.pairs);
-  if (p.m / p.chunks > 2048)  // long chunks: more wavefronts share each one's rows
+  if (p.lds)
+    hipLaunchKernelGGL(gram_lds_kernel<false>, dim3(p.chunks), dim3(kLdsNW * 64), 0, s, j,
+                       (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  else if (p.m / p.chunks > 2048)  // long chunks: more wavefronts share each one's rows
     hipLaunchKernelGGL((gram_mfma_kernel<false, 16>), grid, dim3(16 * 64), 0, s, j,
                        (const MomentJob*)nullptr, (const int32_t*)nullptr);
   else
@@ -289,17 +439,27 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
-// Batches: one chunk per problem (its rows are a sketch), so no reduce.
-int launch_moments_batch(const MomentJob* dev, int njobs, int64_t chunks, int max_pairs,
-                         const int32_t* chunk_job, hipStream_t s) {
+// Batches (one right-hand side per problem): every row segment of every
+// problem in one launch (chunk_job: job of every segment), then the fixed-
+// order sums of the problems with more than one segment (ent_job: job of
+// every block of 256 entries; ent_blocks of them).
+int launch_moments_batch(const MomentJob* dev, int njobs, int64_t segments,
+                         const int32_t* chunk_job, int64_t ent_blocks, const int32_t* ent_job,
+                         hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   MomentJob none{};
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
-  hipLaunchKernelGGL((gram_mfma_kernel<true, 4>), dim3((unsigned)chunks, (unsigned)max_pairs),
-                     dim3(4 * 64), 0, s, none, dev, chunk_job);
+  hipLaunchKernelGGL(gram_lds_kernel<true>, dim3((unsigned)segments), dim3(kLdsNW * 64), 0, s,
+                     none, dev, chunk_job);
+  if (ent_blocks > 0)
+    hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)ent_blocks), dim3(256), 0, s,
+                       none, dev, ent_job);
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
+
+// entries of a job's reduce (blocks of 256 cover them)
+int64_t moments_entries(const MomentsPlan& p) { return (int64_t)p.pairs * kBlk * kBlk + p.d; }
 
 }  // namespace rnnls

@@ -39,6 +39,7 @@ namespace rnnls {
 namespace {
 
 constexpr int kRegs = 32;  // elements per thread
+constexpr int kReduceRows = 2048;  // block rows of a batch reduce launch
 
 __device__ __forceinline__ int lds_pad(int j) { return j + ((j >> 7) << 2); }
 
@@ -365,16 +366,16 @@ void srht_tiled_kernel(TiledLaunch L) {
   }
 }
 
-// Job of the column this block row handles (batch: the column -> job map).
+// Job of column cg of the launch (batch: the column -> job map).
 template <bool BATCH>
 __device__ __forceinline__ const SketchJob& col_job(const SketchJob& one, const SketchJob* jobs,
-                                                    const int32_t* jmap, int& col) {
+                                                    const int32_t* jmap, int cg, int& col) {
   if constexpr (BATCH) {
-    const int i = jmap[blockIdx.y];
-    col = (int)((int64_t)blockIdx.y - jobs[i].col0);
+    const int i = jmap[cg];
+    col = (int)((int64_t)cg - jobs[i].col0);
     return jobs[i];
   } else {
-    col = blockIdx.y;
+    col = cg;
     return one;
   }
 }
@@ -421,19 +422,23 @@ __device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t 
   }
 }
 
+// Block row y reduces columns y, y + gridDim.y, ... of the launch's `cols`
+// (a batch of thousands of short columns runs on a bounded grid).
 template <bool BATCH>
 __global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap,
-                                   int64_t items, int64_t grid) {
-  int col;
-  const SketchJob& J = col_job<BATCH>(one, jobs, jmap, col);
-  reduce_col(J, col, items, grid);
+                                   int64_t items, int64_t grid, int cols) {
+  for (int cg = blockIdx.y; cg < cols; cg += gridDim.y) {
+    int col;
+    const SketchJob& J = col_job<BATCH>(one, jobs, jmap, cg, col);
+    reduce_col(J, col, items, grid);
+  }
 }
 
 // Small n' (<= 2048): every output straight from the definition, FP64 sums.
 template <bool BATCH>
 __global__ void srht_direct_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap) {
   int col;
-  const SketchJob& J = col_job<BATCH>(one, jobs, jmap, col);
+  const SketchJob& J = col_job<BATCH>(one, jobs, jmap, blockIdx.y, col);
   if (col >= J.ncols) return;
   const int count = *J.count;
   const float* src = (col < J.d) ? J.A + (int64_t)col * J.lda : J.B + (int64_t)(col - J.d) * J.ldb;
@@ -923,7 +928,7 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
   hipLaunchKernelGGL(srht_reduce_kernel<false>, rgrid, dim3(threads), 0, s, j,
                      (const SketchJob*)nullptr, (const int32_t*)nullptr, main_items,
-                     (int64_t)(p.grid > 0 ? p.grid : 1));
+                     (int64_t)(p.grid > 0 ? p.grid : 1), p.ncols);
   timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
@@ -960,8 +965,9 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
   timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
-  hipLaunchKernelGGL(srht_reduce_kernel<true>, rgrid, dim3(threads), 0, s, none, dev,
-                     col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1));
+  const dim3 bgrid(1u, (unsigned)(g.cols < kReduceRows ? g.cols : kReduceRows));
+  hipLaunchKernelGGL(srht_reduce_kernel<true>, bgrid, dim3(threads), 0, s, none, dev,
+                     col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1), (int)g.cols);
   timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }

@@ -24,6 +24,7 @@ SAMPLE_EXACT, SAMPLE_BERNOULLI = 0, 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 OP_SKETCH, OP_SOLVE, OP_RAND_NNLS = 0, 1, 2
 MAX_D, MAX_R, MAX_K, MAX_BOOST, MAX_BOX_D = 128, 32768, 4096, 8, 64
+MAX_D_SOLVE = 512
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = (
@@ -37,7 +38,7 @@ EXPORTS = (
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
     "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost", "rnnls_rand_box",
-    "rnnls_rand_nnls_noalloc",
+    "rnnls_rand_nnls_noalloc", "rnnls_batch_proposal",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
@@ -110,6 +111,7 @@ _SIGS = {
     "rnnls_batch_features": ([_p, _p, _p, _p], ctypes.c_int),
     "rnnls_batch_set_model": ([_p, _p, _p, ctypes.c_float], ctypes.c_int),
     "rnnls_batch_warm_used": ([_p, _p, _p], ctypes.c_int),
+    "rnnls_batch_proposal": ([_p, _p, _p], ctypes.c_int),
     "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
     "rnnls_set_tuning": ([_p], ctypes.c_int),
@@ -514,6 +516,13 @@ class Batch:
         out = torch.empty(len(self.x), dtype=torch.int32, device=self.rnorm.device)
         _check(load().rnnls_batch_warm_used(self._plan, _ptr(out), _stream(stream)),
                "rnnls_batch_warm_used")
+        return out
+
+    def proposal(self, stream=None) -> torch.Tensor:
+        """The last warm-started pass's proposal flags (columns,) uint8."""
+        out = torch.empty(self.columns(), dtype=torch.uint8, device=self.rnorm.device)
+        _check(load().rnnls_batch_proposal(self._plan, _ptr(out), _stream(stream)),
+               "rnnls_batch_proposal")
         return out
 
     def close(self):

