@@ -51,7 +51,7 @@ WORKLOADS = {
 # [2^14, 2^18], d uniform in [8, 96], r = max(32 d, 1024)), and one A of
 # 2^20 x 64 with 512 right-hand sides (r = 2048)
 BATCH_WORKLOADS = ("batch_256", "multi_2p20x64_k512", "learned_4096", "fig1_2p20x64",
-                   "boost_2p20x64_k4", "nmf_2p16x2048_q32", "density_sweep_1e4x128",
+                   "boost_2p20x64_k4", "nmf_2p16x2048_q32", "density_sweep_1e4x300",
                    "box_2p20x64")
 
 # oracle instances per cpu_baseline sample (about 10-30 s on one host core)
@@ -693,17 +693,17 @@ def bench_nmf(args):
 
 
 def bench_density(args):
-    """The sparse-versus-dense experiment (Section 4.2) with d = 128 (this
-    solver's limit; the paper uses 300): n = 10,000, densities 2..64%, for each
-    density 10 random n x (d+1) matrices (nonzeros uniform in [0, 1]) and 10
-    choices of the column that becomes b (100 problems); r = d, d+50, d+100,
-    d+150 in both sampling modes, against the exact solve on all n rows.
-    Relative error = residual ratio minus one; times are GPU means per solve."""
+    """The sparse-versus-dense experiment (Section 4.2) at the paper's size:
+    n = 10,000, d = 300, densities 2..64%; for each density 10 random
+    n x (d+1) matrices (nonzeros uniform in [0, 1]) and 10 choices of the
+    column that becomes b (100 problems); r = d, d+50, d+100, d+150 in both
+    sampling modes, against the exact solve on all n rows.  Relative error =
+    residual ratio minus one; times are GPU means per solve."""
     import numpy as np
     import torch
 
     from paper_0812_4547_amd import rnnls, workloads
-    n, d = 10_000, 128
+    n, d = 10_000, 300
     densities = (0.02, 0.04, 0.08, 0.16, 0.32, 0.64)
     rs = (d, d + 50, d + 100, d + 150)
     stream = torch.cuda.current_stream()
@@ -724,6 +724,7 @@ def bench_density(args):
                           1, stream) / len(probs)
         res_plain = [float(np.linalg.norm(A64 @ s.x.cpu().numpy() - b64))
                      for (_, _, A64, b64), s in zip(probs, plain)]
+        plain_ok = sum(int(s.status.item()) == 0 for s in plain)
         for mode in ("bernoulli", "exact"):
             opts = rnnls.make_opts(mode)
             for r in rs:
@@ -739,13 +740,14 @@ def bench_density(args):
                 rows.append({"density": dens, "mode": mode, "r": r, "problems": len(probs),
                              "relative_error_mean": float(np.mean(err)),
                              "relative_error_max": float(np.max(err)), "status_ok": ok,
-                             "rand_ms": ms, "exact_full_ms": exact_ms,
+                             "rand_ms": ms, "exact_full_ms": exact_ms, "exact_status_ok": plain_ok,
                              "speedup_vs_exact_full": exact_ms / ms})
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     last = rows[-1]
     rec = _base_record(args, 1000.0 / last["rand_ms"], last["rand_ms"], {
-        "workload": "sparse-versus-dense experiment: n = 10,000, d = 128, densities 2..64%, "
-                    "100 problems per density, r = d + 50 i (i = 0..3), both sampling modes",
+        "workload": "sparse-versus-dense experiment at the paper's size: n = 10,000, d = 300, "
+                    "densities 2..64%, 100 problems per density, r = d + 50 i (i = 0..3), both "
+                    "sampling modes",
         "n": n, "d": d, "densities": list(densities), "r_values": list(rs),
         "step": "one randomized solve (density 64%, exact mode, r = d + 150)"})
     rec["sweep"] = rows
@@ -1163,7 +1165,7 @@ def main():
         return bench_nmf(args)
     if args.workload == "box_2p20x64":
         return bench_box(args)
-    if args.workload == "density_sweep_1e4x128":
+    if args.workload == "density_sweep_1e4x300":
         return bench_density(args)
 
     if args.workload == "warm_batch_4096":

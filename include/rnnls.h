@@ -466,6 +466,25 @@ int rnnls_batch_proposal(rnnls_batch* plan, uint8_t* out, void* stream);
 int rnnls_set_tuning(const rnnls_tuning* tuning);
 int rnnls_get_tuning(rnnls_tuning* tuning);
 
+/* ---- the autotuner's cache -----------------------------------------------
+ * rnnls_batch_autotune keeps each plan's choice in a process-wide table keyed
+ * by the plan's shapes (the device's CU count, the sampling mode and every
+ * problem's n', d and row capacity); a later plan with the same key takes the
+ * stored choice without timing anything.
+ * rnnls_tuning_cache_entries  number of entries
+ * rnnls_tuning_cache_clear    empties the table
+ * rnnls_tuning_cache_save     writes the table to a text file, one entry per
+ *                             line: key (16 hex digits), log2 tile rows,
+ *                             workgroups per CU
+ * rnnls_tuning_cache_load     merges such a file into the table; a malformed
+ *                             file merges nothing
+ * save/load return RNNLS_OK, -1 for a NULL path, RNNLS_E_UNSUPPORTED when the
+ * file cannot be opened, written or parsed.  Thread-safe (one mutex). */
+int rnnls_tuning_cache_entries(void);
+int rnnls_tuning_cache_clear(void);
+int rnnls_tuning_cache_save(const char* path);
+int rnnls_tuning_cache_load(const char* path);
+
 /* ---- kernel timing ------------------------------------------------------
  * Off by default.  When on, the library brackets every launch of the timed
  * kernels with two HIP events recorded on the launch stream (no extra

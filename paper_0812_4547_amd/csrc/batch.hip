@@ -15,9 +15,12 @@
 // The autotuner times the sketch launches of the plan's own problems for
 // each candidate (tile-size cap, workgroups per CU) and keeps the fastest.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -33,6 +36,16 @@ struct Candidate {
 const Candidate kCandidates[] = {{15, 1}, {14, 1}, {14, 2}, {13, 2}, {13, 4}, {12, 4}, {12, 8}};
 // row segments of a problem's moments at most (each at least 256 rows)
 constexpr int kMomentSegments = 8;
+
+// The autotuner's choices, process-wide, keyed by a plan's shapes.
+struct TuneCache {
+  std::mutex mu;
+  std::map<uint64_t, Candidate> table;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
 
 struct Settings {
   int sample_mode = RNNLS_SAMPLE_EXACT;
@@ -506,6 +519,27 @@ bool settings_valid(const rnnls_opts* o) {
          o->precision == RNNLS_PREC_FP32;
 }
 
+// Key of a plan's shapes for the autotuner's cache: FNV-1a over the device's
+// CU count, the sampling mode and every problem's (log2 n', d, row capacity).
+uint64_t shape_key(const rnnls_batch& B) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xffu;
+      h *= 0x100000001b3ull;
+    }
+  };
+  mix((uint64_t)B.cus);
+  mix((uint64_t)B.opts.sample_mode);
+  mix((uint64_t)B.count);
+  for (const rnnls_problem& p : B.probs) {
+    mix((uint64_t)ilog2_exact(next_pow2((uint64_t)p.n)));
+    mix((uint64_t)p.d);
+    mix((uint64_t)row_cap(p.r, B.opts, (int64_t)next_pow2((uint64_t)p.n)));
+  }
+  return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -579,6 +613,21 @@ int rnnls_batch_run(rnnls_batch* B, void* stream) {
 
 int rnnls_batch_autotune(rnnls_batch* B, void* stream, rnnls_tuning* chosen) {
   if (!B) return -1;
+  const uint64_t key = shape_key(*B);
+  {
+    TuneCache& C = tune_cache();
+    std::lock_guard<std::mutex> lock(C.mu);
+    const auto it = C.table.find(key);
+    if (it != C.table.end()) {  // the same shapes were timed before
+      const int rc = plan(*B, it->second);
+      if (rc) return rc;
+      if (chosen) {
+        chosen->srht_log_tile = it->second.log_t_cap;
+        chosen->srht_wgs_per_cu = it->second.wgs;
+      }
+      return RNNLS_OK;
+    }
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return RNNLS_E_HIP;
@@ -617,10 +666,66 @@ int rnnls_batch_autotune(rnnls_batch* B, void* stream, rnnls_tuning* chosen) {
   const int rc2 = plan(*B, best_c);
   if (rc) return rc;
   if (rc2) return rc2;
+  {
+    TuneCache& C = tune_cache();
+    std::lock_guard<std::mutex> lock(C.mu);
+    C.table[key] = best_c;
+  }
   if (chosen) {
     chosen->srht_log_tile = best_c.log_t_cap;
     chosen->srht_wgs_per_cu = best_c.wgs;
   }
+  return RNNLS_OK;
+}
+
+int rnnls_tuning_cache_entries(void) {
+  TuneCache& C = tune_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  return (int)C.table.size();
+}
+
+int rnnls_tuning_cache_clear(void) {
+  TuneCache& C = tune_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  C.table.clear();
+  return RNNLS_OK;
+}
+
+int rnnls_tuning_cache_save(const char* path) {
+  if (!path) return -1;
+  TuneCache& C = tune_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return RNNLS_E_UNSUPPORTED;
+  bool ok = true;
+  for (const auto& e : C.table)
+    ok = ok && fprintf(f, "%016llx %d %d\n", (unsigned long long)e.first, e.second.log_t_cap,
+                       e.second.wgs) > 0;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? RNNLS_OK : RNNLS_E_UNSUPPORTED;
+}
+
+int rnnls_tuning_cache_load(const char* path) {
+  if (!path) return -1;
+  FILE* f = fopen(path, "r");
+  if (!f) return RNNLS_E_UNSUPPORTED;
+  std::map<uint64_t, Candidate> read;
+  unsigned long long key = 0;
+  int lt = 0, w = 0;
+  int got;
+  while ((got = fscanf(f, "%llx %d %d", &key, &lt, &w)) == 3) {
+    bool known = false;
+    for (const Candidate& c : kCandidates) known = known || (c.log_t_cap == lt && c.wgs == w);
+    known = known || (lt == 0 && w == 0);
+    if (!known) break;
+    read[(uint64_t)key] = Candidate{lt, w};
+  }
+  const bool ok = got == EOF && feof(f);
+  fclose(f);
+  if (!ok) return RNNLS_E_UNSUPPORTED;  // nothing merged from a malformed file
+  TuneCache& C = tune_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  for (const auto& e : read) C.table[e.first] = e.second;
   return RNNLS_OK;
 }
 

@@ -24,7 +24,7 @@
 // With a single right-hand side (d + k <= 129 columns) a second kernel reads
 // every row once: the rows of a segment go through LDS in chunks of 64 rows
 // of all d + k columns (double-buffered: the next chunk's loads are in flight
-// while the current one is multiplied), and the workgroup's eight wavefronts
+// while the current one is multiplied), and the workgroup's sixteen wavefronts
 // form every block pair of the problem from each chunk, each wavefront its
 // own pairs in its own accumulators.  Row segments (enough to fill the device,
 // at least 256 rows each) write partial blocks that the reduce kernel adds in
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const
 constexpr int kLdsCols = 129;   // d + k
 constexpr int kLdsRows = 64;    // rows per chunk
 constexpr int kLdsCs = kLdsRows + 4;  // column stride in LDS (padded against bank conflicts)
-constexpr int kLdsNW = 8;       // wavefronts per workgroup
+constexpr int kLdsNW = 16;      // wavefronts per workgroup
 constexpr int kLdsMaxPairs = 45;  // 9 blocks of 16: 8 * 9 / 2 + 9
 constexpr int kLdsPW = (kLdsMaxPairs + kLdsNW - 1) / kLdsNW;  // pairs per wavefront
 constexpr int kLdsLoads = (kLdsCols * (kLdsRows / 4) + kLdsNW * 64 - 1) / (kLdsNW * 64);
@@ -265,20 +265,39 @@ __global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
 #pragma unroll 8
       for (int r = 0; r < kLdsRows; ++r) aabs += fabs((double)X[t * kLdsCs + r]);
     }
+    // per 16-row group: every pair's operands first, then the four k-steps
+    // with the pairs interleaved, so consecutive matrix-core instructions
+    // write different accumulators (no dependent chain)
 #pragma unroll
     for (int g = 0; g < kLdsRows / 16; ++g) {
+      float4 xa[kLdsPW], xb[kLdsPW];
 #pragma unroll
       for (int s = 0; s < kLdsPW; ++s) {
-        if (wv + s * kLdsNW >= J.pairs) continue;
-        const float4 xa = *reinterpret_cast<const float4*>(
+        xa[s] = *reinterpret_cast<const float4*>(
             X + (pbi[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
-        const float4 xb = *reinterpret_cast<const float4*>(
+        xb[s] = *reinterpret_cast<const float4*>(
             X + (pbj[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
-        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.x, (double)xb.x, acc[s], 0, 0, 0);
-        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.y, (double)xb.y, acc[s], 0, 0, 0);
-        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.z, (double)xb.z, acc[s], 0, 0, 0);
-        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa.w, (double)xb.w, acc[s], 0, 0, 0);
       }
+#pragma unroll
+      for (int s = 0; s < kLdsPW; ++s)
+        if (wv + s * kLdsNW < J.pairs)
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].x, (double)xb[s].x, acc[s],
+                                                        0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < kLdsPW; ++s)
+        if (wv + s * kLdsNW < J.pairs)
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].y, (double)xb[s].y, acc[s],
+                                                        0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < kLdsPW; ++s)
+        if (wv + s * kLdsNW < J.pairs)
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].z, (double)xb[s].z, acc[s],
+                                                        0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < kLdsPW; ++s)
+        if (wv + s * kLdsNW < J.pairs)
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].w, (double)xb[s].w, acc[s],
+                                                        0, 0, 0);
     }
     if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
     b ^= 1;

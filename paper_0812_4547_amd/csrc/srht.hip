@@ -160,13 +160,23 @@ constexpr int kNonTemporal = 2;
 constexpr int kCached = 0;
 constexpr int64_t kCachedLoadMaxBytes = 512ll << 20;
 
-// Raw buffer loads bound to the LLVM intrinsics themselves: the clang builtin
-// for 128-bit buffer loads is lowered to a 32-bit load here.
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-__device__ f32x4_t buffer_load_f32x4(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset,
-                                     int aux) __asm("llvm.amdgcn.raw.ptr.buffer.load.v4f32");
-__device__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset,
-                                    int aux) __asm("llvm.amdgcn.raw.ptr.buffer.load.i32");
+// Raw buffer loads (buffer_load_dwordx4 / buffer_load_dword with a lane
+// offset, a scalar offset and the cache-policy operand).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+struct f32x4_t {
+  float x, y, z, w;
+};
+template <int AUX>
+__device__ __forceinline__ f32x4_t buffer_load_f32x4(__amdgpu_buffer_rsrc_t rsrc, int voffset,
+                                                     int soffset) {
+  const u32x4_t q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voffset, soffset, AUX);
+  return f32x4_t{__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                 __uint_as_float(q.w)};
+}
+__device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t rsrc, int voffset,
+                                                    int soffset) {
+  return __builtin_amdgcn_raw_buffer_load_b32(rsrc, voffset, soffset, 0);
+}
 
 // Loads of one tile (and its sign word).  With `live` false nothing is read
 // and v is zero: the buffer range is empty.  Aligned columns use buffer loads
@@ -190,13 +200,13 @@ __device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t t
   const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(J.sign_words + tile * (T / kRegs)), (short)0, live ? (T / kRegs) * 4 : 0,
       kBufferFlags);
-  sw = buffer_load_u32(srsrc, 4 * tid, 0, 0);
+  sw = buffer_load_u32(srsrc, 4 * tid, 0);
   if constexpr (MODE != kScalar) {
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)base, (short)0, live ? (MODE == kFullVec ? T : lim) * 4 : 0, kBufferFlags);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const f32x4_t q = buffer_load_f32x4(rsrc, 16 * tid, k * (T / 8) * 4, AUX);
+      const f32x4_t q = buffer_load_f32x4<AUX>(rsrc, 16 * tid, k * (T / 8) * 4);
       v[4 * k + 0] = q.x;
       v[4 * k + 1] = q.y;
       v[4 * k + 2] = q.z;
@@ -346,12 +356,27 @@ void srht_tiled_kernel(TiledLaunch L) {
     const bool last_of_col = RAG || !has_next || (col != cur_col) || new_job;
     if (last_of_col) {
       const SketchJob& J = sjob<BATCH>(L, cur_job);
-      float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
+      // a column whose every tile this workgroup transformed needs no reduce:
+      // its sums go out scaled, as the reduce would write them
+      const bool whole = RAG ? J.tiles == 0
+                             : (piece == 0 && (int32_t)cur_tile + 1 == (int32_t)J.tiles && !J.rag);
+      if (whole) {
+        float* out = cur_col < J.d ? J.SA + (int64_t)cur_col * J.ldsa
+                                   : J.SB + (int64_t)(cur_col - J.d) * J.ldsb;
 #pragma unroll
-      for (int s = 0; s < SPT; ++s) {
-        const int l = tid + s * NT;
-        if (l < count) dst[l] = acc[s];
-        acc[s] = 0.0f;
+        for (int s = 0; s < SPT; ++s) {
+          const int l = tid + s * NT;
+          if (l < count) out[l] = (float)((double)acc[s] * J.inv_sqrt_r);
+          acc[s] = 0.0f;
+        }
+      } else {
+        float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+          const int l = tid + s * NT;
+          if (l < count) dst[l] = acc[s];
+          acc[s] = 0.0f;
+        }
       }
       piece = RAG ? piece : 0;
     }
@@ -395,12 +420,14 @@ __device__ __forceinline__ void store_out(const SketchJob& J, int col, int l, fl
 __device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t items,
                                            int64_t grid) {
   if (col >= J.ncols) return;
-  const int count = *J.count;
   int64_t npieces = 0;
   if (J.tiles > 0) {
     const int64_t first = J.item0 + (int64_t)col * J.tiles;
     npieces = owner_of(first + J.tiles - 1, items, grid) - owner_of(first, items, grid) + 1;
   }
+  // one piece in all: the transform wrote the column itself
+  if (npieces + (J.rag ? 1 : 0) == 1) return;
+  const int count = *J.count;
   const float* base = J.partials + (int64_t)col * J.pieces * J.r_cap;
   // the block's threads stride over the kept rows of the column
   for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < count; l += gridDim.x * blockDim.x) {
@@ -701,11 +728,16 @@ __global__ __launch_bounds__(kMfmaThreads) void srht_mfma_kernel(TiledLaunch L) 
     const bool last_of_col = RAG || (next >= item_end) || (col != cur_col);
     if (last_of_col) {
       const SketchJob& J = L.one;
-      float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
+      // a column whose every tile this workgroup transformed needs no reduce
+      const bool whole = RAG ? J.tiles == 0
+                             : (piece == 0 && (int32_t)cur_tile + 1 == (int32_t)J.tiles && !J.rag);
+      float* dst = whole ? (cur_col < J.d ? J.SA + (int64_t)cur_col * J.ldsa
+                                          : J.SB + (int64_t)(cur_col - J.d) * J.ldsb)
+                         : J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
 #pragma unroll
       for (int s = 0; s < SPT; ++s) {
         const int li = tid + s * NT;
-        if (li < count) dst[li] = acc[s];
+        if (li < count) dst[li] = whole ? (float)((double)acc[s] * J.inv_sqrt_r) : acc[s];
         acc[s] = 0.0f;
       }
       piece = RAG ? piece : 0;

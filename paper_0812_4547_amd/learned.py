@@ -33,6 +33,26 @@ def init_params(seed: int, device="cuda") -> torch.Tensor:
     return torch.from_numpy(theta).to(device)
 
 
+def save_checkpoint(mlp: rnnls.Mlp, path: str) -> None:
+    """The perceptron's FP32 parameters, Adam moments and step count to an
+    .npz file (plain arrays: loadable without unpickling).  The BF16 weights
+    are not stored: they are the rounding of the parameters."""
+    np.savez(path, theta=mlp.theta.cpu().numpy(), m=mlp.m.cpu().numpy(),
+             v=mlp.v.cpu().numpy(), step=np.int64(mlp.step))
+
+
+def load_checkpoint(path: str, device="cuda") -> rnnls.Mlp:
+    """An Mlp restored from save_checkpoint: the same parameters, BF16 weights
+    (rounded again on the device), Adam moments and step, so training
+    continues exactly where it stopped."""
+    with np.load(path, allow_pickle=False) as z:
+        mlp = rnnls.Mlp(torch.from_numpy(z["theta"].astype(np.float32)).to(device))
+        mlp.m.copy_(torch.from_numpy(z["m"].astype(np.float32)))
+        mlp.v.copy_(torch.from_numpy(z["v"].astype(np.float32)))
+        mlp.step = int(z["step"])
+    return mlp
+
+
 def shapes(count: int, seed: int, log2_n=(14.0, 18.0)):
     return workloads.batch_shapes(count=count, seed=seed, log2_n=log2_n)
 

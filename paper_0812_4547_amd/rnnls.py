@@ -38,7 +38,8 @@ EXPORTS = (
     "rnnls_batch_warm_used", "rnnls_timing_enable", "rnnls_timing_read",
     "rnnls_set_tuning", "rnnls_get_tuning", "rnnls_stream_read_blocks", "rnnls_stream_read",
     "rnnls_boost_workspace_bytes", "rnnls_rand_nnls_boost", "rnnls_rand_box",
-    "rnnls_rand_nnls_noalloc", "rnnls_batch_proposal",
+    "rnnls_rand_nnls_noalloc", "rnnls_batch_proposal", "rnnls_tuning_cache_entries",
+    "rnnls_tuning_cache_clear", "rnnls_tuning_cache_save", "rnnls_tuning_cache_load",
 )
 MLP_FEATURES, MLP_WIDTH, MLP_PARAMS, MLP_BF16_WEIGHTS = 8, 128, 17793, 17536
 TIMER_SKETCH, TIMER_MOMENTS, TIMER_SOLVE, TIMER_STREAM_READ, TIMER_RESIDUAL = 0, 1, 2, 3, 4
@@ -112,6 +113,10 @@ _SIGS = {
     "rnnls_batch_set_model": ([_p, _p, _p, ctypes.c_float], ctypes.c_int),
     "rnnls_batch_warm_used": ([_p, _p, _p], ctypes.c_int),
     "rnnls_batch_proposal": ([_p, _p, _p], ctypes.c_int),
+    "rnnls_tuning_cache_entries": ([], ctypes.c_int),
+    "rnnls_tuning_cache_clear": ([], ctypes.c_int),
+    "rnnls_tuning_cache_save": ([ctypes.c_char_p], ctypes.c_int),
+    "rnnls_tuning_cache_load": ([ctypes.c_char_p], ctypes.c_int),
     "rnnls_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "rnnls_timing_read": ([_i32, _p, _p], ctypes.c_int),
     "rnnls_set_tuning": ([_p], ctypes.c_int),
@@ -642,3 +647,22 @@ def get_tuning() -> tuple[int, int]:
     t = Tuning()
     _check(load().rnnls_get_tuning(ctypes.byref(t)), "rnnls_get_tuning")
     return t.srht_log_tile, t.srht_wgs_per_cu
+
+
+def tuning_cache_entries() -> int:
+    """Entries of the autotuner's process-wide cache (one per plan shape)."""
+    return int(load().rnnls_tuning_cache_entries())
+
+
+def tuning_cache_clear() -> None:
+    _check(load().rnnls_tuning_cache_clear(), "rnnls_tuning_cache_clear")
+
+
+def tuning_cache_save(path: str) -> None:
+    """Write the autotuner's cache to a text file."""
+    _check(load().rnnls_tuning_cache_save(os.fsencode(path)), "rnnls_tuning_cache_save")
+
+
+def tuning_cache_load(path: str) -> None:
+    """Merge a file written by tuning_cache_save into the autotuner's cache."""
+    _check(load().rnnls_tuning_cache_load(os.fsencode(path)), "rnnls_tuning_cache_load")

@@ -138,3 +138,31 @@ def test_rand_box_argument_checks(lib):
     assert run(lo=None) == -8
     assert run(hi=None) == -9
     assert run(x=None) == -10
+
+
+def test_tuning_cache_save_and_load(lib, tmp_path):
+    """The autotuner's cache: a file of entries merges in, is written back
+    identically, a malformed file merges nothing (no device work)."""
+    rnnls.tuning_cache_clear()
+    assert rnnls.tuning_cache_entries() == 0
+    src = tmp_path / "tune.txt"
+    src.write_text("00000000000000ab 14 2\n0123456789abcdef 13 4\n")
+    rnnls.tuning_cache_load(str(src))
+    assert rnnls.tuning_cache_entries() == 2
+    out = tmp_path / "out.txt"
+    rnnls.tuning_cache_save(str(out))
+    assert out.read_text() == src.read_text()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("00000000000000cd 14 2\nnot a line\n")
+    with pytest.raises(rnnls.RnnlsError):
+        rnnls.tuning_cache_load(str(bad))
+    odd = tmp_path / "odd.txt"
+    odd.write_text("00000000000000ce 11 3\n")  # not a tile shape the autotuner tries
+    with pytest.raises(rnnls.RnnlsError):
+        rnnls.tuning_cache_load(str(odd))
+    assert rnnls.tuning_cache_entries() == 2
+    with pytest.raises(rnnls.RnnlsError):
+        rnnls.tuning_cache_load(str(tmp_path / "missing.txt"))
+    assert lib.rnnls_tuning_cache_save(None) == -1
+    rnnls.tuning_cache_clear()
+    assert rnnls.tuning_cache_entries() == 0

@@ -148,3 +148,28 @@ def test_batch_rejects_invalid_problem():
     b = torch.from_numpy(p.b).cuda()
     with pytest.raises(rnnls.RnnlsError, match="problem 1"):
         rnnls.Batch([(A, b, 100, 1), (A, b, 9000, 2)])  # r >= n'
+
+
+def test_autotune_choice_is_cached_by_plan_shape(tmp_path):
+    """A second plan with the same shapes takes the first plan's choice from
+    the cache (no new entry); the cache survives a save / clear / load."""
+    rnnls.tuning_cache_clear()
+    probs, b1 = _make_batch(SMALL_BATCH[:5], batch_seed=14)
+    c1 = b1.autotune()
+    assert rnnls.tuning_cache_entries() == 1
+    probs2, b2 = _make_batch(SMALL_BATCH[:5], batch_seed=15)  # same shapes, other data
+    assert b2.autotune() == c1 and rnnls.tuning_cache_entries() == 1
+    path = str(tmp_path / "tune.txt")
+    rnnls.tuning_cache_save(path)
+    rnnls.tuning_cache_clear()
+    rnnls.tuning_cache_load(path)
+    assert rnnls.tuning_cache_entries() == 1
+    probs3, b3 = _make_batch(SMALL_BATCH[:6], batch_seed=16)  # other shapes: timed, new entry
+    b3.autotune()
+    assert rnnls.tuning_cache_entries() == 2
+    b2.run()
+    torch.cuda.synchronize()
+    _check_against_oracle(probs2, b2, which={0, 3})
+    for b in (b1, b2, b3):
+        b.close()
+    rnnls.tuning_cache_clear()

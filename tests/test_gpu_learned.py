@@ -253,3 +253,27 @@ def test_rejected_warm_start_falls_back_to_the_cold_solve():
         ref = nnls.lawson_hanson(SA, Sb)
         assert abs(nnls.relative_residual_gap(SA, Sb, batch.x[i].cpu().numpy(), ref.x)) <= 1e-6
     batch.close()
+
+
+def test_checkpoint_restores_parameters_and_adam_state(tmp_path):
+    """Weights and Adam moments saved after two steps and loaded into a new
+    perceptron: the same forward pass, and a third step lands on the same
+    parameters in both."""
+    theta, X, y = _net_case(2000, 31)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    a = rnnls.Mlp(torch.from_numpy(theta).cuda())
+    for _ in range(2):
+        a.train_step(Xd, yd, 1e-2)
+    path = str(tmp_path / "mlp.npz")
+    learned.save_checkpoint(a, path)
+    b = learned.load_checkpoint(path)
+    assert b.step == a.step == 2
+    assert torch.equal(a.theta, b.theta) and torch.equal(a.wb, b.wb)
+    assert torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+    pa, _ = a.forward(Xd)
+    pb, _ = b.forward(Xd)
+    assert torch.equal(pa, pb)
+    a.train_step(Xd, yd, 1e-2)
+    b.train_step(Xd, yd, 1e-2)
+    torch.cuda.synchronize()
+    assert torch.equal(a.theta, b.theta)
