@@ -474,7 +474,9 @@ int run_all(rnnls_batch& B, hipStream_t s) {
   if (rc) return rc;
   rc = run_sketch(B, s);
   if (rc) return rc;
-  rc = launch_moments_batch(B.mdev, B.count, B.m_chunks, B.chunk_map_dev,
+  int max_cols = 0;
+  for (int i = 0; i < B.count; ++i) max_cols = std::max(max_cols, B.probs[i].d + 1);
+  rc = launch_moments_batch(B.mdev, B.count, max_cols, B.m_chunks, B.chunk_map_dev,
                             (int64_t)B.ent_map.size(), B.ent_map_dev, s);
   if (rc) return rc;
   // with a model, each Lawson-Hanson workgroup first computes its problem's

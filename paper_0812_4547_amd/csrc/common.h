@@ -274,7 +274,7 @@ struct MomentsPlan {
   int64_t m;
   int d, k;
   int chunks, nbA, nb, pairs;
-  int lds;  // one right-hand side: all block pairs from each row chunk in LDS
+  int lds;  // all block pairs from each row chunk in LDS: 1 (d + k <= 112), 2 (<= 129)
 };
 // max_chunks > 0 caps the row chunks (batches spread over problems instead)
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);
@@ -282,8 +282,8 @@ size_t moments_scratch_bytes(const MomentsPlan& p);
 int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s);
 // one right-hand side per job; chunk_job: job of every row segment of the
 // launch; ent_job: job of every block of 256 reduce entries (jobs with more
-// than one segment only)
-int launch_moments_batch(const MomentJob* dev, int njobs, int64_t segments,
+// than one segment only); max_cols: the largest d + 1 of the jobs
+int launch_moments_batch(const MomentJob* dev, int njobs, int max_cols, int64_t segments,
                          const int32_t* chunk_job, int64_t ent_blocks, const int32_t* ent_job,
                          hipStream_t s);
 int64_t moments_entries(const MomentsPlan& p);

@@ -24,11 +24,13 @@
 // With a single right-hand side (d + k <= 129 columns) a second kernel reads
 // every row once: the rows of a segment go through LDS in chunks of 64 rows
 // of all d + k columns (double-buffered: the next chunk's loads are in flight
-// while the current one is multiplied), and the workgroup's sixteen wavefronts
-// form every block pair of the problem from each chunk, each wavefront its
-// own pairs in its own accumulators.  Row segments (enough to fill the device,
-// at least 256 rows each) write partial blocks that the reduce kernel adds in
-// a fixed order, as the chunks of the first kernel.
+// while the current one is multiplied), and the workgroup's wavefronts form
+// every block pair of the problem from each chunk, each wavefront its own
+// pairs in its own accumulators (eight wavefronts and two workgroups per CU
+// up to 112 columns, sixteen wavefronts and one workgroup up to 129).  Row
+// segments (enough to fill the device, at least 256 rows each) write partial
+// blocks that the reduce kernel adds in a fixed order, as the chunks of the
+// first kernel.
 //
 // One problem travels by value in the kernel arguments; a batch of problems
 // (different m, d) reads its descriptors from a device table.
@@ -188,27 +190,35 @@ __global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const
 }
 
 // ---- every block pair of a problem from one pass over its rows
-constexpr int kLdsCols = 129;   // d + k
+constexpr int kLdsCols = 129;   // d + k (the wide form)
+constexpr int kLdsColsN = 112;  // d + k of the narrow form (seven blocks)
 constexpr int kLdsRows = 64;    // rows per chunk
 constexpr int kLdsCs = kLdsRows + 4;  // column stride in LDS (padded against bank conflicts)
-constexpr int kLdsNW = 16;      // wavefronts per workgroup
-constexpr int kLdsMaxPairs = 45;  // 9 blocks of 16: 8 * 9 / 2 + 9
-constexpr int kLdsPW = (kLdsMaxPairs + kLdsNW - 1) / kLdsNW;  // pairs per wavefront
-constexpr int kLdsLoads = (kLdsCols * (kLdsRows / 4) + kLdsNW * 64 - 1) / (kLdsNW * 64);
+
+// COLS columns at most, NW wavefronts: block pairs per wavefront and float4
+// loads per thread per chunk
+template <int COLS, int NW>
+struct LdsShape {
+  static constexpr int nb = (COLS + kBlk - 1) / kBlk;
+  static constexpr int pw = (nb * (nb + 1) / 2 + NW - 1) / NW;
+  static constexpr int half = (pw + 1) / 2;  // pairs whose operands are loaded together
+  static constexpr int loads = (COLS * (kLdsRows / 4) + NW * 64 - 1) / (NW * 64);
+};
 
 // Segment `seg` of the job: rows [m seg / S, m (seg+1) / S) (S = J.chunks).
-template <bool BATCH>
-__global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
-                                                               const MomentJob* jobs,
-                                                               const int32_t* jmap) {
-  __shared__ __attribute__((aligned(16))) float xs[2][kLdsCols * kLdsCs];
+template <bool BATCH, int COLS, int NW>
+__device__ __forceinline__ void gram_lds_body(const MomentJob& one, const MomentJob* jobs,
+                                              const int32_t* jmap) {
+  using L = LdsShape<COLS, NW>;
+  constexpr int PW = L::pw;
+  __shared__ __attribute__((aligned(16))) float xs[2][COLS * kLdsCs];
   int64_t seg64;
   const MomentJob J =
       mjob<BATCH>(one, jobs, jmap, blockIdx.x, blockIdx.x, &MomentJob::chunk0, seg64);
   const int seg = (int)seg64;
   const int t = threadIdx.x;
   const int lane = t & 63;
-  const int wv = t >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int kq = lane >> 4;
   const int D1 = J.d + J.k;
   const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
@@ -219,38 +229,38 @@ __global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
                    (J.k == 0 || (((uintptr_t)J.F % 16 == 0) && (J.ldf % 4 == 0)));
 
   // this thread's share of a chunk's loads: float4 e = column e / 16, rows 4 (e % 16) ..
-  auto fetch = [&](int64_t c0, float4 (&v)[kLdsLoads]) __attribute__((always_inline)) {
+  auto fetch = [&](int64_t c0, float4 (&v)[L::loads]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < kLdsLoads; ++u) {
-      const int e = t + u * kLdsNW * 64;
+    for (int u = 0; u < L::loads; ++u) {
+      const int e = t + u * NW * 64;
       const int col = e >> 4;
       v[u] = (col < D1) ? load_rows4(col_ptr(J, col), c0 + 4 * (e & 15), hi, vec)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  auto stash = [&](float* buf, const float4 (&v)[kLdsLoads]) __attribute__((always_inline)) {
+  auto stash = [&](float* buf, const float4 (&v)[L::loads]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < kLdsLoads; ++u) {
-      const int e = t + u * kLdsNW * 64;
+    for (int u = 0; u < L::loads; ++u) {
+      const int e = t + u * NW * 64;
       const int col = e >> 4;
       if (col < D1) *reinterpret_cast<float4*>(buf + col * kLdsCs + 4 * (e & 15)) = v[u];
     }
   };
 
-  // this wavefront's block pairs: p = wv, wv + 8, ...
-  int pbi[kLdsPW], pbj[kLdsPW];
+  // this wavefront's block pairs: p = wv, wv + NW, ... (uniform)
+  int pbi[PW], pbj[PW];
 #pragma unroll
-  for (int s = 0; s < kLdsPW; ++s) {
-    const int p = wv + s * kLdsNW;
+  for (int s = 0; s < PW; ++s) {
+    const int p = wv + s * NW;
     if (p < J.pairs) pair_blocks(p, J.nbA, J.nb, pbi[s], pbj[s]);
     else pbi[s] = pbj[s] = 0;
   }
-  v4d acc[kLdsPW];
+  v4d acc[PW];
 #pragma unroll
-  for (int s = 0; s < kLdsPW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < PW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
   double aabs = 0.0;  // column t's 1-norm share (t < d)
 
-  float4 nxt[kLdsLoads];
+  float4 nxt[L::loads];
   int b = 0;
   if (r0 < hi) {
     fetch(r0, nxt);
@@ -265,47 +275,43 @@ __global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
 #pragma unroll 8
       for (int r = 0; r < kLdsRows; ++r) aabs += fabs((double)X[t * kLdsCs + r]);
     }
-    // per 16-row group: every pair's operands first, then the four k-steps
-    // with the pairs interleaved, so consecutive matrix-core instructions
-    // write different accumulators (no dependent chain)
+    // per 16-row group and half of the wavefront's pairs: the operands
+    // first, then the four k-steps with the pairs interleaved, so that
+    // consecutive matrix-core instructions write different accumulators
 #pragma unroll
     for (int g = 0; g < kLdsRows / 16; ++g) {
-      float4 xa[kLdsPW], xb[kLdsPW];
 #pragma unroll
-      for (int s = 0; s < kLdsPW; ++s) {
-        xa[s] = *reinterpret_cast<const float4*>(
-            X + (pbi[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
-        xb[s] = *reinterpret_cast<const float4*>(
-            X + (pbj[s] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+      for (int h0 = 0; h0 < PW; h0 += L::half) {
+        float4 xa[L::half], xb[L::half];
+#pragma unroll
+        for (int s = 0; s < L::half; ++s) {
+          const int ps = h0 + s < PW ? h0 + s : PW - 1;
+          xa[s] = *reinterpret_cast<const float4*>(
+              X + (pbi[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+          xb[s] = *reinterpret_cast<const float4*>(
+              X + (pbj[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+        }
+#define RNNLS_KSTEP(C)                                                                  \
+  _Pragma("unroll") for (int s = 0; s < L::half; ++s) {                                 \
+    const int ps = h0 + s;                                                              \
+    if (ps < PW && wv + ps * NW < J.pairs)                                          \
+      acc[ps] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].C, (double)xb[s].C, \
+                                                     acc[ps], 0, 0, 0);                 \
+  }
+        RNNLS_KSTEP(x)
+        RNNLS_KSTEP(y)
+        RNNLS_KSTEP(z)
+        RNNLS_KSTEP(w)
+#undef RNNLS_KSTEP
       }
-#pragma unroll
-      for (int s = 0; s < kLdsPW; ++s)
-        if (wv + s * kLdsNW < J.pairs)
-          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].x, (double)xb[s].x, acc[s],
-                                                        0, 0, 0);
-#pragma unroll
-      for (int s = 0; s < kLdsPW; ++s)
-        if (wv + s * kLdsNW < J.pairs)
-          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].y, (double)xb[s].y, acc[s],
-                                                        0, 0, 0);
-#pragma unroll
-      for (int s = 0; s < kLdsPW; ++s)
-        if (wv + s * kLdsNW < J.pairs)
-          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].z, (double)xb[s].z, acc[s],
-                                                        0, 0, 0);
-#pragma unroll
-      for (int s = 0; s < kLdsPW; ++s)
-        if (wv + s * kLdsNW < J.pairs)
-          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].w, (double)xb[s].w, acc[s],
-                                                        0, 0, 0);
     }
     if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
     b ^= 1;
   }
   // results: partial blocks of the segment, or the final G, Q, c and 1-norms
 #pragma unroll
-  for (int s = 0; s < kLdsPW; ++s) {
-    const int p = wv + s * kLdsNW;
+  for (int s = 0; s < PW; ++s) {
+    const int p = wv + s * NW;
     if (p >= J.pairs) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -332,6 +338,24 @@ __global__ __launch_bounds__(kLdsNW * 64) void gram_lds_kernel(MomentJob one,
     if (J.chunks > 1) J.part_abs[(int64_t)seg * J.d + t] = aabs;
     else J.colabs[t] = aabs;
   }
+}
+
+
+// up to 112 columns: eight wavefronts, two workgroups per CU (LDS and
+// registers sized for it)
+constexpr int kLdsNWN = 8;
+template <bool BATCH>
+__global__ __launch_bounds__(kLdsNWN * 64) __attribute__((amdgpu_waves_per_eu(4))) void
+gram_lds_kernel(MomentJob one, const MomentJob* jobs, const int32_t* jmap) {
+  gram_lds_body<BATCH, kLdsColsN, kLdsNWN>(one, jobs, jmap);
+}
+// up to 129 columns: sixteen wavefronts, one workgroup per CU
+constexpr int kLdsNWW = 16;
+template <bool BATCH>
+__global__ __launch_bounds__(kLdsNWW * 64) void gram_lds_wide_kernel(MomentJob one,
+                                                                     const MomentJob* jobs,
+                                                                     const int32_t* jmap) {
+  gram_lds_body<BATCH, kLdsCols, kLdsNWW>(one, jobs, jmap);
 }
 
 // One thread per output entry, summing the chunks in order (deterministic;
@@ -396,7 +420,7 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   p.nbA = (d + kBlk - 1) / kBlk;
   p.nb = (d + k + kBlk - 1) / kBlk;
   p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
-  p.lds = d + k <= kLdsCols ? 1 : 0;
+  p.lds = d + k <= kLdsColsN ? 1 : (d + k <= kLdsCols ? 2 : 0);
   if (p.lds) {
     // segments of at least 256 rows, at most two workgroups per CU (batches
     // cap them per problem: many problems fill the device together)
@@ -440,8 +464,11 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   const dim3 grid(p.chunks, p.pairs);
-  if (p.lds)
-    hipLaunchKernelGGL(gram_lds_kernel<false>, dim3(p.chunks), dim3(kLdsNW * 64), 0, s, j,
+  if (p.lds == 1)
+    hipLaunchKernelGGL(gram_lds_kernel<false>, dim3(p.chunks), dim3(kLdsNWN * 64), 0, s, j,
+                       (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  else if (p.lds == 2)
+    hipLaunchKernelGGL(gram_lds_wide_kernel<false>, dim3(p.chunks), dim3(kLdsNWW * 64), 0, s, j,
                        (const MomentJob*)nullptr, (const int32_t*)nullptr);
   else if (p.m / p.chunks > 2048)  // long chunks: more wavefronts share each one's rows
     hipLaunchKernelGGL((gram_mfma_kernel<false, 16>), grid, dim3(16 * 64), 0, s, j,
@@ -462,15 +489,20 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
 // problem in one launch (chunk_job: job of every segment), then the fixed-
 // order sums of the problems with more than one segment (ent_job: job of
 // every block of 256 entries; ent_blocks of them).
-int launch_moments_batch(const MomentJob* dev, int njobs, int64_t segments,
+int launch_moments_batch(const MomentJob* dev, int njobs, int max_cols, int64_t segments,
                          const int32_t* chunk_job, int64_t ent_blocks, const int32_t* ent_job,
                          hipStream_t s) {
   if (njobs < 1) return RNNLS_OK;
   MomentJob none{};
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
-  hipLaunchKernelGGL(gram_lds_kernel<true>, dim3((unsigned)segments), dim3(kLdsNW * 64), 0, s,
-                     none, dev, chunk_job);
+  if (max_cols > kLdsCols) return RNNLS_E_UNSUPPORTED;
+  if (max_cols <= kLdsColsN)
+    hipLaunchKernelGGL(gram_lds_kernel<true>, dim3((unsigned)segments), dim3(kLdsNWN * 64), 0, s,
+                       none, dev, chunk_job);
+  else
+    hipLaunchKernelGGL(gram_lds_wide_kernel<true>, dim3((unsigned)segments), dim3(kLdsNWW * 64), 0,
+                       s, none, dev, chunk_job);
   if (ent_blocks > 0)
     hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)ent_blocks), dim3(256), 0, s,
                        none, dev, ent_job);

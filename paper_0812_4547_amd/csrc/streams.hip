@@ -131,7 +131,7 @@ __device__ __forceinline__ void segment_words(int m, int64_t seg, int64_t* w0, i
 
 // Signs + kept mask + kept count of one segment.  Scratch of a job: kept
 // words [n'/32], segment counts [segments].
-template <bool BATCH>
+template <bool BATCH, bool KEPT = true>
 __global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJob one,
                                                                          const StreamJob* jobs,
                                                                          const int32_t* jmap) {
@@ -159,10 +159,12 @@ __global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJ
     uint32_t kbits = 0, sbits = 0, nat = 0;
     if (w < w1) {
       const uint64_t base = (uint64_t)w * 32ull;
+      if (KEPT) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint64_t j = base + (uint64_t)(8 * part + k);
-        if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << (8 * part + k);
+        for (int k = 0; k < 8; ++k) {
+          const uint64_t j = base + (uint64_t)(8 * part + k);
+          if ((int64_t)j < n_pad && kept(rule, (uint32_t)j)) kbits |= 1u << (8 * part + k);
+        }
       }
       sign_bits(J, w, part, sign_key, n_pad, nt, kstride, export_nat, &sbits, &nat);
     }
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJ
     }
     if (part == 0 && w < w1) {
       J.sign_words[w] = sbits;
-      kept_words[w] = kbits;
+      if (KEPT) kept_words[w] = kbits;
       if (J.sign_export && J.sign_export != J.sign_words) J.sign_export[w] = export_nat ? nat : sbits;
       count += __popc(kbits);
     }
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kScanThreads) void streams_scan_rows_kernel(StreamJ
   for (int off = 1; off < 64; off <<= 1) count += __shfl_xor(count, off, 64);
   if ((threadIdx.x & 63) == 0) wave_counts[threadIdx.x >> 6] = count;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (KEPT && threadIdx.x == 0) {
     int total = 0;
 #pragma unroll
     for (int w = 0; w < kScanThreads / 64; ++w) total += wave_counts[w];
@@ -239,6 +241,8 @@ __global__ __launch_bounds__(kWriteThreads) void streams_write_rows_kernel(Strea
   }
 }
 
+__device__ void exact_rows(const StreamJob& J, uint32_t* smem);
+
 // Exact mode in one launch.  Workgroup 0: the kept rows; workgroups 1..: the
 // sign words, kExactWordsPerBlock each.  Dynamic LDS: 2 r_cap + 2 kExactSegs
 // uint32.
@@ -270,10 +274,20 @@ __global__ __launch_bounds__(kExactThreads) void streams_exact_kernel(StreamJob 
     }
     return;
   }
-  uint32_t* vals = ex_smem;                 // pi(k), k < r
-  uint32_t* out = ex_smem + J.r_cap;        // the same, grouped by segment
-  uint32_t* cnt = ex_smem + 2 * J.r_cap;    // per-segment counts, then cursors (ends)
-  uint32_t* off = cnt + kExactSegs;         // exclusive offsets (starts)
+  exact_rows(J, ex_smem);
+}
+
+// The kept rows of exact mode, {pi(k) : k < r} in ascending order, by one
+// workgroup of kExactThreads: the r values are counted per segment of n'/1024
+// rows, placed by the segments' offsets, and each written at its segment's
+// start plus the number of smaller values in its segment.  smem: 2 r_cap +
+// 2 kExactSegs words.
+__device__ void exact_rows(const StreamJob& J, uint32_t* smem) {
+  const int t = threadIdx.x;
+  uint32_t* vals = smem;                 // pi(k), k < r
+  uint32_t* out = smem + J.r_cap;        // the same, grouped by segment
+  uint32_t* cnt = smem + 2 * J.r_cap;    // per-segment counts, then cursors (ends)
+  uint32_t* off = cnt + kExactSegs;      // exclusive offsets (starts)
   __shared__ uint32_t wave_tot[kExactThreads / 64];
   const PermKeys keys = make_perm_keys(J.seed, J.m);
   const int shift = J.m > 10 ? J.m - 10 : 0;  // segment of row x: x >> shift
@@ -333,6 +347,15 @@ __global__ __launch_bounds__(kExactThreads) void streams_exact_kernel(StreamJob 
   }
 }
 
+// Batches in exact mode: the kept rows of problem blockIdx.x (one workgroup
+// each); the sign words come from the scan kernel without its kept test.
+__global__ __launch_bounds__(kExactThreads) void streams_exact_rows_batch_kernel(
+    const StreamJob* jobs) {
+  extern __shared__ uint32_t exb_smem[];
+  const StreamJob J = jobs[blockIdx.x];
+  exact_rows(J, exb_smem);
+}
+
 }  // namespace
 
 size_t streams_scratch_words(int64_t n_pad) {
@@ -381,12 +404,37 @@ int launch_streams_batch(const StreamJob* host, const StreamJob* dev, int njobs,
   const StreamJob& last = host[njobs - 1];
   const unsigned nb = (unsigned)(last.blk0 + streams_blocks(last.m));
   StreamJob none{};
+  // exact mode: the kept rows from the forward bijection (r values per
+  // problem) instead of testing every row through its inverse
+  bool exact = true;
+  int max_cap = 0;
+  for (int i = 0; i < njobs; ++i) {
+    exact = exact && host[i].mode == RNNLS_SAMPLE_EXACT && host[i].r <= host[i].r_cap &&
+            host[i].r_cap <= kExactMaxRows;
+    max_cap = host[i].r_cap > max_cap ? host[i].r_cap : max_cap;
+  }
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_STREAMS, s, &tok);
-  hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kScanThreads), 0, s, none,
-                     dev, blk_job);
-  hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kWriteThreads), 0, s, none,
-                     dev, blk_job);
+  if (exact) {
+    const size_t lds = sizeof(uint32_t) * (2 * (size_t)max_cap + 2 * kExactSegs);
+    static std::atomic<int> lds_limit_set{0};
+    if (lds > 65536 && !lds_limit_set.load()) {
+      const int max_bytes = (int)(sizeof(uint32_t) * (2 * (size_t)kExactMaxRows + 2 * kExactSegs));
+      if (hipFuncSetAttribute((const void*)streams_exact_rows_batch_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes) != hipSuccess)
+        return RNNLS_E_HIP;
+      lds_limit_set.store(1);
+    }
+    hipLaunchKernelGGL((streams_scan_rows_kernel<true, false>), dim3(nb), dim3(kScanThreads), 0,
+                       s, none, dev, blk_job);
+    hipLaunchKernelGGL(streams_exact_rows_batch_kernel, dim3(njobs), dim3(kExactThreads), lds, s,
+                       dev);
+  } else {
+    hipLaunchKernelGGL(streams_scan_rows_kernel<true>, dim3(nb), dim3(kScanThreads), 0, s, none,
+                       dev, blk_job);
+    hipLaunchKernelGGL(streams_write_rows_kernel<true>, dim3(nb), dim3(kWriteThreads), 0, s, none,
+                       dev, blk_job);
+  }
   timer_end(RNNLS_TIMER_STREAMS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
