@@ -176,26 +176,33 @@ __device__ __forceinline__ int pop_lowest(uint64_t (&m)[H]) {
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // The padded order DP (64 or 128) fixes the workgroup: 256 threads in a 16 x
-// 16 grid, each holding a (DP/16) x (DP/16) block of the tableau.
-__host__ __device__ constexpr int lh_threads(int) { return 256; }
+// 16 grid, each holding a 4 x 4 block of the 64 x 64 tableau, or 512 threads
+// (two wavefronts per SIMD) in a 32 x 16 grid, each holding a 4 x 8 block of
+// the 128 x 128 tableau (an 8 x 8 block per thread of 256 did not fit the
+// vector registers: part of it lived in the accumulation registers and was
+// copied back and forth at every sweep).
+__host__ __device__ constexpr int lh_threads(int dp) { return dp > kW ? 512 : 256; }
 __host__ __device__ constexpr int lh_waves(int dp) { return lh_threads(dp) / kW; }
 inline int padded_order(int d) { return d <= kW ? kW : 2 * kW; }
 
 // Scratch of the learned proposal (before Q is staged, in Q's place):
 // the features (128 x 8 FP32); the first hidden layer of a chunk of 32
 // columns (32 rows of 128 FP32, row stride 132), whose space first holds
-// 1/sqrt(G_jj) and the cosines (FP64, 128 each); W2 (128 x 128 BF16,
-// [unit][input], row stride 132); W1 (128 x 8 BF16); output partials
+// 1/sqrt(G_jj), the cosines (FP64, 128 each) and the four quarters' partial
+// feature sums (FP64, 4 x 3 x 128); W2 (128 x 128 BF16,
+// [unit][input], row stride 132); output partials
 // (4 wavefronts x 32 FP32); flags.
 constexpr int kPropCols = 32;
 constexpr int kH1Ld = 132;
 constexpr int kW2Ld = 132;
 constexpr size_t kPropF = 0, kPropH1 = kPropF + 128 * 8 * 4,
                  kPropIsd = kPropH1, kPropCos = kPropIsd + 128 * 8,
-                 kPropW2 = kPropH1 + kPropCols * kH1Ld * 4, kPropW1 = kPropW2 + 128 * kW2Ld * 2,
-                 kPropZ = kPropW1 + 128 * 8 * 2, kPropFl = kPropZ + 4 * kPropCols * 4,
+                 kPropPart = kPropCos + 128 * 8,
+                 kPropW2 = kPropH1 + kPropCols * kH1Ld * 4, kPropZ = kPropW2 + 128 * kW2Ld * 2,
+                 kPropFl = kPropZ + 4 * kPropCols * 4,
                  kPropBytes = kPropFl + 128;
-static_assert(kPropCos + 128 * 8 <= kPropW2, "cosines fit in the hidden-layer space");
+static_assert(kPropPart + 4 * 3 * 128 * 8 <= kPropW2,
+              "cosines and feature partials fit in the hidden-layer space");
 
 // partial sums (one row of 2*kW per wavefront), two pivot-row buffers
 // (2 x 128), Q (d x ld) -- or the proposal's scratch before Q, if larger
@@ -213,9 +220,10 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
-// The learned passive-set proposal of one problem, by the whole workgroup
-// (256 threads), from its Gram form: the per-column features f0..f7 (FP64,
-// stored FP32; definitions in learned.hip) and the perceptron
+// The learned passive-set proposal of one problem, by the workgroup (the
+// network on its first 256 threads), from its Gram form: the per-column features f0..f7 (FP64,
+// stored FP32; definitions in learned.hip; the sums over rows in four
+// quarters added in order) and the perceptron
 // p = sigmoid(w3 . relu(W2 relu(W1 f + b1) + b2) + b3) with BF16 weights and
 // FP32 accumulation.  The first layer runs on the vector units (thread t: the
 // eight units 8 (t % 16) .. of column t / 16 of a 32-column chunk); the second
@@ -232,26 +240,35 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
                         const double (&qv)[H], const double (&dq)[H], const bool (&valid)[H],
                         char* scr, uint64_t (&prop)[H]) {
   typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NTH = lh_threads(H * kW);  // the workgroup; the network uses the first 256
   const int t = threadIdx.x;
   const int lane = t & (kW - 1);
   const int wv = t / kW;
+  const bool net = t < 256;
   float* F = reinterpret_cast<float*>(scr + kPropF);
   double* isd = reinterpret_cast<double*>(scr + kPropIsd);
   double* cosv = reinterpret_cast<double*>(scr + kPropCos);
+  double* part = reinterpret_cast<double*>(scr + kPropPart);
   float* h1 = reinterpret_cast<float*>(scr + kPropH1);
   uint16_t* w2s = reinterpret_cast<uint16_t*>(scr + kPropW2);
-  uint16_t* w1s = reinterpret_cast<uint16_t*>(scr + kPropW1);
   float* zp = reinterpret_cast<float*>(scr + kPropZ);
   uint8_t* fl = reinterpret_cast<uint8_t*>(scr + kPropFl);
 
-  // weights into LDS, row by row as stored (32-bit reads: wb is 4-byte aligned)
+  // W2 into LDS, row by row as stored (32-bit reads: wb is 4-byte
+  // aligned), sixteen reads in flight per thread before their stores
   const uint32_t* wb32 = reinterpret_cast<const uint32_t*>(J.wb);
-  for (int e = t; e < 128 * 64; e += 256) {
-    const int u = e >> 6, v2 = e & 63;
-    *reinterpret_cast<uint32_t*>(w2s + u * kW2Ld + 2 * v2) = wb32[(mlp::bW2 >> 1) + e];
+  constexpr int kStage = 16;
+  for (int e0 = 0; e0 < 128 * 64; e0 += NTH * kStage) {
+    uint32_t v[kStage];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) v[i] = wb32[(mlp::bW2 >> 1) + e0 + t + NTH * i];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const int e = e0 + t + NTH * i;
+      const int u = e >> 6, v2 = e & 63;
+      *reinterpret_cast<uint32_t*>(w2s + u * kW2Ld + 2 * v2) = v[i];
+    }
   }
-  for (int e = t; e < 128 * 4; e += 256)
-    reinterpret_cast<uint32_t*>(w1s)[e] = wb32[(mlp::bW1 >> 1) + e];
 
   // column statistics over the replicated registers (the same in every wave)
   double qa = 0.0, qs = 0.0, ds = 0.0;
@@ -280,25 +297,49 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
       }
   }
   __syncthreads();
-  if (t < d) {  // features of column j = t; row k of G holds G[k][j] (coalesced)
-    const int j = t;
-    const double isdj = isd[j];
-    double csum = 0.0, cmax = -1.0, cw = 0.0;
-    // sixteen rows of G in flight at a time; the terms are added in k order
-    for (int k0 = 0; k0 < d; k0 += 16) {
-      double g[16];
+  // the sums over k of the features, in four quarters of the rows (one per
+  // wavefront; lane l takes columns l + 64 h, reading rows of G coalesced),
+  // sixteen rows in flight at a time; the quarters are then added in order
+  if (wv < 4) {
+    const int rw = (d + 3) / 4;
+    const int k0w = wv * rw;
+    const int k1w = min(d, k0w + rw);
 #pragma unroll
-      for (int e = 0; e < 16; ++e) g[e] = k0 + e < d ? G[(int64_t)(k0 + e) * d + j] : 0.0;
+    for (int h = 0; h < H; ++h) {
+      const int j = lane + h * kW;
+      double csum = 0.0, cmax = -1.0, cw = 0.0;
+      if (valid[h]) {
+        const double isdj = isd[j];
+        for (int k0 = k0w; k0 < k1w; k0 += 16) {
+          double g[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int k = k0 + e;
-        if (k < d && k != j) {
-          const double ck = g[e] * isdj * isd[k];
-          csum += ck;
-          cmax = fmax(cmax, ck);
-          cw += ck * cosv[k];
+          for (int e = 0; e < 16; ++e) g[e] = k0 + e < k1w ? G[(int64_t)(k0 + e) * d + j] : 0.0;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int k = k0 + e;
+            if (k < k1w && k != j) {
+              const double ck = g[e] * isdj * isd[k];
+              csum += ck;
+              cmax = fmax(cmax, ck);
+              cw += ck * cosv[k];
+            }
+          }
         }
       }
+      part[(wv * 3 + 0) * 128 + j] = csum;
+      part[(wv * 3 + 1) * 128 + j] = cmax;
+      part[(wv * 3 + 2) * 128 + j] = cw;
+    }
+  }
+  __syncthreads();
+  if (t < d) {  // features of column j = t
+    const int j = t;
+    double csum = 0.0, cmax = -1.0, cw = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      csum += part[(w * 3 + 0) * 128 + j];
+      cmax = fmax(cmax, part[(w * 3 + 1) * 128 + j]);
+      cw += part[(w * 3 + 2) * 128 + j];
     }
     const double qj = q[j];
     const double gd = G[(int64_t)j * d + j];
@@ -319,8 +360,13 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
   const int c1 = t >> 4;
   const int u1 = 8 * (t & 15);
   float b1u[8];
+  uint32_t w1p[8][4];  // this thread's eight rows of W1, BF16 pairs (held in registers)
 #pragma unroll
-  for (int b = 0; b < 8; ++b) b1u[b] = J.theta[mlp::ob1 + u1 + b];
+  for (int b = 0; b < 8; ++b) {
+    b1u[b] = net ? J.theta[mlp::ob1 + u1 + b] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w1p[b][i] = net ? wb32[(mlp::bW1 >> 1) + (u1 + b) * 4 + i] : 0u;
+  }
   // second layer: this wavefront's column block and units; its lane's unit
   // (column of the output tiles) in each of the four tiles
   const int cb = 16 * (wv & 1);
@@ -330,13 +376,13 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     const int u = ub + 16 * tt + (lane & 15);
-    b2u[tt] = J.theta[mlp::ob2 + u];
-    w3u[tt] = bf16f(J.wb[mlp::bw3 + u]);
+    b2u[tt] = net ? J.theta[mlp::ob2 + u] : 0.0f;
+    w3u[tt] = net ? bf16f(J.wb[mlp::bw3 + u]) : 0.0f;
   }
   const float b3 = J.theta[mlp::ob3];
   __syncthreads();  // features, weights in place; isd / cosv are dead from here
   for (int c0 = 0; c0 < d; c0 += kPropCols) {
-    {
+    if (net) {
       const int col = c0 + 2 * c1;
       // two columns per thread: 2 c1 and 2 c1 + 1 of the chunk
 #pragma unroll
@@ -349,7 +395,10 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
         for (int b = 0; b < 8; ++b) {
           float h = b1u[b];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) h = fmaf(bf16f(w1s[(u1 + b) * 8 + i]), x[i], h);
+          for (int i = 0; i < 4; ++i) {
+            h = fmaf(__uint_as_float(w1p[b][i] << 16), x[2 * i], h);
+            h = fmaf(__uint_as_float(w1p[b][i] & 0xffff0000u), x[2 * i + 1], h);
+          }
           h1[(2 * c1 + cc) * kH1Ld + u1 + b] = in ? fmaxf(h, 0.0f) : 0.0f;
         }
       }
@@ -358,33 +407,35 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
     // second layer on the matrix cores: D[i][j] = sum_k h1[cb + i][k] W2[u][k]
     // (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of each
     // 16 x 16 x 4 step; D[4 (l / 16) + v][l % 16] returns in accumulator v)
-    v4f acc[4];
+    if (net) {
+      v4f acc[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) acc[tt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int tt = 0; tt < 4; ++tt) acc[tt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 4
-    for (int k0 = 0; k0 < 128; k0 += 4) {
-      const float a = h1[(cb + (lane & 15)) * kH1Ld + k0 + kq];
+      for (int k0 = 0; k0 < 128; k0 += 4) {
+        const float a = h1[(cb + (lane & 15)) * kH1Ld + k0 + kq];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        const float bw = bf16f(w2s[(ub + 16 * tt + (lane & 15)) * kW2Ld + k0 + kq]);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < 4; ++tt) {
+          const float bw = bf16f(w2s[(ub + 16 * tt + (lane & 15)) * kW2Ld + k0 + kq]);
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw, acc[tt], 0, 0, 0);
+        }
       }
-    }
-    // output partials: rows 4 kq + v of the block are columns cb + 4 kq + v
-    float zr[4];
+      // output partials: rows 4 kq + v of the block are columns cb + 4 kq + v
+      float zr[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float z = 0.0f;
+      for (int v = 0; v < 4; ++v) {
+        float z = 0.0f;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) z = fmaf(w3u[tt], fmaxf(acc[tt][v] + b2u[tt], 0.0f), z);
-      // sum over the 16 units of each tile row held by lanes 16 kq .. 16 kq + 15
+        for (int tt = 0; tt < 4; ++tt) z = fmaf(w3u[tt], fmaxf(acc[tt][v] + b2u[tt], 0.0f), z);
+        // sum over the 16 units of each tile row held by lanes 16 kq .. 16 kq + 15
 #pragma unroll
-      for (int off = 1; off < 16; off <<= 1) z += __shfl_xor(z, off, kW);
-      zr[v] = z;
-    }
-    if ((lane & 15) == 0) {
+        for (int off = 1; off < 16; off <<= 1) z += __shfl_xor(z, off, kW);
+        zr[v] = z;
+      }
+      if ((lane & 15) == 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) zp[wv * kPropCols + cb + 4 * kq + v] = zr[v];
+        for (int v = 0; v < 4; ++v) zp[wv * kPropCols + cb + 4 * kq + v] = zr[v];
+      }
     }
     __syncthreads();
     if (t < kPropCols && c0 + t < d) {
@@ -446,15 +497,17 @@ template <int DP, bool BATCH, bool MODEL>
 __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one,
                                                                      const LhJob* jobs) {
   constexpr int H = DP / kW;      // column-indexed entries per lane
-  constexpr int GB = 16;          // blocks per row of the tableau
-  constexpr int B = DP / GB;      // the tableau block of a thread is B x B
+  constexpr int GC = 16;                      // block columns of the tableau
+  constexpr int GR = lh_threads(DP) / GC;     // block rows
+  constexpr int BR = DP / GR;                 // the tableau block of a thread is BR x BC
+  constexpr int BC = DP / GC;
   constexpr int kNW = lh_waves(DP);
   constexpr int kBlock = 16 / H;  // rows of Q whose loads are in flight together
   extern __shared__ __attribute__((aligned(16))) double lh_lds[];
   const int lane = threadIdx.x & (kW - 1);
   const int wv = uni((int)(threadIdx.x / kW));
-  const int br = threadIdx.x / GB;  // block row: rows br*B .. br*B + B - 1
-  const int bc = threadIdx.x % GB;  // block column
+  const int br = threadIdx.x / GC;  // block row: rows br*BR .. br*BR + BR - 1
+  const int bc = threadIdx.x % GC;  // block column: columns bc*BC .. bc*BC + BC - 1
   const LhJob& J = lh_job<BATCH>(one, jobs);
   const int64_t sub = BATCH ? 0 : blockIdx.x;
   const int d = J.d;
@@ -541,7 +594,7 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   }
   __syncthreads();
 
-  double T[B][B];  // this thread's block of the tableau (indices fixed at compile time)
+  double T[BR][BC];  // this thread's block of the tableau (indices fixed at compile time)
   double wz[H];    // the q column of T: z on P, w off P
   double dg[H];    // the diagonal of T
   double xs[H];    // x
@@ -552,11 +605,11 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   // T = Q and x = 0, P empty
   auto start = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int a = 0; a < B; ++a) {
-      const int i = br * B + a;
+    for (int a = 0; a < BR; ++a) {
+      const int i = br * BR + a;
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const int j = bc * B + b;
+      for (int b = 0; b < BC; ++b) {
+        const int j = bc * BC + b;
         T[a][b] = (i < d && j < d) ? Qs[i * ld + j] : 0.0;
       }
     }
@@ -584,51 +637,57 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   auto sweep = [&](int k, double sigma) __attribute__((always_inline)) {
     double* rowk = buf + (nsweep & 1) * 128;
     ++nsweep;
-    if (br == k / B) {
-      double e[B];
+    if (br == k / BR) {
+      double e[BR];
 #pragma unroll
-      for (int a = 0; a < B; ++a) e[a] = (br * B + a == k) ? 1.0 : 0.0;
+      for (int a = 0; a < BR; ++a) e[a] = (br * BR + a == k) ? 1.0 : 0.0;
 #pragma unroll
-      for (int b = 0; b < B; b += 2) {
+      for (int b = 0; b < BC; b += 2) {
         double r0 = 0.0, r1 = 0.0;
 #pragma unroll
-        for (int a = 0; a < B; ++a) {
+        for (int a = 0; a < BR; ++a) {
           r0 = fma(e[a], T[a][b], r0);
           r1 = fma(e[a], T[a][b + 1], r1);
         }
-        *reinterpret_cast<double2*>(rowk + bc * B + b) = make_double2(r0, r1);
+        *reinterpret_cast<double2*>(rowk + bc * BC + b) = make_double2(r0, r1);
       }
     }
     const double D = uni(bcast(dg, k));
     const double rd = uni(bcast(wz, k));
     const double inv = uni(1.0 / D);
     __syncthreads();
-    double rc[B], rr[B], rj[H];
+    double rc[BC], rr[BR], rj[H];
 #pragma unroll
-    for (int b = 0; b < B; b += 2) {
-      const double2 u = *reinterpret_cast<const double2*>(rowk + bc * B + b);
-      const double2 v = *reinterpret_cast<const double2*>(rowk + br * B + b);
+    for (int b = 0; b < BC; b += 2) {
+      const double2 u = *reinterpret_cast<const double2*>(rowk + bc * BC + b);
       rc[b] = u.x;
       rc[b + 1] = u.y;
-      rr[b] = v.x;
-      rr[b + 1] = v.y;
+    }
+#pragma unroll
+    for (int a = 0; a < BR; a += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(rowk + br * BR + a);
+      rr[a] = v.x;
+      rr[a + 1] = v.y;
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) rj[h] = rowk[lane + h * kW];
-    double u[B], v[B], mr[B], mc[B];
+    double u[BR], mr[BR], v[BC], mc[BC];
 #pragma unroll
-    for (int a = 0; a < B; ++a) {
-      const bool rk = br * B + a == k;
-      const bool ck = bc * B + a == k;
+    for (int a = 0; a < BR; ++a) {
+      const bool rk = br * BR + a == k;
       u[a] = rk ? sigma * inv : -rr[a] * inv;
       mr[a] = rk ? 0.0 : 1.0;
-      v[a] = ck ? -sigma : rc[a];
-      mc[a] = ck ? 0.0 : 1.0;
     }
 #pragma unroll
-    for (int a = 0; a < B; ++a)
+    for (int b = 0; b < BC; ++b) {
+      const bool ck = bc * BC + b == k;
+      v[b] = ck ? -sigma : rc[b];
+      mc[b] = ck ? 0.0 : 1.0;
+    }
 #pragma unroll
-      for (int b = 0; b < B; ++b) T[a][b] = fma(u[a], v[b], T[a][b] * mr[a] * mc[b]);
+    for (int a = 0; a < BR; ++a)
+#pragma unroll
+      for (int b = 0; b < BC; ++b) T[a][b] = fma(u[a], v[b], T[a][b] * mr[a] * mc[b]);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const int j = lane + h * kW;
