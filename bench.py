@@ -4,9 +4,9 @@ Default workload (the metric's configuration): batched, warm-started solves.
 A passive-set perceptron is trained on the device from 100k problems of the
 batch generator solved cold by the method itself; 4096 held-out problems of
 the same generator (n log-uniform in [2^14, 2^18], d uniform in [8, 96],
-r = max(32 d, 1024), tf-idf-like entries), all resident in HBM, run as 16
-batch plans of 256 problems replayed as HIP graphs.  One step = one pass over
-all 4096 problems.  `value` = warm-started solves/s; beside it the plain
+r = max(32 d, 1024), tf-idf-like entries), all resident in HBM, run as one
+batch plan of 4096 problems replayed as a HIP graph (--plan-size 256 runs 16
+plans of 256).  One step = one pass over all 4096 problems.  `value` = warm-started solves/s; beside it the plain
 cold-start rate of the same plans, the relative residual gap of every
 warm-started solution against the cold one on the same sketch (max, mean),
 the fallback rate and the outer iterations.  The `roofline` is the sketch
@@ -1124,8 +1124,10 @@ def main():
                          "split hi + lo operands and FP32 accumulation")
     ap.add_argument("--train-instances", type=int, default=100_000)
     ap.add_argument("--heldout", type=int, default=4096)
-    ap.add_argument("--plan-size", type=int, default=256,
-                    help="problems per batch plan of the default workload")
+    ap.add_argument("--plan-size", type=int, default=4096,
+                    help="problems per batch plan of the default workload (4096: the "
+                         "held-out set in one plan, so that the solves of many problems "
+                         "share the device; 256: the batch size of the batching form)")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies of this many MiB (the "

@@ -183,33 +183,40 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // copied back and forth at every sweep).
 __host__ __device__ constexpr int lh_threads(int dp) { return dp > kW ? 512 : 256; }
 __host__ __device__ constexpr int lh_waves(int dp) { return lh_threads(dp) / kW; }
+// wavefronts per SIMD asked of the compiler: three workgroups of the 64-wide
+// solver per CU (at most 168 registers per lane), two of the 128-wide
+__host__ __device__ constexpr int lh_min_waves(int dp) { return dp > kW ? 2 : 3; }
 inline int padded_order(int d) { return d <= kW ? kW : 2 * kW; }
 
-// Scratch of the learned proposal (before Q is staged, in Q's place):
-// the features (128 x 8 FP32); the first hidden layer of a chunk of 32
-// columns (32 rows of 128 FP32, row stride 132), whose space first holds
-// 1/sqrt(G_jj), the cosines (FP64, 128 each) and the four quarters' partial
-// feature sums (FP64, 4 x 3 x 128); W2 (128 x 128 BF16,
-// [unit][input], row stride 132); output partials
-// (4 wavefronts x 32 FP32); flags.
-constexpr int kPropCols = 32;
+// Scratch of the learned proposal.  In the solver's partial-sum and
+// pivot-row space (unused until the proposal is done): the features (128 x 8
+// FP32), 1/sqrt(G_jj) and the cosines (FP64, 128 each).  After Q: the first
+// hidden layer of a chunk of columns (a row of 128 FP32 per column, row
+// stride 132), output partials (4 wavefronts x 32 FP32) and the flags.
+// columns per chunk: 16 for the 64-wide solver (its LDS then fits three
+// workgroups per CU), 32 for the 128-wide one
+__host__ __device__ constexpr int prop_cols(int dp) { return dp > 64 ? 32 : 16; }
 constexpr int kH1Ld = 132;
-constexpr int kW2Ld = 132;
-constexpr size_t kPropF = 0, kPropH1 = kPropF + 128 * 8 * 4,
-                 kPropIsd = kPropH1, kPropCos = kPropIsd + 128 * 8,
-                 kPropPart = kPropCos + 128 * 8,
-                 kPropW2 = kPropH1 + kPropCols * kH1Ld * 4, kPropZ = kPropW2 + 128 * kW2Ld * 2,
-                 kPropFl = kPropZ + 4 * kPropCols * 4,
-                 kPropBytes = kPropFl + 128;
-static_assert(kPropPart + 4 * 3 * 128 * 8 <= kPropW2,
-              "cosines and feature partials fit in the hidden-layer space");
+constexpr size_t kPropF = 0, kPropIsd = kPropF + 128 * 8 * 4, kPropCos = kPropIsd + 128 * 8,
+                 kPropFront = kPropCos + 128 * 8;
+__host__ __device__ constexpr size_t prop_z(int pc) { return (size_t)pc * kH1Ld * 4; }
+__host__ __device__ constexpr size_t prop_fl(int pc) { return prop_z(pc) + 4 * 32 * 4; }
+__host__ __device__ constexpr size_t prop_tail(int pc) { return prop_fl(pc) + 128; }
+// the feature sums' partials (4 quarters x 3 sums x dp columns, FP64) use the
+// hidden layer's space before it is written
+static_assert(4 * 3 * 64 * 8 <= prop_z(prop_cols(64)) && 4 * 3 * 128 * 8 <= prop_z(prop_cols(128)),
+              "feature partials fit in the hidden-layer space");
+static_assert(kPropFront <= (size_t)(4 * 2 * 64 + 2 * 128) * 8,
+              "the proposal's front scratch fits in the partial sums and pivot rows");
+static_assert(mlp::bW1 % 8 == 0 && mlp::bW2 % 8 == 0 && mlp::ob1 % 4 == 0,
+              "16-byte reads of the weights");
 
 // partial sums (one row of 2*kW per wavefront), two pivot-row buffers
-// (2 x 128), Q (d x ld) -- or the proposal's scratch before Q, if larger
+// (2 x 128), Q (d x ld), and with a model the proposal's scratch after Q
 inline size_t lds_words(int d, bool model) {
   const size_t q = (size_t)d * lds_ld(d);
-  const size_t prop = model ? (kPropBytes + 7) / 8 : 0;
-  return (size_t)lh_waves(padded_order(d)) * 2 * kW + 2 * 128 + (q > prop ? q : prop);
+  return (size_t)lh_waves(padded_order(d)) * 2 * kW + 2 * 128 + q +
+         (model ? (prop_tail(prop_cols(padded_order(d))) + 7) / 8 : 0);
 }
 
 __device__ __forceinline__ float bf16f(uint32_t h16) { return __uint_as_float(h16 << 16); }
@@ -220,55 +227,119 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// The perceptron's weights a thread of the first 256 holds: its eight rows of
+// W1 (BF16 pairs) and their biases, and its wavefront's fragments of W2
+// (units 32 w + l % 32, inputs 16 s + 8 (l / 32) .. + 7 for k-step s).
+struct NetRegs {
+  float b1u[8];
+  uint32_t w1p[8][4];
+  uint32_t w2f[8][4];
+};
+
+// Reads them (16-byte reads when the weights are 16-byte aligned: fewer
+// reads in flight than the memory counter holds); issued before Q is staged,
+// so that their latency overlaps Q's.
+__device__ __forceinline__ void load_net(const LhJob& J, NetRegs& W) {
+  const int t = threadIdx.x;
+  const int lane = t & (kW - 1);
+  const int wv = t / kW;
+  const int u1 = 8 * (t & 15);
+  const uint32_t* wb32 = reinterpret_cast<const uint32_t*>(J.wb);
+  const bool al16 = ((reinterpret_cast<uintptr_t>(J.wb) | reinterpret_cast<uintptr_t>(J.theta)) &
+                     15) == 0;
+  if (t >= 256) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      W.b1u[b] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) W.w1p[b][i] = W.w2f[b][i] = 0u;
+    }
+  } else if (al16) {
+    const uint4* w4 = reinterpret_cast<const uint4*>(J.wb);
+    const float4* th4 = reinterpret_cast<const float4*>(J.theta);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint4 v = w4[(mlp::bW1 + (u1 + b) * 8) / 8];
+      W.w1p[b][0] = v.x;
+      W.w1p[b][1] = v.y;
+      W.w1p[b][2] = v.z;
+      W.w1p[b][3] = v.w;
+      const uint4 u = w4[(mlp::bW2 + (32 * wv + (lane & 31)) * 128 + 16 * b + 8 * (lane >> 5)) / 8];
+      W.w2f[b][0] = u.x;
+      W.w2f[b][1] = u.y;
+      W.w2f[b][2] = u.z;
+      W.w2f[b][3] = u.w;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; b += 4) {
+      const float4 v = th4[(mlp::ob1 + u1 + b) / 4];
+      W.b1u[b] = v.x;
+      W.b1u[b + 1] = v.y;
+      W.b1u[b + 2] = v.z;
+      W.b1u[b + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      W.b1u[b] = J.theta[mlp::ob1 + u1 + b];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        W.w1p[b][i] = wb32[(mlp::bW1 >> 1) + (u1 + b) * 4 + i];
+        W.w2f[b][i] =
+            wb32[(mlp::bW2 + (32 * wv + (lane & 31)) * 128 + 16 * b + 8 * (lane >> 5)) / 2 + i];
+      }
+    }
+  }
+}
+
 // The learned passive-set proposal of one problem, by the workgroup (the
-// network on its first 256 threads), from its Gram form: the per-column features f0..f7 (FP64,
-// stored FP32; definitions in learned.hip; the sums over rows in four
-// quarters added in order) and the perceptron
+// network on its first 256 threads), from its Gram form: the per-column
+// features f0..f7 (FP64, stored FP32; definitions in learned.hip; the sums
+// over rows in four quarters added in order, from the copy of G in LDS) and
+// the perceptron
 // p = sigmoid(w3 . relu(W2 relu(W1 f + b1) + b2) + b3) with BF16 weights and
 // FP32 accumulation.  The first layer runs on the vector units (thread t: the
 // eight units 8 (t % 16) .. of column t / 16 of a 32-column chunk); the second
-// on the FP32 matrix cores (v_mfma_f32_16x16x4f32, products of FP32 values
-// accumulated in FP32): wavefront w forms columns 16 (w % 2) .. + 15 of the
-// chunk against units 64 (w / 2) .. + 63, four 16 x 16 output tiles over the
-// 128 inputs.  qv / dq hold q and diag(G) replicated in every wavefront
+// on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16): each FP32 activation
+// is split exactly into three BF16 parts (x = hi + mid + lo, truncated
+// splits), their products with the BF16 weights are exact and accumulate in
+// FP32; wavefront w forms units 32 w .. 32 w + 31 for the 32 columns of the
+// chunk, its fragments of W2 read once into registers (lane layout: lane l
+// supplies A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32]; D holds
+// column l % 32, rows (v % 4) + 8 (v / 4) + 4 (l / 32) in register v).
+// qv / dq hold q and diag(G) replicated in every wavefront
 // (entry lane + 64 h).  Returns the proposal as ballot masks (every wavefront
-// the same) and writes the flags to J.flags when given.  `scr` is LDS
-// scratch of kPropBytes; the caller synchronises before reusing it.
+// the same) and writes the flags to J.flags when given.  Qs: G in LDS (row
+// stride ld); `front` and `tail`: the LDS scratch described above; the caller
+// synchronises before reusing it.
 template <int H>
-__device__ void propose(const LhJob& J, const double* __restrict__ G,
-                        const double* __restrict__ q, int d, double c,
+__device__ void propose(const LhJob& J, const double* __restrict__ Qs, int ld, int d, double c,
                         const double (&qv)[H], const double (&dq)[H], const bool (&valid)[H],
-                        char* scr, uint64_t (&prop)[H]) {
-  typedef float v4f __attribute__((ext_vector_type(4)));
-  constexpr int NTH = lh_threads(H * kW);  // the workgroup; the network uses the first 256
+                        char* front, char* tail, const NetRegs& W, uint64_t (&prop)[H]) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
   const int t = threadIdx.x;
   const int lane = t & (kW - 1);
   const int wv = t / kW;
   const bool net = t < 256;
-  float* F = reinterpret_cast<float*>(scr + kPropF);
-  double* isd = reinterpret_cast<double*>(scr + kPropIsd);
-  double* cosv = reinterpret_cast<double*>(scr + kPropCos);
-  double* part = reinterpret_cast<double*>(scr + kPropPart);
-  float* h1 = reinterpret_cast<float*>(scr + kPropH1);
-  uint16_t* w2s = reinterpret_cast<uint16_t*>(scr + kPropW2);
-  float* zp = reinterpret_cast<float*>(scr + kPropZ);
-  uint8_t* fl = reinterpret_cast<uint8_t*>(scr + kPropFl);
+  float* F = reinterpret_cast<float*>(front + kPropF);
+  double* isd = reinterpret_cast<double*>(front + kPropIsd);
+  double* cosv = reinterpret_cast<double*>(front + kPropCos);
+  constexpr int PC = prop_cols(H * kW);  // columns per chunk
+  float* h1 = reinterpret_cast<float*>(tail);
+  float* zp = reinterpret_cast<float*>(tail + prop_z(PC));
+  uint8_t* fl = reinterpret_cast<uint8_t*>(tail + prop_fl(PC));
 
-  // W2 into LDS, row by row as stored (32-bit reads: wb is 4-byte
-  // aligned), sixteen reads in flight per thread before their stores
-  const uint32_t* wb32 = reinterpret_cast<const uint32_t*>(J.wb);
-  constexpr int kStage = 16;
-  for (int e0 = 0; e0 < 128 * 64; e0 += NTH * kStage) {
-    uint32_t v[kStage];
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) v[i] = wb32[(mlp::bW2 >> 1) + e0 + t + NTH * i];
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) {
-      const int e = e0 + t + NTH * i;
-      const int u = e >> 6, v2 = e & 63;
-      *reinterpret_cast<uint32_t*>(w2s + u * kW2Ld + 2 * v2) = v[i];
-    }
-  }
+  const int c1 = t >> 4;
+  const int u1 = 8 * (t & 15);
+  const float (&b1u)[8] = W.b1u;
+  const uint32_t (&w1p)[8][4] = W.w1p;
+  const uint32_t (&w2f)[8][4] = W.w2f;
+  const int u2 = 32 * wv + (lane & 31);
+  const float b2u = net ? J.theta[mlp::ob2 + u2] : 0.0f;
+  const float w3u = net ? bf16f(J.wb[mlp::bw3 + u2]) : 0.0f;
+  const float b3 = J.theta[mlp::ob3];
+  const float thr = J.threshold;
 
   // column statistics over the replicated registers (the same in every wave)
   double qa = 0.0, qs = 0.0, ds = 0.0;
@@ -297,9 +368,10 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
       }
   }
   __syncthreads();
-  // the sums over k of the features, in four quarters of the rows (one per
-  // wavefront; lane l takes columns l + 64 h, reading rows of G coalesced),
-  // sixteen rows in flight at a time; the quarters are then added in order
+  // the sums over k of the features from G in LDS, in four quarters of the
+  // rows (wavefronts 0..3; lane l: columns l + 64 h); the partials go to the
+  // hidden layer's space and are added in quarter order
+  double* fpart = reinterpret_cast<double*>(tail);
   if (wv < 4) {
     const int rw = (d + 3) / 4;
     const int k0w = wv * rw;
@@ -310,12 +382,12 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
       double csum = 0.0, cmax = -1.0, cw = 0.0;
       if (valid[h]) {
         const double isdj = isd[j];
-        for (int k0 = k0w; k0 < k1w; k0 += 16) {
-          double g[16];
+        for (int k0 = k0w; k0 < k1w; k0 += 8) {
+          double g[8];
 #pragma unroll
-          for (int e = 0; e < 16; ++e) g[e] = k0 + e < k1w ? G[(int64_t)(k0 + e) * d + j] : 0.0;
+          for (int e = 0; e < 8; ++e) g[e] = k0 + e < k1w ? Qs[(k0 + e) * ld + j] : 0.0;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) {
+          for (int e = 0; e < 8; ++e) {
             const int k = k0 + e;
             if (k < k1w && k != j) {
               const double ck = g[e] * isdj * isd[k];
@@ -326,9 +398,9 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
           }
         }
       }
-      part[(wv * 3 + 0) * 128 + j] = csum;
-      part[(wv * 3 + 1) * 128 + j] = cmax;
-      part[(wv * 3 + 2) * 128 + j] = cw;
+      fpart[(wv * 3 + 0) * (H * kW) + j] = csum;
+      fpart[(wv * 3 + 1) * (H * kW) + j] = cmax;
+      fpart[(wv * 3 + 2) * (H * kW) + j] = cw;
     }
   }
   __syncthreads();
@@ -337,12 +409,12 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
     double csum = 0.0, cmax = -1.0, cw = 0.0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      csum += part[(w * 3 + 0) * 128 + j];
-      cmax = fmax(cmax, part[(w * 3 + 1) * 128 + j]);
-      cw += part[(w * 3 + 2) * 128 + j];
+      csum += fpart[(w * 3 + 0) * (H * kW) + j];
+      cmax = fmax(cmax, fpart[(w * 3 + 1) * (H * kW) + j]);
+      cw += fpart[(w * 3 + 2) * (H * kW) + j];
     }
-    const double qj = q[j];
-    const double gd = G[(int64_t)j * d + j];
+    const double qj = (H == 1 || j < kW) ? qv[0] : qv[H - 1];  // lane j % 64 holds q_j
+    const double gd = Qs[j * ld + j];
     const double inv = d > 1 ? 1.0 / (d - 1) : 0.0;
     double lg = (gd > 0.0 && dmean > 0.0) ? log(gd / dmean) : -30.0;
     lg = fmin(30.0, fmax(-30.0, lg));
@@ -356,37 +428,13 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
     f[6] = (float)lg;
     f[7] = (float)d / 128.0f;
   }
-  // first layer: this thread's column of the chunk and eight units
-  const int c1 = t >> 4;
-  const int u1 = 8 * (t & 15);
-  float b1u[8];
-  uint32_t w1p[8][4];  // this thread's eight rows of W1, BF16 pairs (held in registers)
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    b1u[b] = net ? J.theta[mlp::ob1 + u1 + b] : 0.0f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) w1p[b][i] = net ? wb32[(mlp::bW1 >> 1) + (u1 + b) * 4 + i] : 0u;
-  }
-  // second layer: this wavefront's column block and units; its lane's unit
-  // (column of the output tiles) in each of the four tiles
-  const int cb = 16 * (wv & 1);
-  const int ub = 64 * (wv >> 1);
-  const int kq = lane >> 4;
-  float b2u[4], w3u[4];
-#pragma unroll
-  for (int tt = 0; tt < 4; ++tt) {
-    const int u = ub + 16 * tt + (lane & 15);
-    b2u[tt] = net ? J.theta[mlp::ob2 + u] : 0.0f;
-    w3u[tt] = net ? bf16f(J.wb[mlp::bw3 + u]) : 0.0f;
-  }
-  const float b3 = J.theta[mlp::ob3];
-  __syncthreads();  // features, weights in place; isd / cosv are dead from here
-  for (int c0 = 0; c0 < d; c0 += kPropCols) {
+  __syncthreads();  // features in place
+  for (int c0 = 0; c0 < d; c0 += PC) {
     if (net) {
-      const int col = c0 + 2 * c1;
-      // two columns per thread: 2 c1 and 2 c1 + 1 of the chunk
+      constexpr int CPT = PC / 16;  // columns per thread: CPT c1 .. of the chunk
+      const int col = c0 + CPT * c1;
 #pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
+      for (int cc = 0; cc < CPT; ++cc) {
         const bool in = col + cc < d;
         float x[8];
 #pragma unroll
@@ -399,50 +447,70 @@ __device__ void propose(const LhJob& J, const double* __restrict__ G,
             h = fmaf(__uint_as_float(w1p[b][i] << 16), x[2 * i], h);
             h = fmaf(__uint_as_float(w1p[b][i] & 0xffff0000u), x[2 * i + 1], h);
           }
-          h1[(2 * c1 + cc) * kH1Ld + u1 + b] = in ? fmaxf(h, 0.0f) : 0.0f;
+          h1[(CPT * c1 + cc) * kH1Ld + u1 + b] = in ? fmaxf(h, 0.0f) : 0.0f;
         }
       }
     }
     __syncthreads();
-    // second layer on the matrix cores: D[i][j] = sum_k h1[cb + i][k] W2[u][k]
-    // (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of each
-    // 16 x 16 x 4 step; D[4 (l / 16) + v][l % 16] returns in accumulator v)
+    // second layer on the matrix cores: D[i][u] = sum_k h1[i][k] W2[u][k]
     if (net) {
-      v4f acc[4];
+      // one accumulator per split part (three independent chains) where the
+      // registers allow it (the 128-wide solver), else one chain
+      constexpr int NACC = H > 1 ? 3 : 1;
+      f32x16 acc[NACC];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-      for (int k0 = 0; k0 < 128; k0 += 4) {
-        const float a = h1[(cb + (lane & 15)) * kH1Ld + k0 + kq];
+      for (int a = 0; a < NACC; ++a)
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          const float bw = bf16f(w2s[(ub + 16 * tt + (lane & 15)) * kW2Ld + k0 + kq]);
-          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw, acc[tt], 0, 0, 0);
+        for (int v = 0; v < 16; ++v) acc[a][v] = 0.0f;
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) {
+        // (with 16-column chunks rows 16..31 repeat rows 0..15; ignored)
+        const float* hr = h1 + (lane & (PC - 1)) * kH1Ld + 16 * k8 + 8 * (lane >> 5);
+        const float4 x0 = *reinterpret_cast<const float4*>(hr);
+        const float4 x1 = *reinterpret_cast<const float4*>(hr + 4);
+        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        bf16x8 p0, p1, p2;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t hb = __float_as_uint(xv[e]) & 0xffff0000u;
+          const float r1 = xv[e] - __uint_as_float(hb);
+          const uint32_t mb = __float_as_uint(r1) & 0xffff0000u;
+          const float r2 = r1 - __uint_as_float(mb);
+          p0[e] = __builtin_bit_cast(__bf16, (unsigned short)(hb >> 16));
+          p1[e] = __builtin_bit_cast(__bf16, (unsigned short)(mb >> 16));
+          p2[e] = (__bf16)r2;
         }
+        const bf16x8 w = __builtin_bit_cast(bf16x8, w2f[k8]);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p0, w, acc[0], 0, 0, 0);
+        acc[1 % NACC] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p1, w, acc[1 % NACC], 0, 0, 0);
+        acc[2 % NACC] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p2, w, acc[2 % NACC], 0, 0, 0);
       }
-      // output partials: rows 4 kq + v of the block are columns cb + 4 kq + v
-      float zr[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float z = 0.0f;
+      for (int a = 1; a < NACC; ++a)
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) z = fmaf(w3u[tt], fmaxf(acc[tt][v] + b2u[tt], 0.0f), z);
-        // sum over the 16 units of each tile row held by lanes 16 kq .. 16 kq + 15
+        for (int v = 0; v < 16; ++v) acc[0][v] += acc[a][v];
+      // output partials over this wavefront's 32 units: lanes 32 (l / 32) ..
+      // hold the rows (v % 4) + 8 (v / 4) + 4 (l / 32), one unit each
+      float zr[16];
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) z += __shfl_xor(z, off, kW);
-        zr[v] = z;
-      }
-      if ((lane & 15) == 0) {
+      for (int v = 0; v < 16; ++v) zr[v] = w3u * fmaxf(acc[0][v] + b2u, 0.0f);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) zp[wv * kPropCols + cb + 4 * kq + v] = zr[v];
+      for (int off = 1; off < 32; off <<= 1)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) zr[v] += __shfl_xor(zr[v], off, kW);
+      if ((lane & 31) == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = (v & 3) + 8 * (v >> 2) + 4 * (lane >> 5);
+          if (row < PC) zp[wv * 32 + row] = zr[v];
+        }
       }
     }
     __syncthreads();
-    if (t < kPropCols && c0 + t < d) {
-      const int w0 = (t >> 4) & 1;  // the two wavefronts holding column block t / 16
-      const float zz = zp[w0 * kPropCols + t] + zp[(w0 + 2) * kPropCols + t] + b3;
+    if (t < PC && c0 + t < d) {
+      const float zz = ((zp[t] + zp[32 + t]) + (zp[64 + t] + zp[96 + t])) + b3;
       const float p = 1.0f / (1.0f + expf(-zz));
-      fl[c0 + t] = p > J.threshold ? 1 : 0;
+      fl[c0 + t] = p > thr ? 1 : 0;
     }
     __syncthreads();  // h1 and zp are rewritten by the next chunk
   }
@@ -494,7 +562,8 @@ __device__ __forceinline__ const LhJob& lh_job(const LhJob& one, const LhJob* jo
 // (BATCH), or sub-problem blockIdx.x of the job `one`, whose inputs sit at the
 // job's strides.  Q (= G) is d x d row-major (symmetric), d <= DP.
 template <int DP, bool BATCH, bool MODEL>
-__global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one,
+__global__ __launch_bounds__(lh_threads(DP))
+__attribute__((amdgpu_waves_per_eu(lh_min_waves(DP)))) void lawson_hanson_kernel(LhJob one,
                                                                      const LhJob* jobs) {
   constexpr int H = DP / kW;      // column-indexed entries per lane
   constexpr int GC = 16;                      // block columns of the tableau
@@ -508,7 +577,7 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   const int wv = uni((int)(threadIdx.x / kW));
   const int br = threadIdx.x / GC;  // block row: rows br*BR .. br*BR + BR - 1
   const int bc = threadIdx.x % GC;  // block column: columns bc*BC .. bc*BC + BC - 1
-  const LhJob& J = lh_job<BATCH>(one, jobs);
+  const LhJob J = lh_job<BATCH>(one, jobs);  // by value: the fields stay in scalar registers
   const int64_t sub = BATCH ? 0 : blockIdx.x;
   const int d = J.d;
   const double* Qg = J.G + sub * J.G_stride;
@@ -532,10 +601,13 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
       for (int h = 0; h < H; ++h)
         v[e][h] = (i0 + e < r1 && valid[h]) ? Qg[(int64_t)(i0 + e) * d + lane + h * kW] : 0.0;
   };
-  // this wavefront's first rows of Q are requested before anything else, so
-  // their latency overlaps the set-up (after the proposal, with a model)
+  // the perceptron's weights (with a model) and this wavefront's first rows
+  // of Q are requested before anything else, so that their latency overlaps
+  // the set-up
+  NetRegs net_w;
+  if constexpr (MODEL) load_net(J, net_w);
   double v0[kBlock][H];
-  if (!MODEL) fetch(r0, v0);
+  fetch(r0, v0);
 
   const int max_iter = J.max_iter;
   const double* qg = J.q + sub * J.q_stride;
@@ -560,16 +632,6 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
   for (int off = 1; off < kW; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, kW));
   const double c = J.c[sub * J.c_stride];
   const int64_t m_eff = J.m_dev ? (int64_t)J.m_dev[sub * J.m_dev_stride] : J.m;
-  // the learned proposal, computed before Q is staged (its scratch is Q's place)
-  uint64_t prop0[H];
-#pragma unroll
-  for (int h = 0; h < H; ++h) prop0[h] = 0ull;
-  if constexpr (MODEL) {
-    propose<H>(J, Qg, qg, d, c, qv, dq, valid,
-               reinterpret_cast<char*>(lh_lds + kNW * 2 * kW + 2 * 128), prop0);
-    __syncthreads();
-    fetch(r0, v0);
-  }
   const double tau =
       uni(J.tol > 0.0 ? J.tol : 10.0 * DBL_EPSILON * amax * (double)(m_eff > d ? m_eff : d));
 
@@ -593,6 +655,16 @@ __global__ __launch_bounds__(lh_threads(DP)) void lawson_hanson_kernel(LhJob one
       }
   }
   __syncthreads();
+  // the learned proposal, from Q in LDS; its scratch: the partial sums and
+  // pivot rows (idle until it ends) and the space after Q
+  uint64_t prop0[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) prop0[h] = 0ull;
+  if constexpr (MODEL) {
+    propose<H>(J, Qs, ld, d, c, qv, dq, valid, reinterpret_cast<char*>(lh_lds),
+               reinterpret_cast<char*>(Qs + d * ld), net_w, prop0);
+    __syncthreads();
+  }
 
   double T[BR][BC];  // this thread's block of the tableau (indices fixed at compile time)
   double wz[H];    // the q column of T: z on P, w off P
