@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = "NNLS solves/s at ≤1e-2 rel. residual gap vs plain; SRHT GB/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "srht_tiled_2p20x64_r4096_traffic.json")
+TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "srht_tiled_warm_batch_4096_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_0812_4547_amd", "csrc", "srht.hip")
 
 WORKLOADS = {
@@ -78,11 +79,11 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch of the sketch kernel from the committed rocprofv3
     counter summary, or None when absent or taken on different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -886,7 +887,10 @@ def bench_warm_batch(args):
     rec["roofline"] = _with_read_peak({
         "kernel": "srht_tiled_kernel (every sketch launch of the pass)", "bound": "hbm",
         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS,
+        # counters were taken on the 2^14-row variant with one plan of 4096
+        "traffic": (load_traffic(TRAFFIC_FILE_BATCH)
+                    if (per == count == 4096 and sorted(set(tiles)) == [(14, 2)]) else None),
         "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sk_ms,
         "whole_sketch": _whole(alg, kw["streams"] + sk_ms + kw["reduce"])})
     rec["training"] = {"problems": args.train_instances, "rows": train_rows,
