@@ -193,6 +193,7 @@ __global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const
 constexpr int kLdsCols = 129;   // d + k (the wide form)
 constexpr int kLdsColsN = 112;  // d + k of the narrow form (seven blocks)
 constexpr int kLdsRows = 64;    // rows per chunk
+constexpr int64_t kLdsMinRows = 65536;  // single problems: rows for the one-pass kernel
 constexpr int kLdsCs = kLdsRows + 4;  // column stride in LDS (padded against bank conflicts)
 
 // COLS columns at most, NW wavefronts: block pairs per wavefront and float4
@@ -420,7 +421,12 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   p.nbA = (d + kBlk - 1) / kBlk;
   p.nb = (d + k + kBlk - 1) / kBlk;
   p.pairs = p.nbA * p.nb - p.nbA * (p.nbA - 1) / 2 + (p.nb - p.nbA);
-  p.lds = d + k <= kLdsColsN ? 1 : (d + k <= kLdsCols ? 2 : 0);
+  // the one-pass kernel needs many row segments to fill the device: batches
+  // (max_chunks > 0, many problems together) and single problems of at least
+  // kLdsMinRows rows; a single sketch (a few thousand rows) keeps one
+  // workgroup per block pair and chunk of rows, more workgroups in flight
+  const bool one_pass = max_chunks > 0 || m >= kLdsMinRows;
+  p.lds = !one_pass ? 0 : (d + k <= kLdsColsN ? 1 : (d + k <= kLdsCols ? 2 : 0));
   if (p.lds) {
     // segments of at least 256 rows, at most two workgroups per CU (batches
     // cap them per problem: many problems fill the device together)
