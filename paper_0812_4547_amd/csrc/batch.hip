@@ -33,7 +33,7 @@ struct Candidate {
   int log_t_cap, wgs;
 };
 // LDS bounds the occupancy: 2^15-row tiles use 132 KB of the 160 KB per CU.
-const Candidate kCandidates[] = {{15, 1}, {14, 1}, {14, 2}, {13, 2}, {13, 4}, {12, 4}, {12, 8}};
+const Candidate kCandidates[] = {{15, 1}, {14, 1}, {14, 2}, {13, 2}, {13, 3}, {13, 4}, {12, 4}, {12, 8}};
 // row segments of a problem's moments at most (each at least 256 rows)
 constexpr int kMomentSegments = 8;
 

@@ -31,6 +31,7 @@
 // touch.  A second kernel adds the partials of each column in a fixed order
 // (deterministic: no atomics) and applies the 1/sqrt(r) scale.
 #include <atomic>
+#include <type_traits>
 
 #include "common.h"
 
@@ -143,6 +144,128 @@ __device__ __forceinline__ void advance(const TiledLaunch& L, int& ji, int& col,
   tile = RAG ? sjob<BATCH>(L, ji).tiles : 0;
 }
 
+// Wave-uniform copies of job fields.  A batch reads its job table with vector
+// loads (the kernel's stores could alias it as far as the compiler knows), so
+// values taken from it are made uniform explicitly: buffer resources built
+// from them then live in scalar registers (a resource in vector registers
+// makes every load a loop over the distinct values).
+__device__ __forceinline__ int32_t uni(int32_t v) {
+  return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  return __longlong_as_double((long long)uni((int64_t)__double_as_longlong(v)));
+}
+template <class P>
+__device__ __forceinline__ P* uni(P* p) {
+  return reinterpret_cast<P*>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+template <bool U, class V>
+__device__ __forceinline__ V uni_if(V v) {
+  if constexpr (U) return uni(v);
+  else return v;
+}
+
+// Global-memory view of a pointer read from a job table.  Generic pointers
+// would be accessed with flat instructions, and while a flat access is
+// pending the compiler can only wait for all outstanding loads, which
+// would also wait for the next tile's prefetch.
+template <class V>
+__device__ __forceinline__ __attribute__((address_space(1))) V* gmem(V* p) {
+  return (__attribute__((address_space(1))) V*)p;
+}
+
+// What the tile loop reads of the job whose tiles it loads ...
+struct TileSrc {
+  const float* A;
+  const float* B;
+  const uint32_t* sign_words;
+  int64_t lda, ldb, n;
+  int32_t d, ncols, tiles;
+};
+// ... and of the job whose column it writes.
+struct ColDst {
+  float* SA;
+  float* SB;
+  float* partials;
+  int64_t ldsa, ldsb;
+  double inv_sqrt_r;
+  int32_t d, pieces, r_cap, tiles, rag;
+};
+
+// A single problem's fields are kernel arguments (already uniform): the
+// single-problem kernels read them in place.
+template <bool BATCH>
+__device__ __forceinline__ std::conditional_t<BATCH, TileSrc, const SketchJob&> tile_src(
+    const TiledLaunch& L, int ji) {
+  if constexpr (!BATCH) {
+    return L.one;
+  } else {
+    const SketchJob& J = L.jobs[ji];
+    TileSrc S;
+    S.A = uni(J.A);
+    S.B = uni(J.B);
+    S.sign_words = uni(J.sign_words);
+    S.lda = uni(J.lda);
+    S.ldb = uni(J.ldb);
+    S.n = uni(J.n);
+    S.d = uni(J.d);
+    S.ncols = uni(J.ncols);
+    S.tiles = uni((int32_t)J.tiles);
+    return S;
+  }
+}
+
+template <bool BATCH>
+__device__ __forceinline__ std::conditional_t<BATCH, ColDst, const SketchJob&> col_dst(
+    const TiledLaunch& L, int ji) {
+  if constexpr (!BATCH) {
+    return L.one;
+  } else {
+    const SketchJob& J = L.jobs[ji];
+    ColDst D;
+    D.SA = uni(J.SA);
+    D.SB = uni(J.SB);
+    D.partials = uni(J.partials);
+    D.ldsa = uni(J.ldsa);
+    D.ldsb = uni(J.ldsb);
+    D.inv_sqrt_r = uni(J.inv_sqrt_r);
+    D.d = uni(J.d);
+    D.pieces = uni(J.pieces);
+    D.r_cap = uni(J.r_cap);
+    D.tiles = uni((int32_t)J.tiles);
+    D.rag = uni(J.rag);
+    return D;
+  }
+}
+
+// The item after (ji, col, tile) for the tiled kernel, with the loaded job's
+// fields in S (reloaded when the job changes).  Only called when such an item
+// exists.
+template <bool BATCH, bool RAG, class Src>
+__device__ __forceinline__ void tiled_advance(const TiledLaunch& L, int& ji, Src& S, int& col,
+                                              int64_t& tile) {
+  if (!RAG && (int32_t)tile + 1 < (int32_t)S.tiles) {
+    ++tile;
+    return;
+  }
+  ++col;
+  if constexpr (BATCH) {
+    if (col >= S.ncols) {
+      do {
+        ++ji;
+      } while (uni(RAG ? L.jobs[ji].rag : (int32_t)L.jobs[ji].tiles) == 0);
+      col = 0;
+      S = tile_src<true>(L, ji);
+    }
+  }
+  tile = RAG ? S.tiles : 0;
+}
+
 // Load modes: full tiles of 16-byte aligned columns (no bounds checks), the
 // straddling tile of aligned columns (vector loads up to row n, element loads
 // for the one float4 cut by n), and unaligned columns (element loads).
@@ -185,8 +308,8 @@ __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t rsrc,
 // the join).  One lane offset serves all eight loads; the k T/8 row offset
 // sits in a scalar register.  The range ends at row n: a 16-byte load that
 // straddles it returns its in-range words and zeros after them.
-template <int LOG_T, int MODE, int AUX>
-__device__ __forceinline__ void load_tile(const SketchJob& J, int col, int64_t tile, bool live,
+template <int LOG_T, int MODE, int AUX, class Src>
+__device__ __forceinline__ void load_tile(const Src& J, int col, int64_t tile, bool live,
                                           float (&v)[kRegs], uint32_t& sw) {
   constexpr int T = 1 << LOG_T;
   const int tid = threadIdx.x;
@@ -237,14 +360,15 @@ __device__ __forceinline__ int load_kept_rows(const SketchJob& J, int32_t (&srow
 
 // Kept rows handled by this thread, split for the combine: the LDS word of
 // z_t[i_lo] (padded) and the tile bits i_hi = i >> tau (rows are < 2^31).
-template <int LOG_T, int SPT, int NT>
+template <int LOG_T, int SPT, int NT, bool BATCH>
 __device__ __forceinline__ int load_rows(const SketchJob& J, uint32_t (&zidx)[SPT],
                                          uint32_t (&ihi)[SPT]) {
-  const int count = *J.count;
+  // a batch's combine skips the slots past the count with scalar branches
+  const int count = BATCH ? uni(*gmem(J.count)) : *J.count;
 #pragma unroll
   for (int s = 0; s < SPT; ++s) {
     const int l = threadIdx.x + s * NT;
-    const uint32_t i = (l < count) ? (uint32_t)J.rows[l] : 0u;
+    const uint32_t i = (l < count) ? (uint32_t)gmem(J.rows)[l] : 0u;
     zidx[s] = (uint32_t)lds_pad((int)(i & ((1u << LOG_T) - 1u)));
     ihi[s] = i >> LOG_T;
   }
@@ -272,33 +396,40 @@ void srht_tiled_kernel(TiledLaunch L) {
   const int64_t item_end = ((w + 1) * L.items) / L.grid;
   if (item_begin >= item_end) return;
 
+  // job, column and tile of the first item (find_sjob gives the last job
+  // starting at or before it)
   int ji = 0;
-  if constexpr (BATCH) ji = find_sjob<RAG>(L.jobs, L.njobs, item_begin);
+  if constexpr (BATCH) ji = uni(find_sjob<RAG>(L.jobs, L.njobs, item_begin));
+  decltype(auto) S = tile_src<BATCH>(L, ji);  // job of the tile being loaded
+  decltype(auto) D = col_dst<BATCH>(L, ji);    // job of the tile being transformed
   int col;
   int64_t tile;
-  locate<BATCH, RAG>(L, item_begin, ji, col, tile);
+  int piece = 0;
+  {
+    const int64_t i0 = uni_if<BATCH>(job_item0<RAG>(sjob<BATCH>(L, ji)));
+    const int64_t local = item_begin - i0;
+    const int64_t tl = RAG ? 1 : (int64_t)S.tiles;
+    col = (int)(local / tl);
+    tile = RAG ? S.tiles : local % tl;
+    // Partial slot of this workgroup in its columns: every column after the
+    // first starts inside the workgroup's range, so only the first column's
+    // slot needs the owner of its first item (the one division of the loop).
+    const int64_t first = i0 + (int64_t)col * tl;
+    piece = RAG ? D.pieces - 1 : (int)(w - owner_of(first, L.items, L.grid));
+  }
 
   uint32_t zidx[SPT], ihi[SPT];
   float acc[SPT];
-  int count = load_rows<LOG_T, SPT, NT>(sjob<BATCH>(L, ji), zidx, ihi);
+  int count = load_rows<LOG_T, SPT, NT, BATCH>(sjob<BATCH>(L, ji), zidx, ihi);
 #pragma unroll
   for (int s = 0; s < SPT; ++s) acc[s] = 0.0f;
-  // Partial slot of this workgroup in its columns: every column after the
-  // first starts inside the workgroup's range, so only the first column's
-  // slot needs the owner of its first item (the one division of the loop).
-  int piece = 0;
-  {
-    const SketchJob& J = sjob<BATCH>(L, ji);
-    const int64_t first = job_item0<RAG>(J) + (int64_t)col * job_tiles<RAG>(J);
-    piece = RAG ? J.pieces - 1 : (int)(w - owner_of(first, L.items, L.grid));
-  }
 
   // Two register buffers alternate between the tile being transformed and
   // the next tile's loads, so the loads are in flight during every pass.
   float va[kRegs], vb[kRegs];
   uint32_t swa, swb;
   int64_t item = item_begin;
-  load_tile<LOG_T, MODE, AUX>(sjob<BATCH>(L, ji), col, tile, true, va, swa);
+  load_tile<LOG_T, MODE, AUX>(S, col, tile, true, va, swa);
 
   // pass-1 stores: padded word k*T/8 + 4 tid = lds_pad(4 tid) + k*(T/8 + T/256)
   // (T/8 is a multiple of 128), one base and constant offsets
@@ -314,8 +445,8 @@ void srht_tiled_kernel(TiledLaunch L) {
     const int64_t cur_tile = tile;
     // (a ragged launch gives every workgroup exactly one item: no prefetch)
     const bool has_next = !RAG && next < item_end;
-    if (has_next) advance<BATCH, RAG>(L, ji, col, tile);
-    load_tile<LOG_T, MODE, AUX>(sjob<BATCH>(L, ji), col, tile, has_next, vn, swn);
+    if (has_next) tiled_advance<BATCH, RAG>(L, ji, S, col, tile);
+    load_tile<LOG_T, MODE, AUX>(S, col, tile, has_next, vn, swn);
     // step 4 of Algorithm 1: the sign flip, fused into the load
 #pragma unroll
     for (int e = 0; e < kRegs; ++e) v[e] = flip(v[e], (sw >> e) & 1u);
@@ -345,24 +476,28 @@ void srht_tiled_kernel(TiledLaunch L) {
       for (int e = 0; e < kRegs; ++e) lds[p3_base + 132 * e] = u[e];
     }
     __syncthreads();
-    // pruned combine: y[i] += (-1)^popcount(i_hi & t) * z_t[i_lo]
+    // pruned combine: y[i] += (-1)^popcount(i_hi & t) * z_t[i_lo]; a batch
+    // sizes SPT for its largest r and skips the slots past each problem's
+    // kept rows (one problem fills its slots but the last)
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-      const float z = lds[zidx[s]];
-      acc[s] += flip(z, (uint32_t)__popc(ihi[s] & (uint32_t)cur_tile) & 1u);
+      if (!BATCH || s * NT < count) {
+        const float z = lds[zidx[s]];
+        acc[s] += flip(z, (uint32_t)__popc(ihi[s] & (uint32_t)cur_tile) & 1u);
+      }
     }
     __syncthreads();
     const bool new_job = BATCH && !RAG && has_next && (ji != cur_job);
     const bool last_of_col = RAG || !has_next || (col != cur_col) || new_job;
     if (last_of_col) {
-      const SketchJob& J = sjob<BATCH>(L, cur_job);
+      const auto& J = D;
       // a column whose every tile this workgroup transformed needs no reduce:
       // its sums go out scaled, as the reduce would write them
       const bool whole = RAG ? J.tiles == 0
                              : (piece == 0 && (int32_t)cur_tile + 1 == (int32_t)J.tiles && !J.rag);
       if (whole) {
-        float* out = cur_col < J.d ? J.SA + (int64_t)cur_col * J.ldsa
-                                   : J.SB + (int64_t)(cur_col - J.d) * J.ldsb;
+        auto out = gmem(cur_col < J.d ? J.SA + (int64_t)cur_col * J.ldsa
+                                      : J.SB + (int64_t)(cur_col - J.d) * J.ldsb);
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
           const int l = tid + s * NT;
@@ -370,7 +505,7 @@ void srht_tiled_kernel(TiledLaunch L) {
           acc[s] = 0.0f;
         }
       } else {
-        float* dst = J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap;
+        auto dst = gmem(J.partials + ((int64_t)cur_col * J.pieces + piece) * J.r_cap);
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
           const int l = tid + s * NT;
@@ -380,7 +515,12 @@ void srht_tiled_kernel(TiledLaunch L) {
       }
       piece = RAG ? piece : 0;
     }
-    if (new_job) count = load_rows<LOG_T, SPT, NT>(sjob<BATCH>(L, ji), zidx, ihi);
+    if constexpr (BATCH) {
+      if (new_job) {
+        D = col_dst<BATCH>(L, ji);
+        count = load_rows<LOG_T, SPT, NT, BATCH>(sjob<BATCH>(L, ji), zidx, ihi);
+      }
+    }
     item = next;
   };
 
