@@ -61,6 +61,17 @@ __device__ inline uint32_t perm_apply(const PermKeys& k, uint32_t x) {
 }
 
 // ---------------------------------------------------------------- helpers
+// Global-memory view of a pointer that a kernel read from a job table (or
+// otherwise cannot prove global).  Generic pointers are accessed with flat
+// instructions, which count against both the vector-memory and the LDS
+// counters and may complete out of order: while one is pending the compiler
+// can only wait for every outstanding access, so a prefetch in flight is
+// waited for at the next LDS read.
+template <class V>
+__device__ __forceinline__ __attribute__((address_space(1))) V* gmem(V* p) {
+  return (__attribute__((address_space(1))) V*)p;
+}
+
 inline int ilog2_exact(uint64_t v) {
   int m = 0;
   while ((1ull << m) < v) ++m;

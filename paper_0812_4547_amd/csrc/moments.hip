@@ -84,9 +84,15 @@ __device__ __forceinline__ const float* col_ptr(const MomentJob& J, int c) {
 }
 
 // rows rr .. rr+3 of a column (zero past `hi` or for a missing column)
-__device__ __forceinline__ float4 load_rows4(const float* col, int64_t rr, int64_t hi, bool vec) {
-  if (!col || rr >= hi) return make_float4(0.f, 0.f, 0.f, 0.f);
-  if (vec && rr + 4 <= hi) return *reinterpret_cast<const float4*>(col + rr);
+__device__ __forceinline__ float4 load_rows4(const float* col_any, int64_t rr, int64_t hi,
+                                             bool vec) {
+  if (!col_any || rr >= hi) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const auto col = gmem(col_any);
+  if (vec && rr + 4 <= hi) {
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    const f32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(col + rr);
+    return make_float4(q.x, q.y, q.z, q.w);
+  }
   float t[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) t[e] = rr + e < hi ? col[rr + e] : 0.0f;
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(NW * 64) void gram_mfma_kernel(MomentJob one, const
   pair_blocks(p, J.nbA, J.nb, bi, bj);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
+  const int64_t m_eff = J.m_dev ? (int64_t)*gmem(J.m_dev) : J.m;
   const int64_t r0 = (J.m * chunk) / J.chunks;
   const int64_t r1 = (J.m * (chunk + 1)) / J.chunks;
   const int64_t hi = r1 < m_eff ? r1 : m_eff;
@@ -222,7 +228,7 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int kq = lane >> 4;
   const int D1 = J.d + J.k;
-  const int64_t m_eff = J.m_dev ? (int64_t)*J.m_dev : J.m;
+  const int64_t m_eff = J.m_dev ? (int64_t)*gmem(J.m_dev) : J.m;
   const int64_t r0 = (J.m * seg) / J.chunks;
   const int64_t r1 = (J.m * (seg + 1)) / J.chunks;
   const int64_t hi = r1 < m_eff ? r1 : m_eff;
@@ -239,12 +245,19 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
+  // column 1-norms from the loaded values: load slot u keeps its column
+  // ((t + u NW 64) / 16) for the whole segment, its 16 lanes summed at the end
+  double sabs[L::loads];
+#pragma unroll
+  for (int u = 0; u < L::loads; ++u) sabs[u] = 0.0;
   auto stash = [&](float* buf, const float4 (&v)[L::loads]) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < L::loads; ++u) {
       const int e = t + u * NW * 64;
       const int col = e >> 4;
       if (col < D1) *reinterpret_cast<float4*>(buf + col * kLdsCs + 4 * (e & 15)) = v[u];
+      sabs[u] += (fabs((double)v[u].x) + fabs((double)v[u].y)) +
+                 (fabs((double)v[u].z) + fabs((double)v[u].w));
     }
   };
 
@@ -259,7 +272,6 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
   v4d acc[PW];
 #pragma unroll
   for (int s = 0; s < PW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
-  double aabs = 0.0;  // column t's 1-norm share (t < d)
 
   float4 nxt[L::loads];
   int b = 0;
@@ -272,10 +284,6 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
     if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
     __syncthreads();
     const float* X = xs[b];
-    if (t < J.d) {
-#pragma unroll 8
-      for (int r = 0; r < kLdsRows; ++r) aabs += fabs((double)X[t * kLdsCs + r]);
-    }
     // per 16-row group and half of the wavefront's pairs: the operands
     // first, then the four k-steps with the pairs interleaved, so that
     // consecutive matrix-core instructions write different accumulators
@@ -335,9 +343,18 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
       }
     }
   }
-  if (t < J.d) {
-    if (J.chunks > 1) J.part_abs[(int64_t)seg * J.d + t] = aabs;
-    else J.colabs[t] = aabs;
+  // 1-norms: the 16 lanes of each slot's column (a fixed tree: every lane
+  // ends with the same sum)
+#pragma unroll
+  for (int u = 0; u < L::loads; ++u) {
+    double sa = sabs[u];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) sa += __shfl_xor(sa, off, 16);
+    const int col = (t + u * NW * 64) >> 4;
+    if ((t & 15) == 0 && col < J.d) {
+      if (J.chunks > 1) J.part_abs[(int64_t)seg * J.d + col] = sa;
+      else J.colabs[col] = sa;
+    }
   }
 }
 

@@ -170,15 +170,6 @@ __device__ __forceinline__ V uni_if(V v) {
   else return v;
 }
 
-// Global-memory view of a pointer read from a job table.  Generic pointers
-// would be accessed with flat instructions, and while a flat access is
-// pending the compiler can only wait for all outstanding loads, which
-// would also wait for the next tile's prefetch.
-template <class V>
-__device__ __forceinline__ __attribute__((address_space(1))) V* gmem(V* p) {
-  return (__attribute__((address_space(1))) V*)p;
-}
-
 // What the tile loop reads of the job whose tiles it loads ...
 struct TileSrc {
   const float* A;
