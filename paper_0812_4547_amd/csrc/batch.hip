@@ -279,6 +279,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     s.r_cap = rcap[i];
     s.mode = o.sample_mode;
     s.sign_log_t = log_t[i];
+    s.sign_rows = (int32_t)p.n;
     s.blk0 = blk0;
     blk0 += streams_blocks(m[i]);
     B.blk_map.insert(B.blk_map.end(), (size_t)streams_blocks(m[i]), i);

@@ -102,7 +102,8 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // streams_scratch_words(n') uint32.
 struct StreamJob {
   uint64_t seed;
-  int32_t m, r, r_cap, mode, sign_log_t, pad_;
+  int32_t m, r, r_cap, mode, sign_log_t;
+  int32_t sign_rows;  // signs drawn for rows below this (> 0; rows past it are zero), else all n'
   int64_t blk0;  // first block in a batched launch
   uint32_t* sign_words;
   uint32_t* sign_export;

@@ -105,11 +105,14 @@ __device__ __forceinline__ void sign_bits(const StreamJob& J, int64_t w, int par
   const uint64_t base = (uint64_t)w * 32ull;
   const uint64_t first =
       J.sign_log_t > 0 ? ((uint64_t)(w / nt) << J.sign_log_t) + 4ull * (uint64_t)(w % nt) : base;
+  // rows past the input are zero after the flip whatever their sign: a batch
+  // draws no sign for them (bit 0)
+  const int64_t lim = J.sign_rows > 0 ? (int64_t)J.sign_rows : n_pad;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int b = 8 * part + k;
     const uint64_t j = first + (uint64_t)((b >> 2) * kstride + (b & 3));
-    if ((int64_t)j < n_pad) *sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
+    if ((int64_t)j < lim) *sbits |= (uint32_t)(mix64(sign_key + j) >> 63) << b;
   }
   if (export_nat) {
 #pragma unroll
