@@ -36,6 +36,8 @@
 // (different m, d) reads its descriptors from a device table.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace rnnls {
@@ -274,48 +276,67 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
   for (int s = 0; s < PW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
 
   float4 nxt[L::loads];
-  int b = 0;
-  if (r0 < hi) {
-    fetch(r0, nxt);
-    stash(xs[0], nxt);
-  }
-  for (int64_t c0 = r0; c0 < hi; c0 += kLdsRows) {
-    const bool more = c0 + kLdsRows < hi;
-    if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
-    __syncthreads();
-    const float* X = xs[b];
-    // per 16-row group and half of the wavefront's pairs: the operands
-    // first, then the four k-steps with the pairs interleaved, so that
-    // consecutive matrix-core instructions write different accumulators
-#pragma unroll
-    for (int g = 0; g < kLdsRows / 16; ++g) {
-#pragma unroll
-      for (int h0 = 0; h0 < PW; h0 += L::half) {
-        float4 xa[L::half], xb[L::half];
-#pragma unroll
-        for (int s = 0; s < L::half; ++s) {
-          const int ps = h0 + s < PW ? h0 + s : PW - 1;
-          xa[s] = *reinterpret_cast<const float4*>(
-              X + (pbi[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
-          xb[s] = *reinterpret_cast<const float4*>(
-              X + (pbj[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
-        }
-#define RNNLS_KSTEP(C)                                                                  \
-  _Pragma("unroll") for (int s = 0; s < L::half; ++s) {                                 \
-    const int ps = h0 + s;                                                              \
-    if (ps < PW && wv + ps * NW < J.pairs)                                          \
-      acc[ps] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s].C, (double)xb[s].C, \
-                                                     acc[ps], 0, 0, 0);                 \
-  }
-        RNNLS_KSTEP(x)
-        RNNLS_KSTEP(y)
-        RNNLS_KSTEP(z)
-        RNNLS_KSTEP(w)
-#undef RNNLS_KSTEP
-      }
+  // The chunk loop for K active pairs (K is uniform per wavefront: pairs
+  // wv, wv + NW, ... below J.pairs), so that the products carry no per-pair
+  // guard: a guarded matrix-core instruction sat in a block of its own, with
+  // its operand conversions and LDS wait in front of it.
+  auto chunks = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int HALF = K > 1 ? (K + 1) / 2 : 1;  // pairs whose operands are loaded together
+    int b = 0;
+    if (r0 < hi) {
+      fetch(r0, nxt);
+      stash(xs[0], nxt);
     }
-    if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
-    b ^= 1;
+    for (int64_t c0 = r0; c0 < hi; c0 += kLdsRows) {
+      const bool more = c0 + kLdsRows < hi;
+      if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
+      __syncthreads();
+      const float* X = xs[b];
+      // per 16-row group and half of the wavefront's pairs: the operands
+      // first, then the four k-steps with the pairs interleaved, so that
+      // consecutive matrix-core instructions write different accumulators
+#pragma unroll
+      for (int g = 0; g < kLdsRows / 16; ++g) {
+#pragma unroll
+        for (int h0 = 0; h0 < K; h0 += HALF) {
+          constexpr int NS = HALF;
+          double xa[NS][4], xb[NS][4];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int ps = h0 + s < K ? h0 + s : K - 1;
+            const float4 fa = *reinterpret_cast<const float4*>(
+                X + (pbi[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+            const float4 fb = *reinterpret_cast<const float4*>(
+                X + (pbj[ps] * kBlk + (lane & 15)) * kLdsCs + 16 * g + 4 * kq);
+            xa[s][0] = fa.x; xa[s][1] = fa.y; xa[s][2] = fa.z; xa[s][3] = fa.w;
+            xb[s][0] = fb.x; xb[s][1] = fb.y; xb[s][2] = fb.z; xb[s][3] = fb.w;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+              if (h0 + s < K)
+                acc[h0 + s] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s][k], xb[s][k],
+                                                                  acc[h0 + s], 0, 0, 0);
+        }
+      }
+      if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
+      b ^= 1;
+    }
+  };
+  int npw = 0;  // active pairs of this wavefront
+#pragma unroll
+  for (int s = 0; s < PW; ++s) npw += (wv + s * NW < J.pairs) ? 1 : 0;
+  npw = __builtin_amdgcn_readfirstlane(npw);
+  static_assert(PW <= 5, "chunk loop instances");
+  switch (npw) {
+    case 0: chunks(std::integral_constant<int, 0>{}); break;
+    case 1: chunks(std::integral_constant<int, 1>{}); break;
+    case 2: chunks(std::integral_constant<int, PW >= 2 ? 2 : 1>{}); break;
+    case 3: chunks(std::integral_constant<int, PW >= 3 ? 3 : 1>{}); break;
+    case 4: chunks(std::integral_constant<int, PW >= 4 ? 4 : 1>{}); break;
+    default: chunks(std::integral_constant<int, PW >= 5 ? 5 : 1>{}); break;
   }
   // results: partial blocks of the segment, or the final G, Q, c and 1-norms
 #pragma unroll
