@@ -449,6 +449,61 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(MomentJob one, const M
   }
 }
 
+// A single problem with many segments: 16 entries per block, each summed by
+// 16 threads over interleaved chunk groups (chunk q, q + 16, ... in order),
+// then the 16 group sums in group order: a fixed order of additions, with 32
+// chunks per thread instead of all of them.
+constexpr int kRedEnt = 16, kRedGroups = 16;
+__global__ __launch_bounds__(kRedEnt* kRedGroups) void gram_reduce_wide_kernel(MomentJob J) {
+  __shared__ double part[kRedGroups][kRedEnt];
+  const int el = threadIdx.x % kRedEnt;
+  const int q = threadIdx.x / kRedEnt;
+  const int nblk = J.pairs * kBlk * kBlk;
+  const int e = blockIdx.x * kRedEnt + el;
+  const bool live = e < nblk + J.d;
+  const double* src = live ? (e < nblk ? J.part + e : J.part_abs + (e - nblk)) : nullptr;
+  const int64_t stride = e < nblk ? nblk : J.d;
+  double s = 0.0;
+  if (live) {
+    int c = q;
+    for (; c + 3 * kRedGroups < J.chunks; c += 4 * kRedGroups) {
+      const double a0 = src[(int64_t)c * stride];
+      const double a1 = src[(int64_t)(c + kRedGroups) * stride];
+      const double a2 = src[(int64_t)(c + 2 * kRedGroups) * stride];
+      const double a3 = src[(int64_t)(c + 3 * kRedGroups) * stride];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; c < J.chunks; c += kRedGroups) s += src[(int64_t)c * stride];
+  }
+  part[q][el] = s;
+  __syncthreads();
+  if (q != 0 || !live) return;
+  double t = 0.0;
+#pragma unroll
+  for (int g = 0; g < kRedGroups; ++g) t += part[g][el];
+  if (e >= nblk) {
+    J.colabs[e - nblk] = t;
+    return;
+  }
+  const int D1 = J.d + J.k;
+  int bi, bj;
+  pair_blocks(e / (kBlk * kBlk), J.nbA, J.nb, bi, bj);
+  const int i = bi * kBlk + (e / kBlk) % kBlk;
+  const int j = bj * kBlk + e % kBlk;
+  if (i > j || j >= D1) return;
+  if (j < J.d) {
+    J.G[(int64_t)i * J.d + j] = t;
+    J.G[(int64_t)j * J.d + i] = t;
+  } else if (i < J.d) {
+    J.Q[(int64_t)(j - J.d) * J.ldq + i] = t;
+  } else if (i == j) {
+    J.c[i - J.d] = t;
+  }
+}
+
 }  // namespace
 
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
@@ -522,8 +577,12 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
                        (const MomentJob*)nullptr, (const int32_t*)nullptr);
   if (p.chunks > 1) {
     const int64_t nent = (int64_t)p.pairs * kBlk * kBlk + p.d;
-    hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)), dim3(256),
-                       0, s, j, (const MomentJob*)nullptr, (const int32_t*)nullptr);
+    if (p.chunks >= 4 * kRedGroups)
+      hipLaunchKernelGGL(gram_reduce_wide_kernel, dim3((unsigned)((nent + kRedEnt - 1) / kRedEnt)),
+                         dim3(kRedEnt * kRedGroups), 0, s, j);
+    else
+      hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)((nent + 255) / 256)),
+                         dim3(256), 0, s, j, (const MomentJob*)nullptr, (const int32_t*)nullptr);
   }
   timer_end(RNNLS_TIMER_MOMENTS, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
