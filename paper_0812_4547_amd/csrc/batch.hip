@@ -78,8 +78,10 @@ struct Group {
   std::vector<int> members;  // problem indices
   std::vector<SketchJob> jobs;
   std::vector<int32_t> col_map;  // column of the group -> job in the group
+  std::vector<int32_t> red_cols;  // columns of the group transformed by several workgroups
   SketchJob* dev = nullptr;
   int32_t* col_map_dev = nullptr;
+  int32_t* red_cols_dev = nullptr;
 };
 
 }  // namespace
@@ -208,6 +210,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   // sketch items and pieces per group
   for (Group& G : B.groups) {
     int64_t item0 = 0, item0_rag = 0, col0 = 0;
+    G.red_cols.clear();
     for (int i : G.members) {
       const rnnls_problem& p = B.probs[i];
       const int ncols = p.d + 1;
@@ -226,6 +229,14 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
         j.item0_rag = item0_rag;
         item0 += (int64_t)ncols * j.tiles;
         j.pieces = srht_owner_pieces(j.item0, j.tiles, ncols, G.g.items, G.g.grid);
+        // only these columns have partials to add (the others are written
+        // whole by the transform)
+        for (int c = 0; c < ncols; ++c) {
+          const int64_t first = j.item0 + (int64_t)c * j.tiles;
+          if (srht_owner_of(first + j.tiles - 1, G.g.items, G.g.grid) !=
+              srht_owner_of(first, G.g.items, G.g.grid))
+            G.red_cols.push_back((int32_t)(j.col0 + c));
+        }
       }
       pieces[i] = j.pieces;
       G.jobs.push_back(j);
@@ -420,10 +431,12 @@ int plan(rnnls_batch& B, const Candidate& c) {
   bytes += map_bytes(B.chunk_map);
   const size_t o_em = bytes;
   bytes += map_bytes(B.ent_map);
-  std::vector<size_t> o_gm;
+  std::vector<size_t> o_gm, o_rc;
   for (Group& G : B.groups) {
     o_gm.push_back(bytes);
     bytes += map_bytes(G.col_map);
+    o_rc.push_back(bytes);
+    bytes += map_bytes(G.red_cols);
   }
   if (hipMalloc(&B.dev_tables, bytes) != hipSuccess) {
     B.dev_tables = nullptr;
@@ -442,8 +455,10 @@ int plan(rnnls_batch& B, const Candidate& c) {
   copy(o_bm, B.blk_map.data(), sizeof(int32_t) * B.blk_map.size());
   copy(o_cm, B.chunk_map.data(), sizeof(int32_t) * B.chunk_map.size());
   copy(o_em, B.ent_map.data(), sizeof(int32_t) * B.ent_map.size());
-  for (size_t g = 0; g < B.groups.size(); ++g)
+  for (size_t g = 0; g < B.groups.size(); ++g) {
     copy(o_gm[g], B.groups[g].col_map.data(), sizeof(int32_t) * B.groups[g].col_map.size());
+    copy(o_rc[g], B.groups[g].red_cols.data(), sizeof(int32_t) * B.groups[g].red_cols.size());
+  }
   if (hipMemcpy(B.dev_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
     return RNNLS_E_HIP;
   char* base = static_cast<char*>(B.dev_tables);
@@ -456,15 +471,18 @@ int plan(rnnls_batch& B, const Candidate& c) {
   B.blk_map_dev = reinterpret_cast<int32_t*>(base + o_bm);
   B.chunk_map_dev = reinterpret_cast<int32_t*>(base + o_cm);
   B.ent_map_dev = reinterpret_cast<int32_t*>(base + o_em);
-  for (size_t g = 0; g < B.groups.size(); ++g)
+  for (size_t g = 0; g < B.groups.size(); ++g) {
     B.groups[g].col_map_dev = reinterpret_cast<int32_t*>(base + o_gm[g]);
+    B.groups[g].red_cols_dev = reinterpret_cast<int32_t*>(base + o_rc[g]);
+  }
   B.tune = c;
   return RNNLS_OK;
 }
 
 int run_sketch(rnnls_batch& B, hipStream_t s) {
   for (Group& G : B.groups) {
-    const int rc = launch_srht_batch(G.g, G.dev, (int)G.jobs.size(), G.col_map_dev, s);
+    const int rc = launch_srht_batch(G.g, G.dev, (int)G.jobs.size(), G.col_map_dev,
+                                     G.red_cols_dev, (int)G.red_cols.size(), s);
     if (rc) return rc;
   }
   return RNNLS_OK;

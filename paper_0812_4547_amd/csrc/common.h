@@ -277,9 +277,13 @@ struct SrhtGroup {
   int max_r_cap;
   bool vec;   // every job 16-byte aligned (main launch without bounds checks)
 };
-// col_job_map: job of every column of the group (device)
+// col_job_map: job of every column of the group (device); red_cols: the nred
+// columns whose partials the reduce adds (device)
 int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
-                      const int32_t* col_job_map, hipStream_t s);
+                      const int32_t* col_job_map, const int32_t* red_cols, int nred,
+                      hipStream_t s);
+// workgroup of a persistent launch owning item x (items split into grid ranges)
+int64_t srht_owner_of(int64_t x, int64_t items, int64_t grid);
 int srht_owner_pieces(int64_t item0, int64_t tiles, int ncols, int64_t items, int64_t grid);
 
 struct MomentsPlan {

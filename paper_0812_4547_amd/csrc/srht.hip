@@ -584,8 +584,9 @@ __device__ __forceinline__ void reduce_col(const SketchJob& J, int col, int64_t 
 // (a batch of thousands of short columns runs on a bounded grid).
 template <bool BATCH>
 __global__ void srht_reduce_kernel(SketchJob one, const SketchJob* jobs, const int32_t* jmap,
-                                   int64_t items, int64_t grid, int cols) {
-  for (int cg = blockIdx.y; cg < cols; cg += gridDim.y) {
+                                   int64_t items, int64_t grid, int cols, const int32_t* list) {
+  for (int k = blockIdx.y; k < cols; k += gridDim.y) {
+    const int cg = list ? list[k] : k;  // a batch names the columns with partials
     int col;
     const SketchJob& J = col_job<BATCH>(one, jobs, jmap, cg, col);
     reduce_col(J, col, items, grid);
@@ -1091,13 +1092,16 @@ int launch_srht(const SrhtPlan& p, SketchJob j, hipStream_t s) {
   timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
   hipLaunchKernelGGL(srht_reduce_kernel<false>, rgrid, dim3(threads), 0, s, j,
                      (const SketchJob*)nullptr, (const int32_t*)nullptr, main_items,
-                     (int64_t)(p.grid > 0 ? p.grid : 1), p.ncols);
+                     (int64_t)(p.grid > 0 ? p.grid : 1), p.ncols, (const int32_t*)nullptr);
   timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
 
+int64_t srht_owner_of(int64_t x, int64_t items, int64_t grid) { return owner_of(x, items, grid); }
+
 int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
-                      const int32_t* col_job_map, hipStream_t s) {
+                      const int32_t* col_job_map, const int32_t* red_cols, int nred,
+                      hipStream_t s) {
   if (njobs < 1 || g.cols < 1) return RNNLS_OK;
   const int threads = 256;
   const dim3 rgrid(1u, (unsigned)g.cols);
@@ -1128,9 +1132,11 @@ int launch_srht_batch(const SrhtGroup& g, const SketchJob* dev, int njobs,
   timer_end(RNNLS_TIMER_SKETCH, s, tok);
   if (rc != RNNLS_OK) return rc;
   timer_begin(RNNLS_TIMER_REDUCE, s, &tok);
-  const dim3 bgrid(1u, (unsigned)(g.cols < kReduceRows ? g.cols : kReduceRows));
-  hipLaunchKernelGGL(srht_reduce_kernel<true>, bgrid, dim3(threads), 0, s, none, dev,
-                     col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1), (int)g.cols);
+  if (nred > 0) {
+    const dim3 bgrid(1u, (unsigned)(nred < kReduceRows ? nred : kReduceRows));
+    hipLaunchKernelGGL(srht_reduce_kernel<true>, bgrid, dim3(threads), 0, s, none, dev,
+                       col_job_map, g.items, (int64_t)(g.grid > 0 ? g.grid : 1), nred, red_cols);
+  }
   timer_end(RNNLS_TIMER_REDUCE, s, tok);
   return hipGetLastError() == hipSuccess ? RNNLS_OK : RNNLS_E_HIP;
 }
