@@ -357,6 +357,28 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     B.ljobs[h].push_back(lj);
     B.l_max_d[h] = std::max(B.l_max_d[h], p.d);
   }
+  // moments segments in decreasing order of work (block pairs x rows), so
+  // that the launch ends on the short ones
+  {
+    std::vector<int> order(np);
+    for (int i = 0; i < np; ++i) order[i] = i;
+    auto work = [&](int i) {
+      return (int64_t)B.mjobs[i].pairs * (B.mjobs[i].m / std::max(1, B.mjobs[i].chunks));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    int64_t c0 = 0;
+    B.chunk_map.clear();
+    for (int i : order) {
+      B.mjobs[i].chunk0 = c0;
+      c0 += B.mjobs[i].chunks;
+      B.chunk_map.insert(B.chunk_map.end(), (size_t)B.mjobs[i].chunks, i);
+    }
+  }
+  // widest problems first: a solve's time grows with d, and workgroups start
+  // in launch order, so the short solves fill the launch's tail
+  for (int h = 0; h < 2; ++h)
+    std::stable_sort(B.ljobs[h].begin(), B.ljobs[h].end(),
+                     [](const LhJob& a, const LhJob& b) { return a.d > b.d; });
   B.m_chunks = chunk0;
   B.m_max_pairs = max_pairs;
   for (Group& G : B.groups) {
