@@ -207,6 +207,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
       o_sa(np), o_sb(np), o_mom(np), o_G(np), o_q(np), o_c(np), o_abs(np);
   std::vector<int> pieces(np, 0);
   std::vector<MomentsPlan> mp(np);
+  const int seg_cap = std::max(1, std::min(kMomentSegments, (8 * B.cus + np - 1) / np));
   // sketch items and pieces per group
   for (Group& G : B.groups) {
     int64_t item0 = 0, item0_rag = 0, col0 = 0;
@@ -245,9 +246,11 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
   for (int i = 0; i < np; ++i) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
-    // row segments of at least 256 rows, at most 8 per problem (many
-    // problems fill the device together)
-    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, kMomentSegments);
+    // row segments of at least 256 rows, at most 8 per problem, and no more
+    // than about four workgroups per slot of the device (two per CU) over the
+    // plan: a plan of thousands of problems fills the device with one segment
+    // each and then writes no partial blocks (nor runs their reduce)
+    mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, seg_cap);
     o_rows[i] = put(off, sizeof(int32_t) * rcap[i]);
     o_cnt[i] = put(off, sizeof(int32_t));
     o_st[i] = put(off, sizeof(int32_t));
