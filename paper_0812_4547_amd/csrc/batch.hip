@@ -207,7 +207,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
       o_sa(np), o_sb(np), o_mom(np), o_G(np), o_q(np), o_c(np), o_abs(np);
   std::vector<int> pieces(np, 0);
   std::vector<MomentsPlan> mp(np);
-  const int seg_cap = std::max(1, std::min(kMomentSegments, (8 * B.cus + np - 1) / np));
+  const int seg_cap = std::max(1, std::min(kMomentSegments, (4 * B.cus + np - 1) / np));
   // sketch items and pieces per group
   for (Group& G : B.groups) {
     int64_t item0 = 0, item0_rag = 0, col0 = 0;
