@@ -247,7 +247,7 @@ size_t build(rnnls_batch& B, const Candidate& c, void* ws) {
     const rnnls_problem& p = B.probs[i];
     const int64_t n_pad = 1ll << m[i];
     // row segments of at least 256 rows, at most 8 per problem, and no more
-    // than about four workgroups per slot of the device (two per CU) over the
+    // than about two workgroups per slot of the device (two per CU) over the
     // plan: a plan of thousands of problems fills the device with one segment
     // each and then writes no partial blocks (nor runs their reduce)
     mp[i] = moments_plan(rcap[i], p.d, 1, B.cus, seg_cap);
