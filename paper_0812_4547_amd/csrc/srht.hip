@@ -16,8 +16,10 @@
 //   pass 1 (straight from the global loads): bits {0,1} and {tau-3..tau-1}
 //   pass 2 (LDS, in place):                  bits 2..6
 //   pass 3 (LDS, in place):                  bits 7..tau-4
-// LDS is padded by 4 words every 128 words so that the pass-2 gathers (stride
-// 4 words across 32 elements, 128 words across lanes) hit distinct banks.
+// Each wavefront's pass-2 tasks are rows it wrote in pass 1, so only passes
+// 2 -> 3, 3 -> combine and combine -> next tile need a workgroup barrier.
+// LDS is padded (4 words every 128 rows, 8 per value of the tile's top three
+// row bits) so that the pass-2 gathers of a wavefront hit distinct banks.
 //
 // Tiles entirely past row n hold zeros and are skipped.  Tiles fully inside A
 // go through the main launch (unguarded 16-byte loads); the one tile per
@@ -43,6 +45,15 @@ constexpr int kRegs = 32;  // elements per thread
 constexpr int kReduceRows = 2048;  // block rows of a batch reduce launch
 
 __device__ __forceinline__ int lds_pad(int j) { return j + ((j >> 7) << 2); }
+
+// LDS word of tile row j: 4 words of padding every 128 rows (the pass-2
+// gathers, 4 words apart within a 128-row block, then hit distinct banks) and
+// 8 more per value of the top three row bits k (a wavefront's pass-2 tasks
+// differ in k, and would otherwise map to the same banks).
+template <int LOG_T>
+__device__ __forceinline__ int lds_row(int j) {
+  return j + ((j >> 7) << 2) + ((j >> (LOG_T - 3)) << 3);
+}
 
 template <int MASK>
 __device__ __forceinline__ void fwht_regs(float (&v)[kRegs]) {
@@ -360,7 +371,7 @@ __device__ __forceinline__ int load_rows(const SketchJob& J, uint32_t (&zidx)[SP
   for (int s = 0; s < SPT; ++s) {
     const int l = threadIdx.x + s * NT;
     const uint32_t i = (l < count) ? (uint32_t)gmem(J.rows)[l] : 0u;
-    zidx[s] = (uint32_t)lds_pad((int)(i & ((1u << LOG_T) - 1u)));
+    zidx[s] = (uint32_t)lds_row<LOG_T>((int)(i & ((1u << LOG_T) - 1u)));
     ihi[s] = i >> LOG_T;
   }
   return count;
@@ -378,7 +389,7 @@ __attribute__((amdgpu_waves_per_eu(tiled_min_waves<LOG_T, SPT, MODE>())))
 void srht_tiled_kernel(TiledLaunch L) {
   constexpr int T = 1 << LOG_T;
   constexpr int NT = T / kRegs;
-  constexpr int LDS_WORDS = T + (T >> 5);
+  constexpr int LDS_WORDS = T + (T >> 5) + 64;
   __shared__ __attribute__((aligned(16))) float lds[LDS_WORDS];
 
   const int tid = threadIdx.x;
@@ -422,11 +433,24 @@ void srht_tiled_kernel(TiledLaunch L) {
   int64_t item = item_begin;
   load_tile<LOG_T, MODE, AUX>(S, col, tile, true, va, swa);
 
-  // pass-1 stores: padded word k*T/8 + 4 tid = lds_pad(4 tid) + k*(T/8 + T/256)
+  // pass-1 stores: word of row k*T/8 + 4 tid = lds_row(4 tid) + k*(T/8 + T/256 + 8)
   // (T/8 is a multiple of 128), one base and constant offsets
-  float* const p1 = lds + lds_pad(4 * tid);
-  const int p2_base = (tid & 3) + ((tid >> 2) << 7) + ((tid >> 2) << 2);
-  const int p3_base = (tid & 127) + (tid >> 7) * (4096 + 128);
+  float* const p1 = lds + lds_row<LOG_T>(4 * tid);
+  // pass 2: the task of a thread is the 32 rows c + 128 m + 4 e (e < 32).
+  // Pass 1 leaves the rows whose bits 8 .. tau-4 equal a wavefront's index
+  // (the top bits of 4 tid) in that wavefront, so each wavefront takes the
+  // tasks whose rows it wrote: m = m0 + 2 w + 2^(1 + WB) kh (kh the top three
+  // row bits), and no workgroup barrier separates the two passes.
+  constexpr int WB = LOG_T - 11;  // log2 of the wavefronts per workgroup
+  const int p2_base = [&] {
+    const int lane = tid & 63, c = lane & 3, m0 = (lane >> 2) & 1, kh = lane >> 3;
+    const int m = m0 | ((tid >> 6) << 1) | (kh << (1 + WB));
+    return lds_row<LOG_T>(c + (m << 7));
+  }();
+  // pass 3: rows (tid & 127) + 128 e + 4096 (tid >> 7); the base has no row
+  // bits 7..11, so adding 128 e reaches the k bits only through e
+  const int p3_base = lds_row<LOG_T>((tid & 127) + ((tid >> 7) << 12));
+  auto p3_off = [](int e) constexpr { return 132 * e + 8 * ((e << 7) >> (LOG_T - 3)); };
 
   auto step = [&](float (&v)[kRegs], uint32_t sw, float (&vn)[kRegs],
                   uint32_t& swn) __attribute__((always_inline)) {
@@ -446,9 +470,13 @@ void srht_tiled_kernel(TiledLaunch L) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       float4 q = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-      *reinterpret_cast<float4*>(p1 + k * (T / 8 + T / 256)) = q;
+      *reinterpret_cast<float4*>(p1 + k * (T / 8 + T / 256 + 8)) = q;
     }
-    __syncthreads();
+    // pass 2 reads only rows this wavefront wrote: LDS operations of a
+    // wavefront complete in order, so ordering the compiler is enough
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {  // pass 2: bits 2..6
       float u[kRegs];
 #pragma unroll
@@ -461,10 +489,10 @@ void srht_tiled_kernel(TiledLaunch L) {
     {  // pass 3: bits 7..tau-4 (register bits 0..tau-11), others carried
       float u[kRegs];
 #pragma unroll
-      for (int e = 0; e < kRegs; ++e) u[e] = lds[p3_base + 132 * e];
+      for (int e = 0; e < kRegs; ++e) u[e] = lds[p3_base + p3_off(e)];
       fwht_regs<(1 << (LOG_T - 10)) - 1>(u);
 #pragma unroll
-      for (int e = 0; e < kRegs; ++e) lds[p3_base + 132 * e] = u[e];
+      for (int e = 0; e < kRegs; ++e) lds[p3_base + p3_off(e)] = u[e];
     }
     __syncthreads();
     // pruned combine: y[i] += (-1)^popcount(i_hi & t) * z_t[i_lo]; a batch
