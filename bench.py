@@ -79,9 +79,11 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(path=TRAFFIC_FILE):
+def load_traffic(path=TRAFFIC_FILE, log_tile=None):
     """HBM bytes per launch of the sketch kernel from the committed rocprofv3
-    counter summary, or None when absent or taken on different kernel source."""
+    counter summary, or None when absent or taken on different kernel source.
+    With log_tile, the figure of the tile-size variant of that size (a batch
+    summary holds one per variant the autotuner timed)."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -89,6 +91,8 @@ def load_traffic(path=TRAFFIC_FILE):
         return None
     if t.get("kernel_source_sha256_16") != kernel_hash():
         return None
+    if log_tile is not None:
+        return (t.get("variants") or {}).get(str(log_tile), {}).get("hbm_bytes_per_launch")
     return t.get("hbm_bytes_per_launch")
 
 
@@ -888,9 +892,9 @@ def bench_warm_batch(args):
         "kernel": "srht_tiled_kernel (every sketch launch of the pass)", "bound": "hbm",
         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        # counters were taken on the 2^14-row variant with one plan of 4096
-        "traffic": (load_traffic(TRAFFIC_FILE_BATCH)
-                    if (per == count == 4096 and sorted(set(tiles)) == [(14, 2)]) else None),
+        # counters were taken per tile-size variant on one plan of 4096
+        "traffic": (load_traffic(TRAFFIC_FILE_BATCH, log_tile=tiles[0][0])
+                    if (per == count == 4096 and len(set(tiles)) == 1) else None),
         "algorithmic_bytes_per_pass": alg, "sketch_ms_per_pass": sk_ms,
         "whole_sketch": _whole(alg, kw["streams"] + sk_ms + kw["reduce"])})
     rec["training"] = {"problems": args.train_instances, "rows": train_rows,

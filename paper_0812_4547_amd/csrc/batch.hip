@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -682,29 +683,49 @@ int rnnls_batch_autotune(rnnls_batch* B, void* stream, rnnls_tuning* chosen) {
     return RNNLS_E_HIP;
   }
   int rc = RNNLS_OK;
-  float best = 1e30f;
-  Candidate best_c{0, 0};
-  for (const Candidate& c : kCandidates) {
-    rc = plan(*B, c);
-    if (rc == RNNLS_E_WORKSPACE) continue;
-    if (rc) break;
+  // the sketch of candidate c timed over `reps` launches (after one more),
+  // in ms per launch; < 0 when the workspace cannot hold its layout
+  auto time_candidate = [&](const Candidate& c, int reps, float* ms) -> int {
+    *ms = -1.0f;
+    int r = plan(*B, c);
+    if (r == RNNLS_E_WORKSPACE) return RNNLS_OK;
+    if (r) return r;
     // streams once (the sketch reads their output), then the sketch timed
-    if ((rc = launch_streams_batch(B->sjobs.data(), B->sdev, B->count, B->blk_map_dev, s)))
-      break;
-    if ((rc = run_sketch(*B, s))) break;
-    if (hipEventRecord(e0, s) != hipSuccess) { rc = RNNLS_E_HIP; break; }
-    const int reps = 3;
-    for (int k = 0; k < reps && !rc; ++k) rc = run_sketch(*B, s);
-    if (rc) break;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-      rc = RNNLS_E_HIP;
-      break;
-    }
+    if ((r = launch_streams_batch(B->sjobs.data(), B->sdev, B->count, B->blk_map_dev, s)))
+      return r;
+    if ((r = run_sketch(*B, s))) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return RNNLS_E_HIP;
+    for (int k = 0; k < reps && !r; ++k) r = run_sketch(*B, s);
+    if (r) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return RNNLS_E_HIP;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return RNNLS_E_HIP;
+    *ms = t / (float)reps;
+    return RNNLS_OK;
+  };
+  // every candidate once, then the two fastest again in alternation (two
+  // rounds): candidates within a few percent are told apart by the sum
+  std::vector<std::pair<float, int>> timed;
+  const int ncand = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+  for (int ci = 0; ci < ncand && !rc; ++ci) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = RNNLS_E_HIP; break; }
-    if (ms < best) {
-      best = ms;
-      best_c = c;
+    rc = time_candidate(kCandidates[ci], 3, &ms);
+    if (!rc && ms >= 0.0f) timed.push_back({ms, ci});
+  }
+  std::sort(timed.begin(), timed.end());
+  Candidate best_c{0, 0};
+  if (!rc && !timed.empty()) {
+    best_c = kCandidates[timed[0].second];
+    if (timed.size() > 1) {
+      float sum[2] = {timed[0].first, timed[1].first};
+      for (int round = 0; round < 2 && !rc; ++round)
+        for (int t = 0; t < 2 && !rc; ++t) {
+          float ms = 0.0f;
+          rc = time_candidate(kCandidates[timed[t].second], 3, &ms);
+          sum[t] += ms;
+        }
+      if (!rc && sum[1] < sum[0]) best_c = kCandidates[timed[1].second];
     }
   }
   (void)hipEventDestroy(e0);
