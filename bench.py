@@ -813,9 +813,26 @@ def bench_warm_batch(args):
     print(f"{len(plans)} plans of {per} held-out problems resident "
           f"({alg / 1e9:.1f} GB of [A | b]), autotuned", file=sys.stderr, flush=True)
 
+    # several plans: their graph replays are spread over a few streams (all of
+    # default priority), forked from and joined back into the timed stream,
+    # so one plan's latency-bound solves overlap the next plans' sketches
+    side = [torch.cuda.Stream() for _ in range(min(4, len(plans)))] if len(plans) > 1 else []
+
     def one_pass():
-        for P in plans:
-            P.launch()
+        if not side:
+            for P in plans:
+                P.launch()
+            return
+        fork = torch.cuda.Event()
+        fork.record(stream)
+        for st in side:
+            st.wait_event(fork)
+        for i, P in enumerate(plans):
+            P.launch(side[i % len(side)])
+        for st in side:
+            done = torch.cuda.Event()
+            done.record(st)
+            stream.wait_event(done)
 
     def phase(model):
         for P in plans:
@@ -866,7 +883,8 @@ def bench_warm_batch(args):
         "workload": f"batched warm-started RandomizedNNLS: {count} held-out problems of the "
                     "batch generator (n log-uniform in [2^14, 2^18], d uniform in [8, 96], "
                     "r = max(32 d, 1024); tf-idf-like entries generated on the device) in "
-                    f"{len(plans)} batch plans of {per}, HIP graph replay, autotuned tiles; "
+                    f"{len(plans)} batch plans of {per}, HIP graph replay"
+                    f"{f' on {len(side)} streams' if side else ''}, autotuned tiles; "
                     "Lawson-Hanson warm-started from the learned passive-set proposal, "
                     "KKT-judged with cold fallback",
         "problems": count, "plan_size": per, "heldout_seed": hseed,
