@@ -290,7 +290,8 @@ struct MomentsPlan {
   int64_t m;
   int d, k;
   int chunks, nbA, nb, pairs;
-  int lds;  // all block pairs from each row chunk in LDS: 1 (d + k <= 112), 2 (<= 129)
+  int lds;  // all block pairs from each row chunk in LDS: 1 (d + k <= 112), 2 (<= 129),
+            // 3 (a single problem, d + k <= 80: loads two chunks ahead)
 };
 // max_chunks > 0 caps the row chunks (batches spread over problems instead)
 MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks = 0);

@@ -215,7 +215,9 @@ struct LdsShape {
 };
 
 // Segment `seg` of the job: rows [m seg / S, m (seg+1) / S) (S = J.chunks).
-template <bool BATCH, int COLS, int NW>
+// DEPTH: chunks whose loads are in flight while one is multiplied (2 keeps
+// a second register buffer: each chunk's loads get two chunks of products)
+template <bool BATCH, int COLS, int NW, int DEPTH = 1>
 __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const MomentJob* jobs,
                                               const int32_t* jmap) {
   using L = LdsShape<COLS, NW>;
@@ -280,22 +282,14 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
   // wv, wv + NW, ... below J.pairs), so that the products carry no per-pair
   // guard: a guarded matrix-core instruction sat in a block of its own, with
   // its operand conversions and LDS wait in front of it.
+  float4 nx2[DEPTH == 2 ? L::loads : 1];  // the second buffer of DEPTH 2
   auto chunks = [&](auto kc) __attribute__((always_inline)) {
     constexpr int K = decltype(kc)::value;
     constexpr int HALF = K > 1 ? (K + 1) / 2 : 1;  // pairs whose operands are loaded together
-    int b = 0;
-    if (r0 < hi) {
-      fetch(r0, nxt);
-      stash(xs[0], nxt);
-    }
-    for (int64_t c0 = r0; c0 < hi; c0 += kLdsRows) {
-      const bool more = c0 + kLdsRows < hi;
-      if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
-      __syncthreads();
-      const float* X = xs[b];
-      // per 16-row group and half of the wavefront's pairs: the operands
-      // first, then the four k-steps with the pairs interleaved, so that
-      // consecutive matrix-core instructions write different accumulators
+    // per 16-row group and half of the wavefront's pairs: the operands
+    // first, then the four k-steps with the pairs interleaved, so that
+    // consecutive matrix-core instructions write different accumulators
+    auto products = [&](const float* X) __attribute__((always_inline)) {
 #pragma unroll
       for (int g = 0; g < kLdsRows / 16; ++g) {
 #pragma unroll
@@ -321,8 +315,40 @@ __device__ __forceinline__ void gram_lds_body(const MomentJob& one, const Moment
                                                                   acc[h0 + s], 0, 0, 0);
         }
       }
-      if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
-      b ^= 1;
+    };
+    int b = 0;
+    if (r0 < hi) {
+      fetch(r0, nxt);
+      stash(xs[0], nxt);
+    }
+    if constexpr (DEPTH == 1) {
+      for (int64_t c0 = r0; c0 < hi; c0 += kLdsRows) {
+        const bool more = c0 + kLdsRows < hi;
+        if (more) fetch(c0 + kLdsRows, nxt);  // in flight during this chunk's products
+        __syncthreads();
+        products(xs[b]);
+        if (more) stash(xs[b ^ 1], nxt);  // the other buffer: last read before the barrier above
+        b ^= 1;
+      }
+    } else {
+      if (r0 + kLdsRows < hi) fetch(r0 + kLdsRows, nxt);
+      // chunk c0: the next chunk's values are in A (requested a chunk ago),
+      // the one after goes into F; the two buffers alternate
+      auto iter = [&](int64_t c0, float4 (&A)[L::loads], float4 (&F)[L::loads])
+                      __attribute__((always_inline)) {
+        if (c0 + 2 * kLdsRows < hi) fetch(c0 + 2 * kLdsRows, F);
+        __syncthreads();
+        products(xs[b]);
+        if (c0 + kLdsRows < hi) stash(xs[b ^ 1], A);
+        b ^= 1;
+      };
+      for (int64_t c0 = r0; c0 < hi;) {
+        iter(c0, nxt, nx2);
+        c0 += kLdsRows;
+        if (c0 >= hi) break;
+        iter(c0, nx2, nxt);
+        c0 += kLdsRows;
+      }
     }
   };
   int npw = 0;  // active pairs of this wavefront
@@ -387,6 +413,17 @@ template <bool BATCH>
 __global__ __launch_bounds__(kLdsNWN * 64) __attribute__((amdgpu_waves_per_eu(4))) void
 gram_lds_kernel(MomentJob one, const MomentJob* jobs, const int32_t* jmap) {
   gram_lds_body<BATCH, kLdsColsN, kLdsNWN>(one, jobs, jmap);
+}
+// up to 80 columns: eight wavefronts, two workgroups per CU, each chunk's
+// loads requested two chunks ahead (a single problem's segments are long and
+// would wait on their loads; five blocks give each wavefront at most two
+// pairs, which leaves the registers for the second buffer)
+constexpr int kLdsColsS = 80;
+constexpr int kLdsNWS = 8;
+template <bool BATCH>
+__global__ __launch_bounds__(kLdsNWS * 64) __attribute__((amdgpu_waves_per_eu(4))) void
+gram_lds_small_kernel(MomentJob one, const MomentJob* jobs, const int32_t* jmap) {
+  gram_lds_body<BATCH, kLdsColsS, kLdsNWS, 2>(one, jobs, jmap);
 }
 // up to 129 columns: sixteen wavefronts, one workgroup per CU
 constexpr int kLdsNWW = 16;
@@ -520,6 +557,7 @@ MomentsPlan moments_plan(int64_t m, int d, int k, int cus, int max_chunks) {
   // workgroup per block pair and chunk of rows, more workgroups in flight
   const bool one_pass = max_chunks > 0 || m >= kLdsMinRows;
   p.lds = !one_pass ? 0 : (d + k <= kLdsColsN ? 1 : (d + k <= kLdsCols ? 2 : 0));
+  if (p.lds == 1 && max_chunks <= 0 && d + k <= kLdsColsS) p.lds = 3;  // single, narrow
   if (p.lds) {
     // segments of at least 256 rows, at most two workgroups per CU (batches
     // cap them per problem: many problems fill the device together)
@@ -563,7 +601,10 @@ int launch_moments(const MomentsPlan& p, MomentJob j, hipStream_t s) {
   void* tok = nullptr;
   timer_begin(RNNLS_TIMER_MOMENTS, s, &tok);
   const dim3 grid(p.chunks, p.pairs);
-  if (p.lds == 1)
+  if (p.lds == 3)
+    hipLaunchKernelGGL(gram_lds_small_kernel<false>, dim3(p.chunks), dim3(kLdsNWS * 64), 0, s, j,
+                       (const MomentJob*)nullptr, (const int32_t*)nullptr);
+  else if (p.lds == 1)
     hipLaunchKernelGGL(gram_lds_kernel<false>, dim3(p.chunks), dim3(kLdsNWN * 64), 0, s, j,
                        (const MomentJob*)nullptr, (const int32_t*)nullptr);
   else if (p.lds == 2)
